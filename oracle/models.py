@@ -1,0 +1,180 @@
+"""Modified-gravity model functions (Secs. 4-6, App. B-C).
+
+Each model supplies, as functions of wavenumber k [h/Mpc] and scale factor a:
+
+* mu(k, a): linear modification of the Poisson equation (Sec. 4, eq. eulerian);
+* gamma2_orth(k, a): the Lagrangian second-order kernel gamma_2 evaluated at the
+  orthogonal triangle k1 = k2 = k/sqrt(2), k1.k2 = 0, the argument the approximate
+  second-order growth equation uses (Sec. 4.2, eq. fofrapprox).  At k1 . k2 = 0
+  the extra Lagrangian term (3/2) Omega_m(a) [mu(k)-mu(k1)] k1.k2/k2^2 vanishes, so
+  gamma_2 = gamma_2^E there;
+* a2m2(a): a^2 m^2(a) of the linear field equation (Sec. 6; App. B), in (h/Mpc)^2;
+* coupling(a): C(a) of the general field equation (App. B):
+  nabla^2 phi = a^2 m^2 phi + C kappa delta eps_screen;
+* the screening factor eps_screen (Sec. 6).
+"""
+
+import numpy as np
+
+from .background import E, omega_m_of_a
+from .params import (MODEL_LCDM, MODEL_FR, MODEL_NDGP, FILTER_GAUSS, FILTER_TOPHAT,
+                     FILTER_SHARPK, H0_OVER_C)
+
+
+# ----------------------------------------------------------------------------- f(R)
+def fr_X(a, om):
+    return om * np.asarray(a, dtype=np.float64) ** -3 + 4.0 * (1.0 - om)
+
+
+def fr_Y(om):
+    return om + 4.0 * (1.0 - om)
+
+
+def fr_a2m2(a, om, fr0):
+    """a^2 m^2(a) for Hu-Sawicki n = 1 (Sec. 5.1, eq. mofahus):
+    m^2 = H0^2 (Om + 4 OL) / (2|fR0|) * ((Om a^-3 + 4 OL)/(Om + 4 OL))^3,
+    with H0 -> H0/c so that m is in h/Mpc."""
+    X, Y = fr_X(a, om), fr_Y(om)
+    return a * a * H0_OVER_C ** 2 * Y * (X / Y) ** 3 / (2.0 * fr0)
+
+
+def fr_fR_abs(a, om, fr0):
+    """|f_R(a)| = |fR0| ((Om + 4 OL)/(Om a^-3 + 4 OL))^2 (Sec. 5.1)."""
+    return fr0 * (fr_Y(om) / fr_X(a, om)) ** 2
+
+
+def fr_mu(k, a, om, fr0):
+    """mu = 1 + (1/3) k^2 / (k^2 + a^2 m^2) (Sec. 5.1)."""
+    k2 = np.asarray(k, dtype=np.float64) ** 2
+    return 1.0 + k2 / (3.0 * (k2 + fr_a2m2(a, om, fr0)))
+
+
+def fr_Pi(k, a, om, fr0):
+    """Pi(k,a) = (k/(a H0))^2 + (Om a^-3 + 4 OL)^3 / (2|fR0| (Om + 4 OL)^2) (Sec. 5.1)."""
+    X, Y = fr_X(a, om), fr_Y(om)
+    return (np.asarray(k, dtype=np.float64) / (a * H0_OVER_C)) ** 2 \
+        + X ** 3 / (2.0 * fr0 * Y ** 2)
+
+
+def fr_gamma2E(k, k1, k2, a, om, fr0):
+    """gamma_2^E of Hu-Sawicki f(R) (Sec. 5.1):
+    -(9 Om^2/(48 a^6 |fR0|^2)) (k/(aH))^2 X^5/Y^4 / (Pi(k) Pi(k1) Pi(k2))."""
+    X, Y = fr_X(a, om), fr_Y(om)
+    kah = np.asarray(k, dtype=np.float64) / (a * H0_OVER_C * E(a, om))
+    return (-9.0 * om * om / (48.0 * a ** 6 * fr0 * fr0) * kah * kah * X ** 5 / Y ** 4
+            / (fr_Pi(k, a, om, fr0) * fr_Pi(k1, a, om, fr0) * fr_Pi(k2, a, om, fr0)))
+
+
+# ----------------------------------------------------------------------------- nDGP
+def dgp_beta(a, om, rc):
+    """beta_DGP = 1 + 2 r_c H (1 + Hdot/(3 H^2)) (Sec. 5.2).  With Hdot the
+    cosmic-time derivative, Hdot/H^2 = dlnH/dlna = -(3/2) Omega_m(a) in flat LCDM,
+    so beta = 1 + 2 (r_c H0) E(a) (1 - Omega_m(a)/2)."""
+    return 1.0 + 2.0 * rc * E(a, om) * (1.0 - 0.5 * omega_m_of_a(a, om))
+
+
+def dgp_mu(a, om, rc):
+    return 1.0 + 1.0 / (3.0 * dgp_beta(a, om, rc))
+
+
+def dgp_gamma2E_orth(a, om, rc):
+    """gamma_2^E = -(H0/H)^2 (r_c H0)^2 Om^2 / (6 beta^3 a^6) (1 - cos^2 theta) (Sec. 5.2),
+    at cos theta = 0."""
+    b = dgp_beta(a, om, rc)
+    return -(rc * rc * om * om) / (6.0 * E(a, om) ** 2 * b ** 3 * a ** 6)
+
+
+# ----------------------------------------------------------------------------- dispatch
+class Model:
+    """Model functions of a run (bound to its cosmology and model parameters)."""
+
+    def __init__(self, p, force_lcdm_growth=False):
+        self.p = p
+        self.om = p.omega_m
+        self.kind = p.model
+        self.lcdm_growth = force_lcdm_growth or (p.growth_mode == 1)
+
+    # --- linear growth inputs (App. B: the user supplies mu and gamma_2)
+    def mu(self, k, a):
+        k = np.asarray(k, dtype=np.float64)
+        if self.lcdm_growth or self.kind == MODEL_LCDM:
+            return np.ones_like(k)
+        if self.kind == MODEL_FR:
+            return fr_mu(k, a, self.om, self.p.fr0_abs)
+        if self.kind == MODEL_NDGP:
+            return np.full_like(k, dgp_mu(a, self.om, self.p.rc_h0))
+        raise ValueError(self.kind)
+
+    def gamma2_orth(self, k, a):
+        k = np.asarray(k, dtype=np.float64)
+        if self.lcdm_growth or self.kind == MODEL_LCDM:
+            return np.zeros_like(k)
+        if self.kind == MODEL_FR:
+            kk = k / np.sqrt(2.0)
+            return fr_gamma2E(k, kk, kk, a, self.om, self.p.fr0_abs)
+        if self.kind == MODEL_NDGP:
+            return np.full_like(k, dgp_gamma2E_orth(a, self.om, self.p.rc_h0))
+        raise ValueError(self.kind)
+
+    # --- N-body field equation (Sec. 6, App. B)
+    @property
+    def has_fifth_force(self):
+        return self.kind in (MODEL_FR, MODEL_NDGP)
+
+    def a2m2(self, a):
+        if self.kind == MODEL_FR:
+            return float(fr_a2m2(a, self.om, self.p.fr0_abs))
+        return 0.0
+
+    def coupling(self, a):
+        """C(a): 1/3 for f(R) (Sec. 6.1), 1/(3 beta_DGP) for nDGP (Sec. 6.2)."""
+        if self.kind == MODEL_FR:
+            return 1.0 / 3.0
+        if self.kind == MODEL_NDGP:
+            return float(1.0 / (3.0 * dgp_beta(a, self.om, self.p.rc_h0)))
+        return 0.0
+
+
+# ----------------------------------------------------------------------------- screening
+def eps_chameleon(phi_n, fR_abs):
+    """eps = min(1, |3 f_R(a) / (2 Phi_N)|) (Sec. 6.1); eps = 1 where Phi_N = 0.
+    phi_n is the dimensionless conventional Newtonian potential Phi/c^2."""
+    phi_n = np.asarray(phi_n, dtype=np.float64)
+    out = np.ones_like(phi_n)
+    nz = phi_n != 0.0
+    out[nz] = np.minimum(1.0, np.abs(1.5 * fR_abs / phi_n[nz]))
+    return out
+
+
+def vainshtein_x(rho_over_mean, a, om, rc, beta):
+    """x = 8 (r_c H0)^2 Omega_m (rho/rho_bar) / (9 beta^2 a^3) (Sec. 6.2, with the
+    physical mean density rho_bar_0 a^-3 of the Vainshtein radius), rho/rho_bar
+    clamped at 0."""
+    y = np.maximum(0.0, np.asarray(rho_over_mean, dtype=np.float64))
+    return 8.0 * rc * rc * om * y / (9.0 * beta * beta * a ** 3)
+
+
+def eps_vainshtein(x):
+    """eps = 2 (sqrt(1+x) - 1)/x = 2/(1 + sqrt(1+x)) (Sec. 6.2, read so that eps -> 1
+    as x -> 0 and eps -> 2/sqrt(x) deep inside the Vainshtein radius)."""
+    return 2.0 / (1.0 + np.sqrt(1.0 + np.asarray(x, dtype=np.float64)))
+
+
+def window(kR, kind):
+    """Fourier-space smoothing windows offered for the density screening (App. B):
+    Gaussian exp(-(kR)^2/2), spherical top-hat 3 (sin x - x cos x)/x^3, sharp-k
+    Theta(1 - kR)."""
+    x = np.asarray(kR, dtype=np.float64)
+    if kind == FILTER_GAUSS:
+        return np.exp(-0.5 * x * x)
+    if kind == FILTER_TOPHAT:
+        out = np.ones_like(x)
+        nz = x > 1e-4
+        xs = x[nz]
+        out[nz] = 3.0 * (np.sin(xs) - xs * np.cos(xs)) / xs ** 3
+        small = ~nz
+        out[small] = 1.0 - x[small] ** 2 / 10.0
+        return out
+    if kind == FILTER_SHARPK:
+        return (x <= 1.0).astype(np.float64)
+    raise ValueError(kind)

@@ -1,0 +1,81 @@
+"""Run parameters and unit conventions of the oracle.
+
+Units (a reading of Sec. 2, where kappa = 4 pi G rho_bar a^4 = (3/2) Omega_m H0^2 a and
+d tau = dt / a^2):
+
+* lengths in Mpc/h, wavenumbers in h/Mpc;
+* time in units of 1/H0, so H(a) = E(a) and kappa(a) = 1.5 Omega_m a;
+* wherever H0 multiplies a length (m(a), Pi(k,a), k/(aH), the Newtonian
+  potential compared with f_R), H0 is converted with H0/c = 1/2997.92458 h/Mpc.
+"""
+
+from dataclasses import dataclass, replace
+
+MODEL_LCDM = 0
+MODEL_FR = 1      # Hu-Sawicki f(R), n = 1 (Sec. 5.1)
+MODEL_NDGP = 2    # normal-branch DGP (Sec. 5.2)
+
+FILTER_GAUSS = 0
+FILTER_TOPHAT = 1
+FILTER_SHARPK = 2
+
+H0_OVER_C = 1.0 / 2997.92458   # h/Mpc
+
+
+@dataclass(frozen=True)
+class Params:
+    omega_m: float = 0.3
+    omega_b: float = 0.05
+    h: float = 0.7
+    n_s: float = 0.96
+    sigma8: float = 0.8
+    t_cmb: float = 2.7255
+    model: int = MODEL_LCDM
+    fr0_abs: float = 1e-5
+    rc_h0: float = 1.0
+    screening: int = 1
+    filter: int = FILTER_GAUSS
+    r_smooth: float = 1.0
+    growth_mode: int = 0          # 0: true D(k,a) of the model; 1: LCDM growth factors
+    np1d: int = 32
+    nmesh1d: int = 64
+    box: float = 200.0
+    z_init: float = 19.0
+    n_steps: int = 10
+    seed: int = 1
+
+    @property
+    def a_ini(self):
+        return 1.0 / (1.0 + self.z_init)
+
+    @property
+    def n_part(self):
+        return self.np1d ** 3
+
+    @property
+    def n_cells(self):
+        return self.nmesh1d ** 3
+
+    @property
+    def cell(self):
+        return self.box / self.nmesh1d
+
+    @property
+    def scale_dependent(self):
+        """True when the LPT growth factors depend on k (Sec. 4): only f(R) run
+        with its own growth factors.  LCDM and nDGP have k-independent D1, D2
+        (Sec. 5.2), and growth_mode 1 forces the LCDM factors (Sec. 7.1)."""
+        return self.model == MODEL_FR and self.growth_mode == 0
+
+    def with_(self, **kw):
+        return replace(self, **kw)
+
+
+def is_2a3b(n):
+    if n < 2 or n % 2:
+        return False
+    while n % 2 == 0:
+        n //= 2
+    while n % 3 == 0:
+        n //= 3
+    return n == 1

@@ -1,0 +1,238 @@
+"""Pins of the oracle's background, model functions and growth factors against closed
+forms, limits and cross-checks between independent passages of the paper."""
+
+import numpy as np
+import pytest
+from scipy import integrate
+
+from oracle import Params, MODEL_FR, MODEL_NDGP
+from oracle.background import E, tau_between, omega_m_of_a
+from oracle.growth import solve_growth
+from oracle.models import (Model, fr_a2m2, fr_fR_abs, fr_gamma2E, fr_mu, fr_X, fr_Y,
+                           dgp_beta, dgp_gamma2E_orth, eps_vainshtein, eps_chameleon)
+from oracle.params import H0_OVER_C
+
+ONE = lambda k, a: np.ones_like(k)      # noqa: E731
+ZERO = lambda k, a: np.zeros_like(k)    # noqa: E731
+
+
+def test_tau_eds_closed_form():
+    # EdS: d tau = da / a^(3/2)  ->  tau = 2 (a0^-1/2 - a^-1/2)
+    for a0, a1 in [(0.05, 1.0), (0.1, 0.37), (0.5, 0.9)]:
+        assert tau_between(a0, a1, 1.0) == pytest.approx(2 * (a0 ** -0.5 - a1 ** -0.5),
+                                                         rel=1e-12)
+
+
+def test_growth_eds_lcdm_closed_form():
+    # EdS, mu = 1: D1 = a/a_ini, D2 = -(3/7) D1^2 exactly (Sec. 3.2)
+    ai = 0.05
+    a = np.array([0.05, 0.1, 0.3, 0.77, 1.0])
+    G = solve_growth(np.array([0.0]), a, 1.0, ONE, ZERO, ai)[:, 0, :]
+    D1 = a / ai
+    assert np.allclose(G[:, 0], D1, rtol=1e-10, atol=0)
+    assert np.allclose(G[:, 3], -3.0 / 7.0 * D1 ** 2, rtol=1e-10, atol=0)
+    # tau-derivatives: dD1/dtau = a^{3/2}/a_ini, D1'' = (3/2) a^2/a_ini
+    assert np.allclose(G[:, 1], a ** 1.5 / ai, rtol=1e-10)
+    assert np.allclose(G[:, 2], 1.5 * a ** 2 / ai, rtol=1e-12)
+
+
+def _eds_const_mu(mu, a, ai):
+    """Closed form for EdS with constant mu: D1 = sum c_s (a/ai)^p_s,
+    p(p + 1/2) = (3/2) mu; D2 from the particular solutions of the D1^2 source plus
+    the homogeneous solution fixed by D2 = -3/7, dD2/dtau = -(6/7) a_i^{1/2}."""
+    disc = np.sqrt(1 + 24 * mu)
+    p = np.array([(-1 + disc) / 4, (-1 - disc) / 4])
+    # D1(ai) = 1, dD1/dtau(ai) = ai^{1/2}  with d(a^p)/dtau = p a^(p+1/2)
+    cp = (1 - p[1]) / (p[0] - p[1])
+    c = np.array([cp, 1 - cp])
+    x = a / ai
+    D1 = c[0] * x ** p[0] + c[1] * x ** p[1]
+    # particular solution of D'' - (3/2) mu a D = -(3/2) mu a D1^2:
+    # for a source term s x^q (x = a/ai): A x^q with A [q(q+1/2) - 3mu/2] = -(3/2) mu s
+    part = np.zeros_like(x)
+    dpart0 = 0.0
+    part0 = 0.0
+    for i in range(2):
+        for j in range(2):
+            q = p[i] + p[j]
+            s = c[i] * c[j]
+            A = -1.5 * mu * s / (q * (q + 0.5) - 1.5 * mu)
+            part += A * x ** q
+            part0 += A
+            dpart0 += A * q
+    # homogeneous b_s x^p_s with  part0 + sum b = -3/7,  dpart0 + sum b p = -6/7
+    M = np.array([[1, 1], [p[0], p[1]]])
+    b = np.linalg.solve(M, [-3 / 7 - part0, -6 / 7 - dpart0])
+    D2 = part + b[0] * x ** p[0] + b[1] * x ** p[1]
+    return D1, D2
+
+
+@pytest.mark.parametrize("mu", [4.0 / 3.0, 1.1, 0.9])
+def test_growth_eds_constant_mu_closed_form(mu):
+    ai = 0.05
+    a = np.array([0.08, 0.2, 0.5, 1.0])
+    G = solve_growth(np.array([0.0]), a, 1.0, lambda k, aa: np.full_like(k, mu), ZERO, ai)
+    D1, D2 = _eds_const_mu(mu, a, ai)
+    assert np.allclose(G[:, 0, 0], D1, rtol=1e-10)
+    assert np.allclose(G[:, 0, 3], D2, rtol=1e-10)
+
+
+def test_growth_lcdm_growing_plus_decaying_mode():
+    # LCDM: the two solutions of D'' = kappa D are the growing mode
+    # D+ = E(a) int_0^a da'/(a' E)^3 (Heath 1977) and the decaying mode D- = E(a).
+    om, ai = 0.3, 0.05
+    a = np.array([0.05, 0.2, 0.6, 1.0])
+
+    def Dp(x):
+        v, _ = integrate.quad(lambda t: 1.0 / (t * E(t, om)) ** 3, 0.0, x, epsabs=0,
+                              epsrel=1e-13, limit=200)
+        return E(x, om) * v
+
+    def dDp_dtau(x):      # d/dtau = a^3 E d/da
+        h = 1e-5 * x
+        return x ** 3 * E(x, om) * (Dp(x + h) - Dp(x - h)) / (2 * h)
+
+    def dDm_dtau(x):      # dE/da = -1.5 om a^-4 / E
+        return x ** 3 * E(x, om) * (-1.5 * om * x ** -4 / E(x, om))
+
+    # fit alpha D+ + beta D- to D1 = 1, D1' = a_i^2 E(a_i)
+    Mx = np.array([[Dp(ai), E(ai, om)], [dDp_dtau(ai), dDm_dtau(ai)]])
+    al, be = np.linalg.solve(Mx, [1.0, ai ** 2 * E(ai, om)])
+    want = np.array([al * Dp(x) + be * E(x, om) for x in a])
+    G = solve_growth(np.array([0.0]), a, om, ONE, ZERO, ai)
+    assert np.allclose(G[:, 0, 0], want, rtol=1e-8)
+
+
+def test_growth_lcdm_second_order_omega_scaling():
+    # Bouchet et al. (1995): D2 ~= -(3/7) Omega_m^{-1/143} D1^2 for LCDM
+    om, ai = 0.3, 0.05
+    G = solve_growth(np.array([0.0]), np.array([1.0]), om, ONE, ZERO, ai)[0, 0]
+    assert G[3] / (-3.0 / 7.0 * G[0] ** 2) == pytest.approx(om ** (-1.0 / 143.0), abs=5e-4)
+
+
+def test_fr_growth_limits():
+    # k -> 0: LCDM growth; k -> infinity: constant mu = 4/3 (Sec. 5.1).  EdS background
+    # (Omega_m = 1) so that the large-k limit has a closed form.
+    p = Params(model=MODEL_FR, omega_m=1.0, fr0_abs=1e-5)
+    m = Model(p)
+    ai = 0.05
+    a = np.array([0.3, 1.0])
+    G = solve_growth(np.array([1e-7, 1e9]), a, 1.0, m.mu, m.gamma2_orth, ai)
+    assert np.allclose(G[:, 0, 0], a / ai, rtol=1e-9)
+    assert np.allclose(G[:, 0, 3], -3 / 7 * (a / ai) ** 2, rtol=1e-9)
+    D1, D2 = _eds_const_mu(4.0 / 3.0, a, ai)
+    assert np.allclose(G[:, 1, 0], D1, rtol=1e-8)
+    assert np.allclose(G[:, 1, 3], D2, rtol=1e-8)
+
+
+def _solve_exact_D2(k, k1, k2, cos, om, mu_fn, g2E_fn, ai, a_out):
+    """Exact second-order kernel D2(k, k1, k2, a) of eq. (fofrexact) for one triangle,
+    with D1(k1), D1(k2) integrated alongside (test helper, k-independent mu only)."""
+    c2 = cos * cos
+
+    def rhs(a, y):
+        D1a, dD1a, D1b, dD1b, D2, dD2 = y
+        kap = 1.5 * om * a
+        mk, m1 = mu_fn(k, a), mu_fn(k1, a)
+        g2 = g2E_fn(a) * (1 - c2)
+        src = -kap * mk * D1a * D1b * (1 - (2 * m1 - mk) / mk * c2
+                                       + 2 * a ** 4 * E(a, om) ** 2 / (kap * mk) * g2)
+        f = 1.0 / (a ** 3 * E(a, om))
+        return [dD1a * f, kap * m1 * D1a * f, dD1b * f, kap * mu_fn(k2, a) * D1b * f,
+                dD2 * f, (kap * mk * D2 + src) * f]
+
+    g0 = ai ** 2 * E(ai, om)
+    y0 = [1, g0, 1, g0, -3 / 7 * (1 - c2), -6 / 7 * (1 - c2) * g0]
+    s = integrate.solve_ivp(rhs, (ai, a_out), y0, method="DOP853", rtol=1e-12, atol=1e-14)
+    return s.y[4, -1]
+
+
+@pytest.mark.parametrize("model", ["lcdm", "ndgp"])
+def test_approximate_D2_exact_for_scale_independent_models(model):
+    # Sec. 4.2: the approximation is exact for gamma_2 = 0, and for
+    # gamma_2 = f(a)(1 - cos^2) with mu = mu(a) (nDGP): D2_exact = (1 - cos^2) D2_hat.
+    om, ai = 0.3, 0.05
+    if model == "lcdm":
+        mu_fn = lambda k, a: 1.0            # noqa: E731
+        g2E = lambda a: 0.0                 # noqa: E731
+        m = Model(Params())
+    else:
+        p = Params(model=MODEL_NDGP, rc_h0=0.5)
+        m = Model(p)
+        mu_fn = lambda k, a: float(m.mu(np.array([k]), a)[0])    # noqa: E731
+        g2E = lambda a: dgp_gamma2E_orth(a, om, 0.5)              # noqa: E731
+    Dhat = solve_growth(np.array([0.0]), np.array([1.0]), om, m.mu, m.gamma2_orth, ai)[0, 0, 3]
+    rng = np.random.default_rng(3)
+    for _ in range(3):
+        k1, k2 = rng.uniform(0.05, 2.0, 2)
+        cos = rng.uniform(-0.95, 0.95)
+        k = np.sqrt(k1 * k1 + k2 * k2 + 2 * k1 * k2 * cos)
+        D2 = _solve_exact_D2(k, k1, k2, cos, om, mu_fn, g2E, ai, 1.0)
+        assert D2 == pytest.approx((1 - cos * cos) * Dhat, rel=1e-9)
+
+
+def test_fr_phi_crit_integral_equals_fR():
+    # App. C: Phi_crit(a) = (9 Om / (2 beta)) int_0^a beta / ((m^2/H0^2) a'^4) da' with
+    # beta = 1/sqrt(6) and the HS m^2(a) reduces to (3/2)|f_R(a)| of Sec. 5.1.
+    om, fr0 = 0.3, 1e-5
+    for a in (0.2, 0.5, 1.0):
+        def integrand(x):
+            m2_over_H02 = fr_a2m2(x, om, fr0) / (x * x * H0_OVER_C ** 2)
+            return 1.0 / (m2_over_H02 * x ** 4)
+        I, _ = integrate.quad(integrand, 0.0, a, epsabs=0, epsrel=1e-13, limit=200)
+        assert 4.5 * om * I == pytest.approx(1.5 * fr_fR_abs(a, om, fr0), rel=1e-10)
+
+
+def test_fr_gamma2_matches_general_m_beta_form():
+    # App. C gives gamma_2^E = m^2 (dm^2/da) beta^2 Om / (2 H0^4 Pi Pi Pi) k^2/(a^4 H^2),
+    # Pi = (k/(a H0))^2 + m^2/H0^2; with HS beta = 1/sqrt(6) and m^2(a) it must equal
+    # the f(R) gamma_2^E of Sec. 5.1.
+    om, fr0 = 0.3, 1e-5
+    for a in (0.3, 1.0):
+        def m2(x):   # m^2/H0^2
+            return fr_a2m2(x, om, fr0) / (x * x * H0_OVER_C ** 2)
+        h = 1e-6 * a
+        dm2 = (m2(a + h) - m2(a - h)) / (2 * h)
+        for k, k1, k2 in [(0.1, 0.2, 0.15), (1.0, 0.7071, 0.7071), (3.0, 1.0, 2.5)]:
+            Pi = lambda q: (q / (a * H0_OVER_C)) ** 2 + m2(a)     # noqa: E731
+            H = E(a, om) * H0_OVER_C
+            gen = m2(a) * dm2 * (1 / 6) * om / (2 * Pi(k) * Pi(k1) * Pi(k2)) * k * k / (a ** 4 * H * H)
+            assert fr_gamma2E(k, k1, k2, a, om, fr0) == pytest.approx(gen, rel=1e-7)
+
+
+def test_fr_mu_limits_and_compton_scale():
+    om, fr0 = 0.3, 1e-5
+    assert fr_mu(1e-9, 1.0, om, fr0) == pytest.approx(1.0, abs=1e-12)
+    assert fr_mu(1e9, 1.0, om, fr0) == pytest.approx(4.0 / 3.0, rel=1e-12)
+    # mu = 1 + 1/6 exactly where k = a m
+    am = np.sqrt(fr_a2m2(1.0, om, fr0))
+    assert fr_mu(am, 1.0, om, fr0) == pytest.approx(1 + 1 / 6, rel=1e-14)
+    assert fr_X(1.0, om) == pytest.approx(fr_Y(om))
+
+
+def test_dgp_beta_hdot_reading():
+    # beta = 1 + 2 r_c H (1 + Hdot/(3 H^2)), Hdot = dH/dt = a H dH/da (cosmic time),
+    # evaluated by finite differences of the background, independently of the
+    # closed form used in the model.
+    om, rc = 0.3, 1.0
+    for a in (0.1, 0.5, 1.0):
+        h = 1e-6 * a
+        dHda = (E(a + h, om) - E(a - h, om)) / (2 * h)
+        Hdot = a * E(a, om) * dHda
+        want = 1 + 2 * rc * E(a, om) * (1 + Hdot / (3 * E(a, om) ** 2))
+        assert dgp_beta(a, om, rc) == pytest.approx(want, rel=1e-9)
+    assert omega_m_of_a(1.0, om) == pytest.approx(om)
+
+
+def test_screening_factor_limits():
+    # Vainshtein: eps -> 1 for x -> 0, eps sqrt(x) -> 2 for x -> infinity (Sec. 6.2)
+    assert eps_vainshtein(1e-12) == pytest.approx(1.0, abs=1e-12)
+    assert eps_vainshtein(1e12) * 1e6 == pytest.approx(2.0, rel=1e-5)
+    # the printed closed form 2(sqrt(1+x)-1)/x agrees away from x = 0
+    x = np.array([0.1, 1.0, 30.0])
+    assert np.allclose(eps_vainshtein(x), 2 * (np.sqrt(1 + x) - 1) / x, rtol=1e-14)
+    # chameleon: unscreened for shallow potentials, |3 fR/(2 Phi)| for deep ones
+    fR = 1e-5
+    assert np.all(eps_chameleon(np.array([1e-9, -1e-8, 0.0]), fR) == 1.0)
+    deep = np.array([-1e-4, 3e-4])
+    assert np.allclose(eps_chameleon(deep, fR), np.abs(1.5 * fR / deep), rtol=1e-15)
