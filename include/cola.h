@@ -1,0 +1,175 @@
+/*
+ * cola.h -- C ABI of libcola, an MI355X (gfx950) implementation of the particle-mesh
+ * hot path of COLA with scale-dependent growth and approximate screening
+ * (Winther, Koyama, Manera, Wright & Zhao, arXiv:1703.00879).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ * Units: lengths in Mpc/h, time in 1/H0, super-comoving time d tau = dt/a^2 (Sec. 2).
+ * Particles: N = np1d^3, stored in row-major Lagrangian order p = (ix*np1d + iy)*np1d + iz,
+ *   with Lagrangian position q = (L/np1d)*(ix,iy,iz) + cell/2 (cell = L/nmesh1d).
+ *   The state holds FP32 structure-of-arrays displacements u = x - q (never wrapped)
+ *   and FP32 residual velocities v = d(delta x)/d tau about the LPT path (Sec. 2).
+ * Memory: the library allocates nothing.  Every buffer is caller-owned device memory
+ *   whose size comes from cola_query_sizes(); the state struct is caller-owned host
+ *   memory holding those device pointers and the step counter.
+ * Streams: every call enqueues work on the caller's stream and returns without
+ *   synchronising, except cola_power_spectrum (writes host arrays) and the
+ *   profiling read-out.
+ * Errors: every call returns a cola_status; on error nothing has been enqueued and
+ *   outputs are untouched; cola_last_error() gives a message for the calling thread.
+ * Concurrency: different states may be used from different streams at once; calls on
+ *   one state must be serialised by the caller.
+ */
+#ifndef COLA_H
+#define COLA_H
+
+#include <stddef.h>
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t cola_status;
+#define COLA_OK 0
+#define COLA_E_ARG (-1)          /* invalid parameter or NULL pointer */
+#define COLA_E_SIZE (-2)         /* buffer too small / size overflow */
+#define COLA_E_STATE (-3)        /* call out of order (e.g. step before make_ic) */
+#define COLA_E_HIP (-4)          /* a HIP runtime call failed */
+#define COLA_E_UNSUPPORTED (-5)  /* valid request this build does not implement */
+
+/* Gravity models (Sec. 5): LCDM, Hu-Sawicki f(R) with n = 1, normal-branch DGP. */
+#define COLA_LCDM 0
+#define COLA_FR_HS1 1
+#define COLA_NDGP 2
+
+/* Fourier-space smoothing windows for density (Vainshtein) screening (App. B). */
+#define COLA_SMOOTH_GAUSS 0
+#define COLA_SMOOTH_TOPHAT 1
+#define COLA_SMOOTH_SHARPK 2
+
+/* Run parameters.  Background: flat LCDM (App. B).  Initial power: Eisenstein-Hu
+ * no-wiggle shape normalised to sigma8 of linear LCDM at z = 0 and scaled back to
+ * a_ini with the LCDM growth factor.  Model inputs per Sec. 5; screening per Sec. 6.
+ * growth_mode 0 uses the model's own D1(k,a), D2(k,a) (Sec. 4); 1 uses the LCDM
+ * growth factors with the modified force (Sec. 7.1).
+ * Valid ranges (else COLA_E_ARG): 0 < omega_m <= 1, 0 <= omega_b < omega_m, h > 0,
+ * sigma8 > 0, t_cmb > 0, np1d and nmesh1d of the form 2^a 3^b with b <= 1,
+ * 8 <= np1d <= nmesh1d <= 2048, nmesh1d a multiple of np1d, box > 0, z_init > 0,
+ * 1 <= n_steps <= 4096, fr0_abs > 0 for f(R), rc_h0 > 0 for nDGP, r_smooth >= 0,
+ * filter in 0..2, model in 0..2, growth_mode in 0..1, screening in 0..1. */
+typedef struct cola_params {
+  double omega_m, omega_b, h, n_s, sigma8, t_cmb;
+  double fr0_abs;     /* |f_R0| of Hu-Sawicki f(R) (Sec. 5.1) */
+  double rc_h0;       /* r_c H0 of nDGP (Sec. 5.2) */
+  double r_smooth;    /* smoothing radius R for Vainshtein screening, Mpc/h (Sec. 6.2) */
+  double box;         /* L, Mpc/h */
+  double z_init;      /* initial redshift; a_ini = 1/(1 + z_init) */
+  uint64_t seed;      /* seed of the counter-based white noise */
+  int32_t model, screening, filter, growth_mode;
+  int32_t np1d, nmesh1d, n_steps, reserved;
+} cola_params;
+
+/* Byte sizes of the caller-owned device buffers of one state. */
+typedef struct cola_sizes {
+  size_t disp_bytes;    /* float [3][N] */
+  size_t vel_bytes;     /* float [3][N] */
+  size_t lpt_bytes;     /* LPT store: Psi1, Psi2 per particle, or phi1_k, phi2_k */
+  size_t tables_bytes;  /* FP64 growth tables, FFT twiddles, reduction scratch */
+  size_t work_bytes;    /* PM meshes and particle-grid temporaries */
+  size_t total_bytes;
+} cola_sizes;
+
+/* A run's device state (all pointers caller-owned device memory, 256-byte aligned). */
+typedef struct cola_state {
+  float* disp;          /* [3][N] u = x - q, Mpc/h */
+  float* vel;           /* [3][N] residual velocity about the LPT path */
+  void* lpt;
+  void* tables;
+  void* work;
+  int32_t next_step;    /* index i of the next cola_step (a_i -> a_{i+1}); -1 = no IC */
+  int32_t prepared;     /* set by cola_prepare / cola_make_ic */
+} cola_state;
+
+/* Sizes of every buffer a state with these parameters needs.  Pure host function:
+ * no HIP call.  Returns COLA_E_ARG for invalid parameters. */
+cola_status cola_query_sizes(const cola_params* p, cola_sizes* out);
+
+/* Validate parameters only (pure host function). */
+cola_status cola_validate(const cola_params* p);
+
+/* Build the growth tables (Secs. 4.1-4.2 and App. B: D1'' = kappa mu D1 and the
+ * approximate D2 equation with gamma_2 at k1 = k2 = k/sqrt(2), solved per integer
+ * |nu|^2 of the particle grid in FP64 on the GPU) and the FFT twiddles.  Sets
+ * st->prepared; leaves the particles untouched. */
+cola_status cola_prepare(const cola_params* p, cola_state* st, hipStream_t stream);
+
+/* 2LPT initial conditions (Secs. 3-4): seeded white noise -> delta_k with the initial
+ * spectrum -> phi1_k = delta_k/k^2 -> the 2LPT source of eq. (lcdm2lpt) -> phi2_k
+ * = -S_k/k^2; u = Psi_LPT(q, a_ini) = Psi1 - (3/7) Psi2, v = 0.  Stores the LPT fields
+ * (per particle for k-independent growth, in Fourier space for scale-dependent
+ * growth, App. A) and sets next_step = 0.  Calls cola_prepare if needed. */
+cola_status cola_make_ic(const cola_params* p, cola_state* st, hipStream_t stream);
+
+/* Particle-mesh force at scale factor a for the current displacements (Secs. 2, 6):
+ * CIC density -> FFT -> Newtonian potential plus the screened linear fifth force
+ * nabla^2 phi = a^2 m^2 phi + C kappa delta eps_screen, eps evaluated in real space
+ * -> F = -grad(Phi_N + phi) by three inverse FFTs -> CIC interpolation.
+ * force_out: device float [3][N] or NULL.  mesh_out: device float [5][nmesh^3] or NULL,
+ * unpadded row-major meshes (rho = 1 + delta, screened source S = delta eps,
+ * F_x, F_y, F_z).  Requires a prepared state; does not change it. */
+cola_status cola_pm_force(const cola_params* p, cola_state* st, double a,
+                          float* force_out, float* mesh_out, hipStream_t stream);
+
+/* One COLA step a_i -> a_{i+1} (Sec. 2; leapfrog with merged kicks, a_i uniform in a):
+ * PM force at x(a_i); v += dtau_kick (F - d^2 Psi_LPT/dtau^2 (q, a_i));
+ * u += dtau_drift v + Psi_LPT(q, a_{i+1}) - Psi_LPT(q, a_i).  For scale-dependent
+ * growth the LPT terms are rebuilt every step by inverse FFTs of the stored k-space
+ * fields times D(k,a) (App. A).  i must equal st->next_step (else COLA_E_STATE);
+ * increments it. */
+cola_status cola_step(const cola_params* p, cola_state* st, int32_t i, hipStream_t stream);
+
+/* Shell-averaged power spectrum of the current particles (the P(k) output of Sec. 8):
+ * CIC on the PM mesh, FFT, P_b = < L^3 |delta_k|^2 / (M^2 W_CIC^2) > over shells
+ * b = floor(|nu| + 1/2), modes weighted 2 for 0 < nu_z < n/2.  Host outputs k_out,
+ * p_out (double [nbins]) and nmodes_out (int64 [nbins], may be NULL); bin 0 (k = 0)
+ * is reported as zero power.  Synchronises the stream. */
+cola_status cola_power_spectrum(const cola_params* p, cola_state* st, int32_t nbins,
+                                double* k_out, double* p_out, int64_t* nmodes_out,
+                                hipStream_t stream);
+
+/* Wrapped comoving positions x = (q + u) mod L into device float [3][N]. */
+cola_status cola_positions(const cola_params* p, const cola_state* st, float* xyz_out,
+                           hipStream_t stream);
+
+/* Copy the FP64 growth table slice of step i (0..n_steps) to host memory:
+ * out[k*6 + c] = (D1, D1', D1'', D2, D2', D2'')[c] at a_i for integer |nu|^2 = k,
+ * k = 0 .. n_k-1 (n_k = 1 for k-independent growth).  Synchronises.  *n_k_out gets n_k. */
+cola_status cola_growth_table(const cola_params* p, const cola_state* st, int32_t i,
+                              double* out, int64_t out_len, int64_t* n_k_out,
+                              hipStream_t stream);
+
+/* Fill dst (device float, nmesh^3 or np^3 unpadded row-major as chosen by `grid`:
+ * 0 = particle grid) with the seeded unit Gaussian white noise the initial
+ * conditions use (SplitMix64, Box-Muller).  For checking the generator. */
+cola_status cola_white_noise(const cola_params* p, int32_t grid, float* dst,
+                             hipStream_t stream);
+
+/* Kernel timing by HIP events on the launch stream: enable (1) / disable (0)
+ * recording; read accumulated milliseconds and launch counts per kernel name
+ * (synchronises the last recorded stream).  names/ms/counts are host arrays of
+ * length cap; returns the number of kernels in *n_out. */
+cola_status cola_profile_enable(int32_t on);
+cola_status cola_profile_read(char (*names)[48], double* ms, int64_t* counts,
+                              int32_t cap, int32_t* n_out);
+cola_status cola_profile_reset(void);
+
+const char* cola_status_string(cola_status s);
+const char* cola_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* COLA_H */

@@ -1,0 +1,549 @@
+// C ABI of libcola: argument checks, buffer carving, and the order of kernel launches
+// for the initial conditions, the PM force, the COLA step and the power spectrum.
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "internal.h"
+
+namespace cola {
+
+// ------------------------------------------------------------------ errors
+static thread_local std::string g_last_error;
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+template <class F>
+static cola_status guarded(F&& f) {
+  try {
+    f();
+    return COLA_OK;
+  } catch (const Error& e) {
+    set_error(e.msg);
+    return e.code;
+  } catch (const std::exception& e) {
+    set_error(e.what());
+    return COLA_E_HIP;
+  }
+}
+
+// ------------------------------------------------------------------ profiling
+namespace {
+struct Pending {
+  const char* name;
+  hipEvent_t a, b;
+};
+struct ProfState {
+  std::mutex mu;
+  bool on = false;
+  std::vector<Pending> pending;
+  std::vector<hipEvent_t> pool;
+  std::map<std::string, std::pair<double, int64_t>> acc;
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e;
+    COLA_HIP_CHECK(hipEventCreate(&e));
+    return e;
+  }
+  void drain() {   // caller holds mu
+    for (auto& p : pending) {
+      COLA_HIP_CHECK(hipEventSynchronize(p.b));
+      float ms = 0.f;
+      COLA_HIP_CHECK(hipEventElapsedTime(&ms, p.a, p.b));
+      auto& slot = acc[p.name];
+      slot.first += ms;
+      slot.second += 1;
+      pool.push_back(p.a);
+      pool.push_back(p.b);
+    }
+    pending.clear();
+  }
+};
+ProfState& prof() {
+  static ProfState s;
+  return s;
+}
+}  // namespace
+
+ProfScope::ProfScope(const char* name, hipStream_t s) : name_(name), s_(s) {
+  ProfState& P = prof();
+  if (!P.on) return;
+  std::lock_guard<std::mutex> lk(P.mu);
+  a_ = P.get();
+  b_ = P.get();
+  COLA_HIP_CHECK(hipEventRecord(a_, s_));
+}
+
+ProfScope::~ProfScope() {
+  if (!a_) return;
+  ProfState& P = prof();
+  std::lock_guard<std::mutex> lk(P.mu);
+  if (hipEventRecord(b_, s_) == hipSuccess) P.pending.push_back({name_, a_, b_});
+  if (P.pending.size() > 4096) {
+    try {
+      P.drain();
+    } catch (...) {
+    }
+  }
+}
+
+// ------------------------------------------------------------------ buffers of a state
+struct Bufs {
+  Layout L;
+  double* growth;
+  double* ref;
+  float2* tw_m;
+  float2* tw_p;
+  void* pk_scratch;
+  float4* pk_out;
+  unsigned long long* pk_cnt;
+  float2* mesh[5];
+  float2* pf[6];
+  float2* phi1;
+  float2* phi2;
+  float* psi1;
+  float* psi2;
+};
+
+template <class T>
+static T* at(void* base, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(base) + off);
+}
+
+static void check_ptr(const void* p, const char* what) {
+  if (!p) throw Error{COLA_E_ARG, std::string(what) + " is NULL"};
+  if (reinterpret_cast<uintptr_t>(p) % kAlign)
+    throw Error{COLA_E_ARG, std::string(what) + " must be 256-byte aligned"};
+}
+
+static Bufs carve(const cola_params& p, const cola_state* st) {
+  if (!st) throw Error{COLA_E_ARG, "state is NULL"};
+  Bufs b;
+  b.L = make_layout(p);
+  const Layout& L = b.L;
+  check_ptr(st->disp, "state.disp");
+  check_ptr(st->vel, "state.vel");
+  check_ptr(st->lpt, "state.lpt");
+  check_ptr(st->tables, "state.tables");
+  check_ptr(st->work, "state.work");
+  b.growth = at<double>(st->tables, L.off_growth);
+  b.ref = at<double>(st->tables, L.off_ref);
+  b.tw_m = at<float2>(st->tables, L.off_tw_m);
+  b.tw_p = at<float2>(st->tables, L.off_tw_p);
+  b.pk_scratch = at<void>(st->tables, L.off_scratch);
+  b.pk_out = at<float4>(st->tables, L.off_scratch + pk_scratch_bytes(L, 2048));
+  b.pk_cnt = reinterpret_cast<unsigned long long*>(b.pk_out + 2048);
+  for (int i = 0; i < 5; ++i) b.mesh[i] = at<float2>(st->work, L.off_mesh[i]);
+  for (int i = 0; i < 6; ++i) b.pf[i] = L.kdep ? at<float2>(st->work, L.off_pfield[i]) : nullptr;
+  if (L.kdep) {
+    b.phi1 = at<float2>(st->lpt, 0);
+    b.phi2 = at<float2>(st->lpt, align_up(L.pgrid_elems * sizeof(float2)));
+    b.psi1 = b.psi2 = nullptr;
+  } else {
+    b.phi1 = b.phi2 = nullptr;
+    b.psi1 = at<float>(st->lpt, 0);
+    b.psi2 = at<float>(st->lpt, L.disp_bytes);
+  }
+  return b;
+}
+
+static FFTPlan plan_mesh(const Bufs& b) { return FFTPlan{b.L.nm, b.L.pitch_m, b.tw_m}; }
+static FFTPlan plan_part(const Bufs& b) { return FFTPlan{b.L.np, b.L.pitch_p, b.tw_p}; }
+
+static inline float* R(float2* p) { return reinterpret_cast<float*>(p); }
+
+// Twiddle tables exp(-2 pi i t / n) in double precision, rounded once; kept for the life
+// of the process so the asynchronous upload never reads freed host memory.
+static const std::vector<float2>& twiddles(int n) {
+  static std::mutex mu;
+  static std::map<int, std::vector<float2>> cache;
+  std::lock_guard<std::mutex> lk(mu);
+  auto it = cache.find(n);
+  if (it != cache.end()) return it->second;
+  std::vector<float2> t(n);
+  for (int i = 0; i < n; ++i) {
+    const double ang = -2.0 * M_PI * i / n;
+    t[i] = make_float2((float)std::cos(ang), (float)std::sin(ang));
+  }
+  return cache.emplace(n, std::move(t)).first->second;
+}
+
+static void do_prepare(const cola_params& p, cola_state* st, const Bufs& b, hipStream_t s) {
+  const auto& tm = twiddles(b.L.nm);
+  const auto& tp = twiddles(b.L.np);
+  COLA_HIP_CHECK(hipMemcpyAsync(b.tw_m, tm.data(), tm.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+  COLA_HIP_CHECK(hipMemcpyAsync(b.tw_p, tp.data(), tp.size() * sizeof(float2), hipMemcpyHostToDevice, s));
+  launch_growth_ode(p, b.L, b.growth, b.ref, s);
+  st->prepared = 1;
+}
+
+// ------------------------------------------------------------------ PM force core
+// Writes the three force meshes (real, padded) into mesh[0], mesh[3], mesh[4].
+// mesh[0] holds rho after the deposit; mesh[1] delta_k; mesh[2] the screening field and
+// then S_k.  If flat_out is given, rho and S are copied there before being overwritten.
+static void pm_core(const cola_params& p, const Bufs& b, const float* disp, double a,
+                    float* flat_out, hipStream_t s) {
+  const Layout& L = b.L;
+  const FFTPlan pl = plan_mesh(b);
+  const StepScalars sc = step_scalars(p, a);
+  float2* const* M = b.mesh;
+  const float invM = (float)(1.0 / (double)L.M);
+  launch_deposit(L, disp, R(M[0]), s);
+  if (flat_out) launch_unpad_mesh(L, R(M[0]), flat_out, s);
+  fft_r2c(pl, R(M[0]), M[1], s);
+  const float2* src = nullptr;
+  KOp base;
+  base.kf = (float)(2.0 * M_PI / p.box);
+  if (sc.screen) {
+    KOp op = base;
+    op.a = M[1];
+    op.scale = invM;
+    if (p.model == COLA_FR_HS1) {
+      op.g_n = -sc.kappa;
+      fft_c2r(pl, K_POT, op, M[2], R(M[2]), s);
+    } else {
+      op.r_smooth = (float)p.r_smooth;
+      op.filter = p.filter;
+      fft_c2r(pl, K_SMOOTH, op, M[2], R(M[2]), s);
+    }
+    launch_screen(p, L, sc, R(M[0]), R(M[2]), s);
+    if (flat_out) launch_unpad_mesh(L, R(M[2]), flat_out + L.M, s);
+    fft_r2c(pl, R(M[2]), M[2], s);
+    src = M[2];
+  } else if (flat_out) {
+    launch_unpad_mesh(L, R(M[0]), flat_out + L.M, s, 1.f);   // S = delta = rho - 1
+  }
+  float2* outs[3] = {M[0], M[3], M[4]};
+  for (int c = 0; c < 3; ++c) {
+    KOp op = base;
+    op.a = M[1];
+    op.b = src;
+    op.comp = c;
+    op.g_n = -sc.kappa;
+    op.g_5 = sc.fifth ? -sc.coupling * sc.kappa : 0.f;
+    op.a2m2 = sc.a2m2;
+    op.scale = invM;
+    fft_c2r(pl, K_FORCE, op, outs[c], R(outs[c]), s);
+  }
+}
+
+}  // namespace cola
+
+using namespace cola;
+
+// ------------------------------------------------------------------ C ABI
+extern "C" {
+
+const char* cola_status_string(cola_status s) {
+  switch (s) {
+    case COLA_OK: return "ok";
+    case COLA_E_ARG: return "invalid argument";
+    case COLA_E_SIZE: return "size error";
+    case COLA_E_STATE: return "call out of order";
+    case COLA_E_HIP: return "HIP runtime error";
+    case COLA_E_UNSUPPORTED: return "unsupported";
+    default: return "unknown status";
+  }
+}
+
+const char* cola_last_error(void) { return g_last_error.c_str(); }
+
+cola_status cola_validate(const cola_params* p) {
+  return guarded([&] {
+    if (!p) throw Error{COLA_E_ARG, "params is NULL"};
+    validate(*p);
+  });
+}
+
+cola_status cola_query_sizes(const cola_params* p, cola_sizes* out) {
+  return guarded([&] {
+    if (!p || !out) throw Error{COLA_E_ARG, "NULL argument"};
+    const Layout L = make_layout(*p);
+    out->disp_bytes = L.disp_bytes;
+    out->vel_bytes = L.disp_bytes;
+    out->lpt_bytes = L.lpt_bytes;
+    out->tables_bytes = L.tables_bytes;
+    out->work_bytes = L.work_bytes;
+    out->total_bytes = 2 * L.disp_bytes + L.lpt_bytes + L.tables_bytes + L.work_bytes;
+  });
+}
+
+cola_status cola_prepare(const cola_params* p, cola_state* st, hipStream_t s) {
+  return guarded([&] {
+    if (!p) throw Error{COLA_E_ARG, "params is NULL"};
+    const Bufs b = carve(*p, st);
+    do_prepare(*p, st, b, s);
+  });
+}
+
+cola_status cola_make_ic(const cola_params* p, cola_state* st, hipStream_t s) {
+  return guarded([&] {
+    if (!p) throw Error{COLA_E_ARG, "params is NULL"};
+    const Bufs b = carve(*p, st);
+    const Layout& L = b.L;
+    do_prepare(*p, st, b, s);
+    const FFTPlan pp = plan_part(b);
+    float2* const* M = b.mesh;
+    const float invN = (float)(1.0 / (double)L.N);
+    KOp base;
+    base.kf = (float)(2.0 * M_PI / p->box);
+    // white noise -> W_k -> phi1_k = delta_k / k^2
+    launch_noise(*p, L.np, L.pitch_p, R(M[0]), nullptr, s);
+    fft_r2c(pp, R(M[0]), M[0], s);
+    float2* phi1 = L.kdep ? b.phi1 : M[1];
+    launch_ic_phi1(*p, L, M[0], phi1, sigma8_norm(*p), b.ref, s);
+    // 2LPT source S = sum_{i<j} phi_ii phi_jj - phi_ij^2 (eq. lcdm2lpt)
+    for (int c = 0; c < 3; ++c) {
+      KOp op = base;
+      op.a = phi1;
+      op.comp = op.comp2 = c;
+      op.scale = invN;
+      fft_c2r(pp, K_HESS, op, M[2 + c], R(M[2 + c]), s);
+    }
+    const size_t nreal = 2 * L.pgrid_elems;
+    launch_2lpt_diag(R(M[2]), R(M[3]), R(M[4]), nreal, s);
+    const int mix[3][2] = {{0, 1}, {0, 2}, {1, 2}};
+    for (auto& ij : mix) {
+      KOp op = base;
+      op.a = phi1;
+      op.comp = ij[0];
+      op.comp2 = ij[1];
+      op.scale = invN;
+      fft_c2r(pp, K_HESS, op, M[0], R(M[0]), s);
+      launch_2lpt_sub(R(M[2]), R(M[0]), nreal, s);
+    }
+    fft_r2c(pp, R(M[2]), M[2], s);
+    float2* phi2 = L.kdep ? b.phi2 : M[3];
+    {
+      KOp op = base;
+      op.a = M[2];
+      op.g_n = -1.f;
+      op.scale = 1.f;
+      op.n = L.np;
+      op.pitch = L.pitch_p;
+      launch_kspace(K_POT, op, phi2, s);   // phi2_k = -S_k / k^2
+    }
+    float2* outs[3] = {M[0], M[2], M[4]};
+    const float* f3[3] = {R(M[0]), R(M[2]), R(M[4])};
+    if (L.kdep) {
+      // u(a_ini) = IDFT[i k (D1(k, a_0) phi1_k + D2(k, a_0) phi2_k)]
+      for (int c = 0; c < 3; ++c) {
+        KOp op = base;
+        op.a = phi1;
+        op.b = phi2;
+        op.table = b.growth;
+        op.tab_slice0 = 0;
+        op.lpt_mode = 2;
+        op.kdep = 1;
+        op.comp = c;
+        op.scale = invN;
+        fft_c2r(pp, K_LPT, op, outs[c], R(outs[c]), s);
+      }
+      launch_unpad3(L, f3, nullptr, 1.f, 0.f, st->disp, s);
+    } else {
+      float* dst[2] = {b.psi1, b.psi2};
+      float2* src[2] = {phi1, phi2};
+      for (int o = 0; o < 2; ++o) {
+        for (int c = 0; c < 3; ++c) {
+          KOp op = base;
+          op.a = src[o];
+          op.comp = c;
+          op.scale = invN;
+          fft_c2r(pp, K_GRAD, op, outs[c], R(outs[c]), s);
+        }
+        launch_unpad3(L, f3, nullptr, 1.f, 0.f, dst[o], s);
+      }
+      launch_combine_u0(L, b.psi1, b.psi2, b.growth, st->disp, s);
+    }
+    launch_fill(st->vel, 3 * (size_t)L.N, 0.f, s);
+    st->next_step = 0;
+  });
+}
+
+cola_status cola_pm_force(const cola_params* p, cola_state* st, double a, float* force_out,
+                          float* mesh_out, hipStream_t s) {
+  return guarded([&] {
+    if (!p) throw Error{COLA_E_ARG, "params is NULL"};
+    const Bufs b = carve(*p, st);
+    if (!st->prepared) throw Error{COLA_E_STATE, "state not prepared"};
+    if (!(a > 0.0 && a <= 10.0)) throw Error{COLA_E_ARG, "a must be in (0, 10]"};
+    pm_core(*p, b, st->disp, a, mesh_out, s);
+    if (mesh_out) {
+      launch_unpad_mesh(b.L, R(b.mesh[0]), mesh_out + 2 * b.L.M, s);
+      launch_unpad_mesh(b.L, R(b.mesh[3]), mesh_out + 3 * b.L.M, s);
+      launch_unpad_mesh(b.L, R(b.mesh[4]), mesh_out + 4 * b.L.M, s);
+    }
+    if (force_out) {
+      GatherArgs g{};
+      g.F[0] = R(b.mesh[0]);
+      g.F[1] = R(b.mesh[3]);
+      g.F[2] = R(b.mesh[4]);
+      g.disp = st->disp;
+      g.vel = st->vel;
+      g.force_out = force_out;
+      launch_gather(b.L, g, s);
+    }
+  });
+}
+
+cola_status cola_step(const cola_params* p, cola_state* st, int32_t i, hipStream_t s) {
+  return guarded([&] {
+    if (!p) throw Error{COLA_E_ARG, "params is NULL"};
+    const Bufs b = carve(*p, st);
+    const Layout& L = b.L;
+    if (!st->prepared || st->next_step < 0) throw Error{COLA_E_STATE, "no initial conditions"};
+    if (i != st->next_step) throw Error{COLA_E_STATE, "step index out of order"};
+    if (i < 0 || i >= p->n_steps) throw Error{COLA_E_STATE, "step index beyond n_steps"};
+    const Cosmo cz{p->omega_m, 1.0 - p->omega_m};
+    const double ai = a_of_step(*p, i), an = a_of_step(*p, i + 1);
+    const double a_lo = (i == 0) ? ai : 0.5 * (a_of_step(*p, i - 1) + ai);
+    const double a_hi = 0.5 * (ai + an);
+    GatherArgs g{};
+    g.dtk = tau_between(cz, a_lo, a_hi);
+    g.dtd = tau_between(cz, ai, an);
+    g.table = b.growth;
+    g.slice0 = (int64_t)i * L.n_k * 6;
+    g.slice1 = (int64_t)(i + 1) * L.n_k * 6;
+    if (L.kdep) {
+      // L''(q, a_i) and Psi_LPT(a_{i+1}) - Psi_LPT(a_i) from the stored k-space fields
+      const FFTPlan pp = plan_part(b);
+      for (int c = 0; c < 6; ++c) {
+        KOp op;
+        op.kf = (float)(2.0 * M_PI / p->box);
+        op.a = b.phi1;
+        op.b = b.phi2;
+        op.table = b.growth;
+        op.tab_slice0 = g.slice0;
+        op.tab_slice1 = g.slice1;
+        op.lpt_mode = c < 3 ? 0 : 1;
+        op.kdep = 1;
+        op.comp = c % 3;
+        op.scale = (float)(1.0 / (double)L.N);
+        fft_c2r(pp, K_LPT, op, b.pf[c], R(b.pf[c]), s);
+        if (c < 3)
+          g.lpp[c] = R(b.pf[c]);
+        else
+          g.dlt[c - 3] = R(b.pf[c]);
+      }
+    } else {
+      g.psi1 = b.psi1;
+      g.psi2 = b.psi2;
+    }
+    pm_core(*p, b, st->disp, ai, nullptr, s);
+    g.F[0] = R(b.mesh[0]);
+    g.F[1] = R(b.mesh[3]);
+    g.F[2] = R(b.mesh[4]);
+    g.disp = st->disp;
+    g.vel = st->vel;
+    launch_gather(L, g, s);
+    st->next_step = i + 1;
+  });
+}
+
+cola_status cola_power_spectrum(const cola_params* p, cola_state* st, int32_t nbins, double* k_out,
+                                double* p_out, int64_t* nmodes_out, hipStream_t s) {
+  return guarded([&] {
+    if (!p || !k_out || !p_out) throw Error{COLA_E_ARG, "NULL argument"};
+    const Bufs b = carve(*p, st);
+    if (nbins < 1 || nbins > 2048) throw Error{COLA_E_ARG, "nbins must be in [1, 2048]"};
+    launch_deposit(b.L, st->disp, R(b.mesh[0]), s);
+    fft_r2c(plan_mesh(b), R(b.mesh[0]), b.mesh[1], s);
+    launch_pk(b.L, b.mesh[1], nbins, b.pk_scratch, b.pk_out, b.pk_cnt, s);
+    std::vector<float4> o(nbins);
+    std::vector<unsigned long long> c(nbins);
+    COLA_HIP_CHECK(hipMemcpyAsync(o.data(), b.pk_out, nbins * sizeof(float4), hipMemcpyDeviceToHost, s));
+    COLA_HIP_CHECK(hipMemcpyAsync(c.data(), b.pk_cnt, nbins * sizeof(unsigned long long),
+                                  hipMemcpyDeviceToHost, s));
+    COLA_HIP_CHECK(hipStreamSynchronize(s));
+    for (int i = 0; i < nbins; ++i) {
+      const double w = (double)c[i];
+      const double sp = (double)o[i].x + (double)o[i].y;
+      const double sk = (double)o[i].z + (double)o[i].w;
+      k_out[i] = w > 0 ? sk / w : 0.0;
+      p_out[i] = w > 0 ? sp / w : 0.0;
+      if (nmodes_out) nmodes_out[i] = (int64_t)c[i];
+    }
+  });
+}
+
+cola_status cola_positions(const cola_params* p, const cola_state* st, float* xyz, hipStream_t s) {
+  return guarded([&] {
+    if (!p || !xyz) throw Error{COLA_E_ARG, "NULL argument"};
+    const Bufs b = carve(*p, st);
+    launch_positions(*p, b.L, st->disp, xyz, s);
+  });
+}
+
+cola_status cola_growth_table(const cola_params* p, const cola_state* st, int32_t i, double* out,
+                              int64_t out_len, int64_t* n_k_out, hipStream_t s) {
+  return guarded([&] {
+    if (!p || !out) throw Error{COLA_E_ARG, "NULL argument"};
+    const Bufs b = carve(*p, st);
+    if (!st->prepared) throw Error{COLA_E_STATE, "state not prepared"};
+    if (i < 0 || i > p->n_steps) throw Error{COLA_E_ARG, "slice index out of range"};
+    const int64_t n = b.L.n_k * 6;
+    if (out_len < n) throw Error{COLA_E_SIZE, "output buffer too small"};
+    COLA_HIP_CHECK(hipMemcpyAsync(out, b.growth + (int64_t)i * n, n * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+    COLA_HIP_CHECK(hipStreamSynchronize(s));
+    if (n_k_out) *n_k_out = b.L.n_k;
+  });
+}
+
+cola_status cola_white_noise(const cola_params* p, int32_t grid, float* dst, hipStream_t s) {
+  return guarded([&] {
+    if (!p || !dst) throw Error{COLA_E_ARG, "NULL argument"};
+    validate(*p);
+    if (grid != 0) throw Error{COLA_E_UNSUPPORTED, "only the particle grid is supported"};
+    launch_noise(*p, p->np1d, half_pitch(p->np1d), nullptr, dst, s);
+  });
+}
+
+cola_status cola_profile_enable(int32_t on) {
+  return guarded([&] {
+    ProfState& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.on = on != 0;
+  });
+}
+
+cola_status cola_profile_reset(void) {
+  return guarded([&] {
+    ProfState& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.drain();
+    P.acc.clear();
+  });
+}
+
+cola_status cola_profile_read(char (*names)[48], double* ms, int64_t* counts, int32_t cap,
+                              int32_t* n_out) {
+  return guarded([&] {
+    ProfState& P = prof();
+    std::lock_guard<std::mutex> lk(P.mu);
+    P.drain();
+    int32_t n = 0;
+    for (auto& kv : P.acc) {
+      if (n < cap && names && ms && counts) {
+        std::strncpy(names[n], kv.first.c_str(), 47);
+        names[n][47] = 0;
+        ms[n] = kv.second.first;
+        counts[n] = kv.second.second;
+      }
+      ++n;
+    }
+    if (n_out) *n_out = n;
+  });
+}
+
+}  // extern "C"

@@ -1,0 +1,172 @@
+// Internal declarations shared by the libcola translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstddef>
+#include <cstdint>
+#include <string>
+
+#include "cola.h"
+
+namespace cola {
+
+// ------------------------------------------------------------------ errors
+struct Error {
+  cola_status code;
+  std::string msg;
+};
+void set_error(const std::string& msg);
+#define COLA_HIP_CHECK(expr)                                                        \
+  do {                                                                              \
+    hipError_t e_ = (expr);                                                         \
+    if (e_ != hipSuccess)                                                           \
+      throw ::cola::Error{COLA_E_HIP, std::string(#expr) + ": " + hipGetErrorString(e_)}; \
+  } while (0)
+#define COLA_LAUNCH_CHECK() COLA_HIP_CHECK(hipGetLastError())
+
+// ------------------------------------------------------------------ profiling
+// Records a pair of events around launches that carry `name` when enabled.
+struct ProfScope {
+  ProfScope(const char* name, hipStream_t s);
+  ~ProfScope();
+  const char* name_;
+  hipStream_t s_;
+  hipEvent_t a_ = nullptr, b_ = nullptr;
+};
+
+// ------------------------------------------------------------------ layout
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
+
+// Half-complex row pitch (complex elements): n/2 + 1 rounded up to 16, so every row of
+// a padded real or half-complex mesh starts on a 128-byte boundary.
+inline int half_pitch(int n) { return (n / 2 + 1 + 15) / 16 * 16; }
+
+struct Layout {
+  int np, nm;               // particle grid and mesh sizes (per dimension)
+  double box;               // L, Mpc/h
+  float inv_cell;           // nmesh / L
+  int64_t N, M;             // particles, mesh cells
+  int pitch_p, pitch_m;     // half-complex pitches
+  size_t pgrid_elems;       // float2 elements of a particle-grid half-complex field
+  size_t mesh_elems;        // float2 elements of a PM mesh half-complex field
+  bool kdep;                // scale-dependent LPT (k-space store)
+  int64_t n_k;              // entries per growth-table slice
+  int n_steps;
+  // offsets (bytes) inside `tables`
+  size_t off_growth, off_ref, off_tw_m, off_tw_p, off_scratch, tables_bytes;
+  size_t scratch_bytes;
+  // offsets (bytes) inside `work`
+  size_t off_mesh[5], off_pfield[6], work_bytes;
+  size_t lpt_bytes, disp_bytes;
+};
+Layout make_layout(const cola_params& p);
+void validate(const cola_params& p);   // throws Error{COLA_E_ARG}
+
+// ------------------------------------------------------------------ host physics (FP64)
+struct Cosmo {
+  double om, ol;
+  double E(double a) const;
+};
+double tau_between(const Cosmo& c, double a0, double a1);
+double sigma8_norm(const cola_params& p);        // A with sigma8^2 = A * I
+double eh_transfer(const cola_params& p, double k);
+struct StepScalars {         // PM-force scalars at scale factor a
+  double a;
+  float kappa, a2m2, coupling;
+  float cham_thr;   // f(R): screening threshold on |Phi_code|: (3/2)|f_R(a)| a^2 / (H0/c)^2
+  float vx_pref;    // nDGP: x = vx_pref (1 + delta_R), 8 (rc H0)^2 Om / (9 beta^2 a^3)
+  float beta;
+  int fifth, screen;  // fifth force on, screening on
+};
+StepScalars step_scalars(const cola_params& p, double a);
+double a_of_step(const cola_params& p, int i);
+
+// ------------------------------------------------------------------ k-space operators
+enum KKind : int {
+  K_COPY = 0,      // out = scale * a
+  K_FORCE = 1,     // out = -i k_c [g_n/k^2 a + g_5/(k^2+a2m2) b] * scale
+  K_POT = 2,       // out = g_n/k^2 a * scale
+  K_SMOOTH = 3,    // out = W(kR) a * scale (k = 0 -> 0)
+  K_LPT = 4,       // out = i k_c (X1 a + X2 b) * scale, X from the growth table
+  K_HESS = 5,      // out = -k_i k_j a * scale
+  K_GRAD = 6,      // out = i k_c a * scale
+  K_INVLAP = 7,    // out = g_n/k^2 a * scale (alias of K_POT with separate name)
+};
+
+struct KOp {
+  const float2* a = nullptr;
+  const float2* b = nullptr;
+  const double* table = nullptr;   // growth table base (K_LPT)
+  int64_t tab_slice0 = 0, tab_slice1 = 0;   // element offsets of two slices (K_LPT)
+  int lpt_mode = 0;                // 0: X = D''(slice0); 1: X = D(slice1) - D(slice0); 2: X = D(slice0)
+  int comp = 0, comp2 = 0;
+  float scale = 1.f;
+  float kf = 1.f;                  // 2 pi / L
+  float g_n = 0.f, g_5 = 0.f, a2m2 = 0.f;
+  float r_smooth = 0.f;
+  int filter = 0;
+  int n = 0, pitch = 0;
+  int kdep = 0;                    // growth table indexed by |nu|^2 (else entry 0)
+};
+
+// ------------------------------------------------------------------ FFT
+struct FFTPlan {
+  int n = 0;            // transform size per dimension
+  int pitch = 0;        // half-complex pitch
+  const float2* tw = nullptr;   // exp(-2 pi i t / n), t = 0..n-1 (device)
+};
+bool fft_size_supported(int n);
+// forward real-to-complex 3D transform (unnormalised, e^{-ikx}); in may alias out
+void fft_r2c(const FFTPlan& pl, const float* in, float2* out, hipStream_t s);
+// inverse complex-to-real 3D transform (unnormalised, e^{+ikx}).  The first pass reads
+// through the k-space operator `op` (kind) and writes `data`; later passes are in place;
+// the real result goes to `out` (may alias data).
+void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* out,
+             hipStream_t s);
+
+// ------------------------------------------------------------------ kernels (launchers)
+void launch_fill(float* p, size_t n, float v, hipStream_t s);
+void launch_growth_ode(const cola_params& p, const Layout& L, double* table, double* ref,
+                       hipStream_t s);
+void launch_noise(const cola_params& p, int n, int pitch, float* dst_padded, float* dst_flat,
+                  hipStream_t s);
+void launch_ic_phi1(const cola_params& p, const Layout& L, const float2* wk, float2* phi1,
+                    double A_norm, const double* ref, hipStream_t s);
+void launch_kspace(int kind, const KOp& op, float2* out, hipStream_t s);
+void launch_2lpt_diag(float* d0, const float* d1, const float* d2, size_t n, hipStream_t s);
+void launch_2lpt_sub(float* acc, const float* d, size_t n, hipStream_t s);
+// out[c][p] = alpha * f0[c](q_p) + beta * f1[c](q_p) from padded particle-grid fields
+void launch_unpad3(const Layout& L, const float* const f0[3], const float* const f1[3],
+                   float alpha, float beta, float* out, hipStream_t s);
+void launch_combine_u0(const Layout& L, const float* psi1, const float* psi2,
+                       const double* table, float* disp, hipStream_t s);
+void launch_deposit(const Layout& L, const float* disp, float* rho_padded, hipStream_t s);
+void launch_screen(const cola_params& p, const Layout& L, const StepScalars& sc,
+                   const float* rho, float* field_inout, hipStream_t s);
+struct GatherArgs {
+  const float* F[3];
+  float* disp;
+  float* vel;
+  const float* psi1;          // scale-independent LPT (else null)
+  const float* psi2;
+  const float* lpp[3];        // scale-dependent LPT fields (padded particle grid)
+  const float* dlt[3];
+  const double* table;        // growth table (scale-independent coefficients)
+  int64_t slice0, slice1;     // element offsets of slices i and i+1
+  double dtk, dtd;
+  float* force_out;           // cola_pm_force: write F_p instead of updating
+};
+void launch_gather(const Layout& L, const GatherArgs& g, hipStream_t s);
+// flat = padded - sub over the n^3 valid cells
+void launch_unpad_mesh(const Layout& L, const float* padded, float* flat, hipStream_t s,
+                       float sub = 0.f);
+void launch_positions(const cola_params& p, const Layout& L, const float* disp, float* xyz,
+                      hipStream_t s);
+// P(k) shell sums with per-block partials and a compensated cross-block reduction.
+// Writes out[b] = (sum w P hi, lo, sum w |k| hi, lo) and counts[b] = sum w (device).
+size_t pk_scratch_bytes(const Layout& L, int nbins);
+void launch_pk(const Layout& L, const float2* dk, int nbins, void* scratch, float4* out,
+               unsigned long long* counts, hipStream_t s);
+
+}  // namespace cola

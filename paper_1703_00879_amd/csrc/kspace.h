@@ -1,0 +1,98 @@
+// Fourier-space operators applied to half-complex fields, evaluated per mode.
+//
+// Layout: element (ix, iy, iz) of an n^3 half-complex field sits at
+// (ix * n + iy) * pitch + iz; nu_x = ix (ix < n/2) or ix - n, likewise nu_y, nu_z = iz
+// (0 .. n/2; iz > n/2 is row padding and evaluates to 0); k = kf * nu, kf = 2 pi / L.
+// An odd factor i k_c is zero on the Nyquist plane of axis c; a mixed factor k_i k_j
+// (i != j) is zero on the Nyquist plane of either axis; the k = 0 mode of every Green's
+// function is zero.  These keep every inverse transform Hermitian.
+#pragma once
+
+#include "internal.h"
+
+namespace cola {
+
+__device__ __forceinline__ float smooth_window(float k2R2, int filter) {
+  if (filter == 0) return expf(-0.5f * k2R2);                 // Gaussian
+  if (filter == 2) return k2R2 <= 1.f ? 1.f : 0.f;            // sharp-k, k R <= 1
+  // spherical top-hat 3 (sin x - x cos x)/x^3; its Taylor series below x = 1/2, where
+  // the closed form cancels in single precision
+  if (k2R2 < 0.25f) return 1.f - k2R2 * (0.1f - k2R2 * (1.f / 280.f - k2R2 * (1.f / 15120.f)));
+  const float x = sqrtf(k2R2);
+  float s, c;
+  sincosf(x, &s, &c);
+  return 3.f * (s - x * c) / (x * x * x);
+}
+
+template <int KIND>
+__device__ __forceinline__ float2 kspace_eval(const KOp& op, int ix, int iy, int iz, int64_t idx) {
+  const int n = op.n, h = n >> 1;
+  if (iz > h) return make_float2(0.f, 0.f);
+  const int nx = ix < h ? ix : ix - n;
+  const int ny = iy < h ? iy : iy - n;
+  const int nz = iz;
+  const int n2 = nx * nx + ny * ny + nz * nz;
+  // component selection without dynamically indexed local arrays (no scratch spills)
+  auto nyq = [&](int c) { return c == 0 ? ix == h : (c == 1 ? iy == h : iz == h); };
+  auto kc = [&](int c) { return op.kf * (float)(c == 0 ? nx : (c == 1 ? ny : nz)); };
+  if constexpr (KIND == K_COPY) {
+    const float2 a = op.a[idx];
+    return make_float2(op.scale * a.x, op.scale * a.y);
+  } else if constexpr (KIND == K_FORCE) {
+    if (n2 == 0 || nyq(op.comp)) return make_float2(0.f, 0.f);
+    const float k2 = op.kf * op.kf * (float)n2;
+    const float2 a = op.a[idx];
+    const float2 b = op.b ? op.b[idx] : a;
+    const float gn = op.g_n / k2, g5 = op.g_5 / (k2 + op.a2m2);
+    const float2 g = make_float2(gn * a.x + g5 * b.x, gn * a.y + g5 * b.y);
+    const float f = kc(op.comp) * op.scale;   // -i k_c g
+    return make_float2(f * g.y, -f * g.x);
+  } else if constexpr (KIND == K_POT) {
+    if (n2 == 0) return make_float2(0.f, 0.f);
+    const float k2 = op.kf * op.kf * (float)n2;
+    const float2 a = op.a[idx];
+    const float f = op.g_n / k2 * op.scale;
+    return make_float2(f * a.x, f * a.y);
+  } else if constexpr (KIND == K_SMOOTH) {
+    if (n2 == 0) return make_float2(0.f, 0.f);
+    const float k2 = op.kf * op.kf * (float)n2;
+    const float f = smooth_window(k2 * op.r_smooth * op.r_smooth, op.filter) * op.scale;
+    const float2 a = op.a[idx];
+    return make_float2(f * a.x, f * a.y);
+  } else if constexpr (KIND == K_LPT) {
+    if (n2 == 0 || nyq(op.comp)) return make_float2(0.f, 0.f);
+    const int64_t e = (int64_t)(op.kdep ? n2 : 0) * 6;
+    const double* t0 = op.table + op.tab_slice0 + e;
+    const double* t1 = op.table + op.tab_slice1 + e;
+    float x1, x2;
+    if (op.lpt_mode == 0) {          // second derivatives at slice 0
+      x1 = (float)t0[2];
+      x2 = (float)t0[5];
+    } else if (op.lpt_mode == 1) {   // D(slice 1) - D(slice 0)
+      x1 = (float)(t1[0] - t0[0]);
+      x2 = (float)(t1[3] - t0[3]);
+    } else {                         // D(slice 0)
+      x1 = (float)t0[0];
+      x2 = (float)t0[3];
+    }
+    const float2 a = op.a[idx];
+    const float2 b = op.b[idx];
+    const float2 g = make_float2(x1 * a.x + x2 * b.x, x1 * a.y + x2 * b.y);
+    const float f = kc(op.comp) * op.scale;   // +i k_c g
+    return make_float2(-f * g.y, f * g.x);
+  } else if constexpr (KIND == K_HESS) {
+    if (op.comp != op.comp2 && (nyq(op.comp) || nyq(op.comp2))) return make_float2(0.f, 0.f);
+    const float f = -kc(op.comp) * kc(op.comp2) * op.scale;
+    const float2 a = op.a[idx];
+    return make_float2(f * a.x, f * a.y);
+  } else if constexpr (KIND == K_GRAD) {
+    if (nyq(op.comp)) return make_float2(0.f, 0.f);
+    const float f = kc(op.comp) * op.scale;
+    const float2 a = op.a[idx];
+    return make_float2(-f * a.y, f * a.x);
+  } else {
+    return make_float2(0.f, 0.f);
+  }
+}
+
+}  // namespace cola

@@ -1,0 +1,499 @@
+// Particle-mesh kernels: CIC deposit, real-space screening, CIC gather fused with the
+// COLA kick and drift, stand-alone k-space operators, layout copies and P(k) binning.
+//
+// Particle p sits in row-major Lagrangian order, p = (ix*np + iy)*np + iz, at
+// q = (ix*ratio + 1/2) cells per axis (ratio = nmesh/np, an integer), so its position in
+// cells is s = ix*ratio + f with f = 1/2 + u/cell.  The integer and fractional parts are
+// kept apart: the CIC offset d = f - floor(f) is exact in single precision, whatever the
+// box size, and only u/cell carries rounding.
+
+#include <algorithm>
+
+#include "internal.h"
+#include "kspace.h"
+
+namespace cola {
+
+// ------------------------------------------------------------------ helpers
+struct CicCell {
+  int64_t i0[3], i1[3];   // wrapped mesh coordinates of the two nodes per axis
+  float w0[3], w1[3];     // their weights (1 - d, d)
+};
+
+__device__ __forceinline__ void cic_axis(int ixq, float u, int nm, int ratio, float inv_cell,
+                                         int64_t& i0, int64_t& i1, float& w0, float& w1) {
+  const float f = 0.5f + u * inv_cell;
+  const float fl = floorf(f);
+  const float d = f - fl;
+  int i = ixq * ratio + (int)fl;
+  i %= nm;
+  if (i < 0) i += nm;
+  i0 = i;
+  i1 = (i + 1 == nm) ? 0 : i + 1;
+  w0 = 1.f - d;
+  w1 = d;
+}
+
+__device__ __forceinline__ void cic_cell(int64_t p, int np, int nm, int ratio, float inv_cell,
+                                         const float* __restrict__ disp, int64_t N, CicCell& c) {
+  const int ip = (int)p;
+  const int ix = ip / (np * np), iy = (ip / np) % np, iz = ip % np;
+  cic_axis(ix, disp[p], nm, ratio, inv_cell, c.i0[0], c.i1[0], c.w0[0], c.w1[0]);
+  cic_axis(iy, disp[N + p], nm, ratio, inv_cell, c.i0[1], c.i1[1], c.w0[1], c.w1[1]);
+  cic_axis(iz, disp[2 * N + p], nm, ratio, inv_cell, c.i0[2], c.i1[2], c.w0[2], c.w1[2]);
+}
+
+static unsigned grid_for(int64_t n, int block, int64_t cap = 1 << 20) {
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + block - 1) / block, cap));
+}
+
+// ------------------------------------------------------------------ fill
+__global__ void k_fill(float* __restrict__ p, int64_t n, float v) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x)
+    p[i] = v;
+}
+
+void launch_fill(float* p, size_t n, float v, hipStream_t s) {
+  ProfScope ps("fill", s);
+  hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, p, (int64_t)n, v);
+  COLA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ CIC deposit
+// rho_j = sum_p m W(x_p - x_j), m = (nmesh/np)^3 so that rho averages to 1.
+__global__ void __launch_bounds__(256)
+k_deposit(const float* __restrict__ disp, float* __restrict__ rho, int64_t N, int np, int nm,
+          int ratio, float inv_cell, int rpitch, float mass) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  CicCell c;
+  cic_cell(p, np, nm, ratio, inv_cell, disp, N, c);
+#pragma unroll
+  for (int ox = 0; ox < 2; ++ox) {
+    const int64_t x = ox ? c.i1[0] : c.i0[0];
+    const float wx = mass * (ox ? c.w1[0] : c.w0[0]);
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy) {
+      const int64_t y = oy ? c.i1[1] : c.i0[1];
+      const float wxy = wx * (oy ? c.w1[1] : c.w0[1]);
+      float* row = rho + (x * nm + y) * rpitch;
+      unsafeAtomicAdd(row + c.i0[2], wxy * c.w0[2]);
+      unsafeAtomicAdd(row + c.i1[2], wxy * c.w1[2]);
+    }
+  }
+}
+
+void launch_deposit(const Layout& L, const float* disp, float* rho, hipStream_t s) {
+  {
+    ProfScope ps("deposit_zero", s);
+    const int64_t n = (int64_t)L.mesh_elems * 2;
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, rho, n, 0.f);
+    COLA_LAUNCH_CHECK();
+  }
+  ProfScope ps("deposit", s);
+  const int ratio = L.nm / L.np;
+  const float mass = (float)ratio * ratio * ratio;
+  hipLaunchKernelGGL(k_deposit, dim3((unsigned)((L.N + 255) / 256)), dim3(256), 0, s, disp, rho,
+                     L.N, L.np, L.nm, ratio, L.inv_cell, 2 * L.pitch_m, mass);
+  COLA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ real-space screening
+// S = delta * eps_screen in place over the padded real mesh (row padding left alone).
+// f(R):  eps = min(1, thr / |Phi|), thr = (3/2)|f_R(a)| a^2 / (H0/c)^2 (Sec. 6.1)
+// nDGP:  eps = 2 / (1 + sqrt(1 + x)), x = vx (1 + delta_R)_+ (Sec. 6.2)
+template <int MODEL>
+__global__ void __launch_bounds__(256)
+k_screen(const float* __restrict__ rho, float* __restrict__ field, int64_t rows, int n,
+         int rpitch, float thr, float vx) {
+  const int64_t total = rows * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n;
+    const int z = (int)(e - r * n);
+    const int64_t i = r * rpitch + z;
+    const float delta = rho[i] - 1.f;
+    const float g = field[i];
+    float eps;
+    if (MODEL == COLA_FR_HS1) {
+      const float ag = fabsf(g);
+      eps = (ag > thr) ? thr / ag : 1.f;
+    } else {
+      const float x = vx * fmaxf(0.f, 1.f + g);
+      eps = 2.f / (1.f + sqrtf(1.f + x));
+    }
+    field[i] = delta * eps;
+  }
+}
+
+void launch_screen(const cola_params& p, const Layout& L, const StepScalars& sc, const float* rho,
+                   float* field, hipStream_t s) {
+  ProfScope ps("screen", s);
+  const int64_t rows = (int64_t)L.nm * L.nm;
+  const unsigned g = grid_for(rows * L.nm, 256);
+  if (p.model == COLA_FR_HS1)
+    hipLaunchKernelGGL(k_screen<COLA_FR_HS1>, dim3(g), dim3(256), 0, s, rho, field, rows, L.nm,
+                       2 * L.pitch_m, sc.cham_thr, 0.f);
+  else
+    hipLaunchKernelGGL(k_screen<COLA_NDGP>, dim3(g), dim3(256), 0, s, rho, field, rows, L.nm,
+                       2 * L.pitch_m, 0.f, sc.vx_pref);
+  COLA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ gather + kick + drift
+struct GatherDev {
+  const float* F0; const float* F1; const float* F2;
+  float* disp; float* vel;
+  const float* psi1; const float* psi2;
+  const float* l0; const float* l1; const float* l2;
+  const float* d0; const float* d1; const float* d2;
+  const double* table; int64_t slice0, slice1;
+  float dtk, dtd;
+  float* force_out;
+};
+
+// F_p = sum_corners W F_j (same CIC weights as the deposit); then
+// v += dtk (F_p - L''(q_p)), u += dtd v + Delta(q_p)   (kick-drift about the LPT path).
+// MODE 0: scale-independent LPT (Psi1, Psi2 per particle, growth scalars from the table);
+// MODE 1: scale-dependent LPT (L'' and Delta fields on the particle grid);
+// MODE 2: force only (write F_p).
+template <int MODE>
+__global__ void __launch_bounds__(256)
+k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int rpitch,
+         int ppitch) {
+  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (p >= N) return;
+  CicCell c;
+  cic_cell(p, np, nm, ratio, inv_cell, g.disp, N, c);
+  float f0 = 0.f, f1 = 0.f, f2 = 0.f;
+#pragma unroll
+  for (int ox = 0; ox < 2; ++ox) {
+    const int64_t x = ox ? c.i1[0] : c.i0[0];
+    const float wx = ox ? c.w1[0] : c.w0[0];
+#pragma unroll
+    for (int oy = 0; oy < 2; ++oy) {
+      const int64_t y = oy ? c.i1[1] : c.i0[1];
+      const float wxy = wx * (oy ? c.w1[1] : c.w0[1]);
+      const int64_t row = (x * nm + y) * rpitch;
+      const int64_t a0 = row + c.i0[2], a1 = row + c.i1[2];
+      const float wa = wxy * c.w0[2], wb = wxy * c.w1[2];
+      f0 += wa * g.F0[a0] + wb * g.F0[a1];
+      f1 += wa * g.F1[a0] + wb * g.F1[a1];
+      f2 += wa * g.F2[a0] + wb * g.F2[a1];
+    }
+  }
+  if (MODE == 2) {
+    g.force_out[p] = f0;
+    g.force_out[N + p] = f1;
+    g.force_out[2 * N + p] = f2;
+    return;
+  }
+  float l[3], d[3];
+  if (MODE == 0) {
+    const double* t0 = g.table + g.slice0;
+    const double* t1 = g.table + g.slice1;
+    const float c1 = (float)t0[2], c2 = (float)t0[5];
+    const float e1 = (float)(t1[0] - t0[0]), e2 = (float)(t1[3] - t0[3]);
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float s1 = g.psi1[a * N + p], s2 = g.psi2[a * N + p];
+      l[a] = c1 * s1 + c2 * s2;
+      d[a] = e1 * s1 + e2 * s2;
+    }
+  } else {
+    const int ip = (int)p;
+    const int64_t q = ((int64_t)(ip / (np * np)) * np + (ip / np) % np) * ppitch + ip % np;
+    l[0] = g.l0[q]; l[1] = g.l1[q]; l[2] = g.l2[q];
+    d[0] = g.d0[q]; d[1] = g.d1[q]; d[2] = g.d2[q];
+  }
+  const float fv[3] = {f0, f1, f2};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float v = g.vel[a * N + p] + g.dtk * (fv[a] - l[a]);
+    g.vel[a * N + p] = v;
+    g.disp[a * N + p] = g.disp[a * N + p] + (g.dtd * v + d[a]);
+  }
+}
+
+void launch_gather(const Layout& L, const GatherArgs& a, hipStream_t s) {
+  GatherDev g;
+  g.F0 = a.F[0]; g.F1 = a.F[1]; g.F2 = a.F[2];
+  g.disp = a.disp; g.vel = a.vel;
+  g.psi1 = a.psi1; g.psi2 = a.psi2;
+  g.l0 = a.lpp[0]; g.l1 = a.lpp[1]; g.l2 = a.lpp[2];
+  g.d0 = a.dlt[0]; g.d1 = a.dlt[1]; g.d2 = a.dlt[2];
+  g.table = a.table; g.slice0 = a.slice0; g.slice1 = a.slice1;
+  g.dtk = (float)a.dtk; g.dtd = (float)a.dtd;
+  g.force_out = a.force_out;
+  const int ratio = L.nm / L.np;
+  const dim3 grid((unsigned)((L.N + 255) / 256)), block(256);
+  if (a.force_out) {
+    ProfScope ps("gather_force", s);
+    hipLaunchKernelGGL(k_gather<2>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
+                       2 * L.pitch_m, 2 * L.pitch_p);
+  } else if (a.psi1) {
+    ProfScope ps("gather_kick_drift", s);
+    hipLaunchKernelGGL(k_gather<0>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
+                       2 * L.pitch_m, 2 * L.pitch_p);
+  } else {
+    ProfScope ps("gather_kick_drift", s);
+    hipLaunchKernelGGL(k_gather<1>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
+                       2 * L.pitch_m, 2 * L.pitch_p);
+  }
+  COLA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ stand-alone k-space op
+template <int KIND>
+__global__ void __launch_bounds__(256) k_kspace(KOp op, float2* __restrict__ out, int64_t total) {
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int iz = (int)(e % op.pitch);
+    const int64_t r = e / op.pitch;
+    const int iy = (int)(r % op.n);
+    const int ix = (int)(r / op.n);
+    out[e] = kspace_eval<KIND>(op, ix, iy, iz, e);
+  }
+}
+
+void launch_kspace(int kind, const KOp& op, float2* out, hipStream_t s) {
+  ProfScope ps("kspace", s);
+  const int64_t total = (int64_t)op.n * op.n * op.pitch;
+  const dim3 g(grid_for(total, 256)), b(256);
+  switch (kind) {
+    case K_COPY: hipLaunchKernelGGL(k_kspace<K_COPY>, g, b, 0, s, op, out, total); break;
+    case K_POT: hipLaunchKernelGGL(k_kspace<K_POT>, g, b, 0, s, op, out, total); break;
+    case K_SMOOTH: hipLaunchKernelGGL(k_kspace<K_SMOOTH>, g, b, 0, s, op, out, total); break;
+    case K_FORCE: hipLaunchKernelGGL(k_kspace<K_FORCE>, g, b, 0, s, op, out, total); break;
+    default: throw Error{COLA_E_ARG, "unsupported stand-alone k-space operator"};
+  }
+  COLA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ 2LPT source pieces
+// d0 <- d0 d1 + d0 d2 + d1 d2 ;  acc <- acc - d^2   (S = sum_{i<j} phi_ii phi_jj - phi_ij^2)
+__global__ void k_2lpt_diag(float* __restrict__ d0, const float* __restrict__ d1,
+                            const float* __restrict__ d2, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float a = d0[i], b = d1[i], c = d2[i];
+    d0[i] = a * b + a * c + b * c;
+  }
+}
+__global__ void k_2lpt_sub(float* __restrict__ acc, const float* __restrict__ d, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    const float x = d[i];
+    acc[i] -= x * x;
+  }
+}
+void launch_2lpt_diag(float* d0, const float* d1, const float* d2, size_t n, hipStream_t s) {
+  ProfScope ps("2lpt_source", s);
+  hipLaunchKernelGGL(k_2lpt_diag, dim3(grid_for(n, 256)), dim3(256), 0, s, d0, d1, d2, (int64_t)n);
+  COLA_LAUNCH_CHECK();
+}
+void launch_2lpt_sub(float* acc, const float* d, size_t n, hipStream_t s) {
+  ProfScope ps("2lpt_source", s);
+  hipLaunchKernelGGL(k_2lpt_sub, dim3(grid_for(n, 256)), dim3(256), 0, s, acc, d, (int64_t)n);
+  COLA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ layout copies
+__global__ void k_unpad3(const float* __restrict__ a0, const float* __restrict__ a1,
+                         const float* __restrict__ a2, const float* __restrict__ b0,
+                         const float* __restrict__ b1, const float* __restrict__ b2, float alpha,
+                         float beta, float* __restrict__ out, int64_t N, int np, int ppitch) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int ip = (int)p;
+    const int64_t q = ((int64_t)(ip / (np * np)) * np + (ip / np) % np) * ppitch + ip % np;
+    float x = alpha * a0[q], y = alpha * a1[q], z = alpha * a2[q];
+    if (b0) {
+      x += beta * b0[q];
+      y += beta * b1[q];
+      z += beta * b2[q];
+    }
+    out[p] = x;
+    out[N + p] = y;
+    out[2 * N + p] = z;
+  }
+}
+
+void launch_unpad3(const Layout& L, const float* const f0[3], const float* const f1[3], float alpha,
+                   float beta, float* out, hipStream_t s) {
+  ProfScope ps("unpad", s);
+  hipLaunchKernelGGL(k_unpad3, dim3(grid_for(L.N, 256)), dim3(256), 0, s, f0[0], f0[1], f0[2],
+                     f1 ? f1[0] : nullptr, f1 ? f1[1] : nullptr, f1 ? f1[2] : nullptr, alpha, beta,
+                     out, L.N, L.np, 2 * L.pitch_p);
+  COLA_LAUNCH_CHECK();
+}
+
+// u = D1(a_0) Psi1 + D2(a_0) Psi2 with the growth factors read from table slice 0
+__global__ void k_combine_u0(const float* __restrict__ psi1, const float* __restrict__ psi2,
+                             const double* __restrict__ t0, float* __restrict__ disp, int64_t n3) {
+  const float c1 = (float)t0[0], c2 = (float)t0[3];
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < n3;
+       i += (int64_t)gridDim.x * blockDim.x)
+    disp[i] = c1 * psi1[i] + c2 * psi2[i];
+}
+
+void launch_combine_u0(const Layout& L, const float* psi1, const float* psi2, const double* table,
+                       float* disp, hipStream_t s) {
+  ProfScope ps("combine_u0", s);
+  hipLaunchKernelGGL(k_combine_u0, dim3(grid_for(3 * L.N, 256)), dim3(256), 0, s, psi1, psi2, table,
+                     disp, 3 * L.N);
+  COLA_LAUNCH_CHECK();
+}
+
+__global__ void k_unpad_mesh(const float* __restrict__ in, float* __restrict__ out, int n,
+                             int rpitch, float sub) {
+  const int64_t total = (int64_t)n * n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n;
+    out[e] = in[r * rpitch + (e - r * n)] - sub;
+  }
+}
+
+void launch_unpad_mesh(const Layout& L, const float* padded, float* flat, hipStream_t s, float sub) {
+  ProfScope ps("unpad_mesh", s);
+  hipLaunchKernelGGL(k_unpad_mesh, dim3(grid_for(L.M, 256)), dim3(256), 0, s, padded, flat, L.nm,
+                     2 * L.pitch_m, sub);
+  COLA_LAUNCH_CHECK();
+}
+
+// x = (q + u) mod L
+__global__ void k_positions(const float* __restrict__ disp, float* __restrict__ xyz, int64_t N,
+                            int np, int nm, int ratio, float inv_cell, float cell) {
+  for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
+       p += (int64_t)gridDim.x * blockDim.x) {
+    const int ip = (int)p;
+    const int ix[3] = {ip / (np * np), (ip / np) % np, ip % np};
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      const float f = 0.5f + disp[a * N + p] * inv_cell;
+      const float fl = floorf(f);
+      int i = (ix[a] * ratio + (int)fl) % nm;
+      if (i < 0) i += nm;
+      xyz[a * N + p] = ((float)i + (f - fl)) * cell;
+    }
+  }
+}
+
+void launch_positions(const cola_params& p, const Layout& L, const float* disp, float* xyz,
+                      hipStream_t s) {
+  ProfScope ps("positions", s);
+  hipLaunchKernelGGL(k_positions, dim3(grid_for(L.N, 256)), dim3(256), 0, s, disp, xyz, L.N, L.np,
+                     L.nm, L.nm / L.np, L.inv_cell, (float)(p.box / p.nmesh1d));
+  COLA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ power spectrum
+// Bin b = floor(|nu| + 1/2) from the integer |nu|^2: b^2 - b < n2 <= b^2 + b.
+__device__ __forceinline__ int shell_of(int n2) {
+  int b = (int)floorf(sqrtf((float)n2) + 0.5f);
+  if (b > 0 && b * b - b >= n2) --b;
+  if (n2 > b * b + b) ++b;
+  return b;
+}
+
+__device__ __forceinline__ float sincf_pi(float x) {   // sin(pi x)/(pi x)
+  return x == 0.f ? 1.f : sinpif(x) / (3.14159265358979323846f * x);
+}
+
+constexpr int kPkBlocks = 1024;
+constexpr int kPkMaxBins = 2048;
+
+// Per block: LDS shell sums of w, w P and w |k| over a grid-stride share of the modes.
+__global__ void __launch_bounds__(256)
+k_pk_partial(const float2* __restrict__ dk, int n, int pitch, int nbins, float kf, float vol,
+             float* __restrict__ part_p, float* __restrict__ part_k,
+             unsigned* __restrict__ part_w) {
+  __shared__ float sp[kPkMaxBins], sk[kPkMaxBins];
+  __shared__ unsigned sw[kPkMaxBins];
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    sp[b] = 0.f;
+    sk[b] = 0.f;
+    sw[b] = 0u;
+  }
+  __syncthreads();
+  const int h = n / 2;
+  const int64_t total = (int64_t)n * n * (h + 1);
+  const float invM = 1.f / ((float)n * (float)n * (float)n);
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int iz = (int)(e % (h + 1));
+    const int64_t r = e / (h + 1);
+    const int iy = (int)(r % n), ix = (int)(r / n);
+    const int nx = ix < h ? ix : ix - n, ny = iy < h ? iy : iy - n;
+    const int n2 = nx * nx + ny * ny + iz * iz;
+    if (n2 == 0) continue;
+    const int b = shell_of(n2);
+    if (b >= nbins) continue;
+    const float2 v = dk[r * pitch + iz];
+    const float wx = sincf_pi((float)nx / n), wy = sincf_pi((float)ny / n),
+                wz = sincf_pi((float)iz / n);
+    const float W = wx * wx * wy * wy * wz * wz;
+    const float ar = v.x * invM / W, ai = v.y * invM / W;
+    const unsigned w = (iz > 0 && iz < h) ? 2u : 1u;
+    atomicAdd(&sp[b], (float)w * vol * (ar * ar + ai * ai));
+    atomicAdd(&sk[b], (float)w * kf * sqrtf((float)n2));
+    atomicAdd(&sw[b], w);
+  }
+  __syncthreads();
+  for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
+    part_p[(int64_t)blockIdx.x * nbins + b] = sp[b];
+    part_k[(int64_t)blockIdx.x * nbins + b] = sk[b];
+    part_w[(int64_t)blockIdx.x * nbins + b] = sw[b];
+  }
+}
+
+// Cross-block reduction per bin with Neumaier-compensated float sums.
+__global__ void k_pk_final(const float* __restrict__ part_p, const float* __restrict__ part_k,
+                           const unsigned* __restrict__ part_w, int nblk, int nbins,
+                           float4* __restrict__ out, unsigned long long* __restrict__ counts) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= nbins) return;
+  float sp = 0.f, cp = 0.f, sk = 0.f, ck = 0.f;
+  unsigned long long w = 0;
+  for (int i = 0; i < nblk; ++i) {
+    const float xp = part_p[(int64_t)i * nbins + b];
+    float t = sp + xp;
+    cp += (fabsf(sp) >= fabsf(xp)) ? (sp - t) + xp : (xp - t) + sp;
+    sp = t;
+    const float xk = part_k[(int64_t)i * nbins + b];
+    t = sk + xk;
+    ck += (fabsf(sk) >= fabsf(xk)) ? (sk - t) + xk : (xk - t) + sk;
+    sk = t;
+    w += part_w[(int64_t)i * nbins + b];
+  }
+  out[b] = make_float4(sp, cp, sk, ck);
+  counts[b] = w;
+}
+
+size_t pk_scratch_bytes(const Layout&, int nbins) {
+  return align_up((size_t)kPkBlocks * nbins * 3 * sizeof(float));
+}
+
+void launch_pk(const Layout& L, const float2* dk, int nbins, void* scratch, float4* out,
+               unsigned long long* counts, hipStream_t s) {
+  if (nbins > kPkMaxBins) throw Error{COLA_E_ARG, "nbins exceeds 2048"};
+  float* part_p = static_cast<float*>(scratch);
+  float* part_k = part_p + (size_t)kPkBlocks * nbins;
+  unsigned* part_w = reinterpret_cast<unsigned*>(part_k + (size_t)kPkBlocks * nbins);
+  const float kf = (float)(2.0 * M_PI / L.box);
+  const float vol = (float)(L.box * L.box * L.box);
+  {
+    ProfScope ps("pk_bin", s);
+    hipLaunchKernelGGL(k_pk_partial, dim3(kPkBlocks), dim3(256), 0, s, dk, L.nm, L.pitch_m, nbins,
+                       kf, vol, part_p, part_k, part_w);
+    COLA_LAUNCH_CHECK();
+  }
+  ProfScope ps("pk_final", s);
+  hipLaunchKernelGGL(k_pk_final, dim3((nbins + 63) / 64), dim3(64), 0, s, part_p, part_k, part_w,
+                     kPkBlocks, nbins, out, counts);
+  COLA_LAUNCH_CHECK();
+}
+
+}  // namespace cola
