@@ -1,0 +1,210 @@
+"""Benchmark of the COLA particle-mesh step on one MI355X.
+
+Workload: nDGP with r_c H0 = 1 and Vainshtein screening (Gaussian smoothing R = 1 Mpc/h),
+Np = 512^3 particles, Nmesh = 1024^3, L = 1024 Mpc/h, seeded Gaussian initial conditions
+(Eisenstein-Hu no-wiggle spectrum, Om = 0.3, h = 0.7, ns = 0.96, sigma8 = 0.8), 2LPT at
+z = 19, 30 COLA steps to z = 0.
+
+A step is one cola_step: CIC deposit, forward FFT, smoothed-density screening (inverse
+FFT, real-space factor, forward FFT), the fused Green's-function / fifth-force / gradient
+inverse FFTs, and the CIC gather fused with the kick and drift.  The initial conditions
+(growth tables + 2LPT) run before the timed region; the power spectrum after it.
+
+Prints one JSON line.  `value` is particle-steps per second over exactly K timed steps
+(bracketed by device synchronisation); `roofline` reports the kernel with the largest
+share of the step against the MI355X HBM peak, timed with HIP events on its launch
+stream; `cpu_baseline` times the FP64 oracle on host cores on a bounded sample of the
+same workload.
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0
+METRIC = "PM particle-steps/s + % HBM peak; mock runs/hour and p99 time-to-z=0"
+
+
+def workload_params(C):
+    return C.Params(model=C.NDGP, rc_h0=1.0, screening=1, filter=0, r_smooth=1.0,
+                    np1d=512, nmesh1d=1024, box=1024.0, z_init=19.0, n_steps=30, seed=1)
+
+
+def algorithmic_bytes(name, p):
+    """Bytes a kernel must move per launch (single-precision fields, unpadded):
+    mesh M = n^3 real cells, half-complex H = n^2 (n/2 + 1) complex values."""
+    n = p.nmesh1d
+    M = n ** 3
+    H = n * n * (n // 2 + 1)
+    N = p.np1d ** 3
+    table = {
+        "fft_r2c_z": 4 * M + 8 * H,                 # read real mesh, write half-complex
+        "fft_c2r_z": 8 * H + 4 * M,
+        "fft_y_fwd": 16 * H, "fft_x_fwd": 16 * H, "fft_y_inv": 16 * H,
+        "fft_x_inv_smooth": 16 * H,                  # read delta_k, write W delta_k pass
+        "fft_x_inv_force": 24 * H,                   # read delta_k and S_k, write F_k pass
+        "deposit": 12 * N + 4 * M,                   # read u, write the density once
+        "deposit_zero": 4 * M,
+        "screen": 12 * M,                            # read rho and delta_R, write S
+        "gather_kick_drift": 12 * M + 72 * N,        # 3 force meshes; u, v, Psi1, Psi2 in; u, v out
+    }
+    return table.get(name)
+
+
+def yardstick_bytes_per_step(p):
+    """Algorithmic bytes of one screened, scale-independent step with 3-pass FFTs:
+    deposit, 2 forward and 4 inverse FFTs, screening, gather+kick+drift."""
+    names_counts = {"deposit": 1, "deposit_zero": 1, "fft_r2c_z": 2, "fft_c2r_z": 4,
+                    "fft_y_fwd": 2, "fft_x_fwd": 2, "fft_y_inv": 4, "fft_x_inv_smooth": 1,
+                    "fft_x_inv_force": 3, "screen": 1, "gather_kick_drift": 1}
+    return sum(algorithmic_bytes(k, p) * c for k, c in names_counts.items())
+
+
+def source_hash():
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_1703_00879_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        h.update(open(os.path.join(csrc, f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def traffic_for(kernel):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or None if
+    the summary is missing or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", "traffic_ndgp_512_1024.json")
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    k = d.get("kernels", {}).get(kernel)
+    return None if k is None else k.get("bytes_per_launch")
+
+
+def cpu_baseline(steps=3):
+    """The FP64 oracle on the host: the same workload (nDGP r_c H0 = 1, screened,
+    2 Mpc/h particle spacing, 1 Mpc/h cells, 30-step time grid, same seed) on a
+    128^3-particle / 256^3-mesh / 256 Mpc/h sub-box, timing `steps` COLA steps."""
+    import numpy as np  # noqa: F401
+    import oracle
+    from oracle.cola import Run
+    p = oracle.Params(model=oracle.MODEL_NDGP, rc_h0=1.0, screening=1, r_smooth=1.0,
+                      np1d=128, nmesh1d=256, box=256.0, z_init=19.0, n_steps=30, seed=1)
+    r = Run(p)
+    t = time.perf_counter()
+    for _ in range(steps):
+        r.step()
+    dt = time.perf_counter() - t
+    return {"value": p.n_part * steps / dt, "unit": "particle-steps/s", "cores": 1,
+            "kind": "oracle",
+            "sample": f"nDGP rcH0=1 screened, 128^3 particles / 256^3 mesh / L=256 Mpc/h "
+                      f"(same spacing and cell as the workload), {steps} COLA steps of the "
+                      f"30-step grid after 2LPT ICs; numpy FFT and CIC, one thread; "
+                      f"{dt:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=28)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-profile", action="store_true",
+                    help="do not record per-kernel HIP events in the timed region")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(the multi-GPU decomposition is not part of this build)", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_1703_00879_amd import cola as C
+
+    p = workload_params(C)
+    if args.warmup + args.steps > p.n_steps:
+        print(f"warmup + steps must be <= {p.n_steps} (one run to z = 0)", file=sys.stderr)
+        sys.exit(2)
+    torch.cuda.set_device(0)
+    st = C.State(p, device="cuda:0")
+    stream = torch.cuda.current_stream()
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    C.cola_make_ic(p, st)
+    torch.cuda.synchronize()
+    ic_ms = (time.perf_counter() - t0) * 1e3
+    print(f"[bench] initial conditions {ic_ms:.1f} ms", file=sys.stderr, flush=True)
+
+    for i in range(args.warmup):
+        C.cola_step(p, st, i)
+    torch.cuda.synchronize()
+    print(f"[bench] {args.warmup} warmup steps done", file=sys.stderr, flush=True)
+
+    if not args.no_profile:
+        C.cola_profile_reset()
+        C.cola_profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.warmup, args.warmup + args.steps):
+        C.cola_step(p, st, i)
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    C.cola_profile_enable(False)
+    prof = {} if args.no_profile else C.cola_profile_read()
+    print(f"[bench] {args.steps} timed steps: {elapsed:.3f} s", file=sys.stderr, flush=True)
+
+    t0 = time.perf_counter()
+    k, P, nm = C.cola_power_spectrum(p, st)
+    pk_ms = (time.perf_counter() - t0) * 1e3
+    ok = bool(torch.isfinite(st.disp_f).all().item())
+
+    N = p.np1d ** 3
+    value = N * args.steps / elapsed
+    ms_step = elapsed * 1e3 / args.steps
+    kernels = {name: {"ms_per_step": ms / args.steps, "launches_per_step": cnt / args.steps}
+               for name, (ms, cnt) in sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    roofline = None
+    if prof:
+        dom, (dom_ms, dom_cnt) = max(prof.items(), key=lambda kv: kv[1][0])
+        by = algorithmic_bytes(dom, p)
+        avg_s = dom_ms / dom_cnt / 1e3
+        ach = by / avg_s / 1e9 if by else None
+        tr = traffic_for(dom)
+        roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS if ach else None,
+                    "traffic": tr, "avg_launch_ms": avg_s * 1e3,
+                    "algorithmic_bytes_per_launch": by}
+    yard = yardstick_bytes_per_step(p)
+    out = {
+        "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "nDGP rcH0=1 Vainshtein-screened (Gaussian R=1 Mpc/h), "
+                               "Np=512^3, Nmesh=1024^3, L=1024 Mpc/h, 2LPT at z=19, "
+                               "30 COLA steps", "gravity": "nDGP", "np1d": 512,
+                   "nmesh1d": 1024, "box_mpc_h": 1024.0, "n_steps": 30, "seed": 1,
+                   "parallelism": "single GPU"},
+        "roofline": roofline,
+        "hbm_frac_yardstick": yard / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "yardstick_bytes_per_step": yard,
+        "ic_ms": ic_ms, "pk_ms": pk_ms, "finite": ok,
+        "kernels": kernels,
+    }
+    if not args.no_cpu_baseline:
+        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline()
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()
