@@ -113,6 +113,8 @@ struct Bufs {
   float2* phi2;
   float* psi1;
   float* psi2;
+  void* bins;
+  float4* entries;
 };
 
 template <class T>
@@ -145,6 +147,8 @@ static Bufs carve(const cola_params& p, const cola_state* st) {
   b.pk_cnt = reinterpret_cast<unsigned long long*>(b.pk_out + 2048);
   for (int i = 0; i < 5; ++i) b.mesh[i] = at<float2>(st->work, L.off_mesh[i]);
   for (int i = 0; i < 6; ++i) b.pf[i] = L.kdep ? at<float2>(st->work, L.off_pfield[i]) : nullptr;
+  b.bins = at<void>(st->work, L.off_bins);
+  b.entries = at<float4>(st->work, L.off_entries);
   if (L.kdep) {
     b.phi1 = at<float2>(st->lpt, 0);
     b.phi2 = at<float2>(st->lpt, align_up(L.pgrid_elems * sizeof(float2)));
@@ -157,8 +161,8 @@ static Bufs carve(const cola_params& p, const cola_state* st) {
   return b;
 }
 
-static FFTPlan plan_mesh(const Bufs& b) { return FFTPlan{b.L.nm, b.L.pitch_m, b.tw_m}; }
-static FFTPlan plan_part(const Bufs& b) { return FFTPlan{b.L.np, b.L.pitch_p, b.tw_p}; }
+static FFTPlan plan_mesh(const Bufs& b) { return FFTPlan{b.L.nm, b.L.pitch_m, b.L.plane_m, b.tw_m}; }
+static FFTPlan plan_part(const Bufs& b) { return FFTPlan{b.L.np, b.L.pitch_p, b.L.plane_p, b.tw_p}; }
 
 static inline float* R(float2* p) { return reinterpret_cast<float*>(p); }
 
@@ -198,7 +202,7 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
   const StepScalars sc = step_scalars(p, a);
   float2* const* M = b.mesh;
   const float invM = (float)(1.0 / (double)L.M);
-  launch_deposit(L, disp, R(M[0]), s);
+  launch_deposit(L, disp, R(M[0]), b.bins, b.entries, s);
   if (flat_out) launch_unpad_mesh(L, R(M[0]), flat_out, s);
   fft_r2c(pl, R(M[0]), M[1], s);
   const float2* src = nullptr;
@@ -208,33 +212,28 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
     KOp op = base;
     op.a = M[1];
     op.scale = invM;
+    int kind = K_SMOOTH;
     if (p.model == COLA_FR_HS1) {
       op.g_n = -sc.kappa;
-      fft_c2r(pl, K_POT, op, M[2], R(M[2]), s);
+      kind = K_POT;
     } else {
       op.r_smooth = (float)p.r_smooth;
       op.filter = p.filter;
-      fft_c2r(pl, K_SMOOTH, op, M[2], R(M[2]), s);
     }
-    launch_screen(p, L, sc, R(M[0]), R(M[2]), s);
-    if (flat_out) launch_unpad_mesh(L, R(M[2]), flat_out + L.M, s);
-    fft_r2c(pl, R(M[2]), M[2], s);
+    fft_screen(pl, kind, op, M[2], R(M[0]), flat_out ? R(M[3]) : nullptr, p.model, sc.cham_thr,
+               sc.vx_pref, s);
+    if (flat_out) launch_unpad_mesh(L, R(M[3]), flat_out + L.M, s);
     src = M[2];
   } else if (flat_out) {
     launch_unpad_mesh(L, R(M[0]), flat_out + L.M, s, 1.f);   // S = delta = rho - 1
   }
-  float2* outs[3] = {M[0], M[3], M[4]};
-  for (int c = 0; c < 3; ++c) {
-    KOp op = base;
-    op.a = M[1];
-    op.b = src;
-    op.comp = c;
-    op.g_n = -sc.kappa;
-    op.g_5 = sc.fifth ? -sc.coupling * sc.kappa : 0.f;
-    op.a2m2 = sc.a2m2;
-    op.scale = invM;
-    fft_c2r(pl, K_FORCE, op, outs[c], R(outs[c]), s);
-  }
+  KOp op = base;
+  op.g_n = -sc.kappa;
+  op.g_5 = sc.fifth ? -sc.coupling * sc.kappa : 0.f;
+  op.a2m2 = sc.a2m2;
+  op.scale = invM;
+  float2* const outs[3] = {M[0], M[3], M[4]};
+  fft_c2r_force3(pl, op, M[1], src, outs, s);
 }
 
 }  // namespace cola
@@ -298,7 +297,7 @@ cola_status cola_make_ic(const cola_params* p, cola_state* st, hipStream_t s) {
     KOp base;
     base.kf = (float)(2.0 * M_PI / p->box);
     // white noise -> W_k -> phi1_k = delta_k / k^2
-    launch_noise(*p, L.np, L.pitch_p, R(M[0]), nullptr, s);
+    launch_noise(*p, L.np, L.pitch_p, L.plane_p, R(M[0]), nullptr, s);
     fft_r2c(pp, R(M[0]), M[0], s);
     float2* phi1 = L.kdep ? b.phi1 : M[1];
     launch_ic_phi1(*p, L, M[0], phi1, sigma8_norm(*p), b.ref, s);
@@ -331,6 +330,7 @@ cola_status cola_make_ic(const cola_params* p, cola_state* st, hipStream_t s) {
       op.scale = 1.f;
       op.n = L.np;
       op.pitch = L.pitch_p;
+      op.plane = L.plane_p;
       launch_kspace(K_POT, op, phi2, s);   // phi2_k = -S_k / k^2
     }
     float2* outs[3] = {M[0], M[2], M[4]};
@@ -456,7 +456,7 @@ cola_status cola_power_spectrum(const cola_params* p, cola_state* st, int32_t nb
     if (!p || !k_out || !p_out) throw Error{COLA_E_ARG, "NULL argument"};
     const Bufs b = carve(*p, st);
     if (nbins < 1 || nbins > 2048) throw Error{COLA_E_ARG, "nbins must be in [1, 2048]"};
-    launch_deposit(b.L, st->disp, R(b.mesh[0]), s);
+    launch_deposit(b.L, st->disp, R(b.mesh[0]), b.bins, b.entries, s);
     fft_r2c(plan_mesh(b), R(b.mesh[0]), b.mesh[1], s);
     launch_pk(b.L, b.mesh[1], nbins, b.pk_scratch, b.pk_out, b.pk_cnt, s);
     std::vector<float4> o(nbins);
@@ -505,7 +505,7 @@ cola_status cola_white_noise(const cola_params* p, int32_t grid, float* dst, hip
     if (!p || !dst) throw Error{COLA_E_ARG, "NULL argument"};
     validate(*p);
     if (grid != 0) throw Error{COLA_E_UNSUPPORTED, "only the particle grid is supported"};
-    launch_noise(*p, p->np1d, half_pitch(p->np1d), nullptr, dst, s);
+    launch_noise(*p, p->np1d, half_pitch(p->np1d), plane_stride(p->np1d), nullptr, dst, s);
   });
 }
 

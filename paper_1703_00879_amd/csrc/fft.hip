@@ -184,13 +184,81 @@ __device__ __forceinline__ void lds_fft(float2* lds, int tid, int T, const float
   Stages<N, DIR, E, B, LS, TWS, 0, 1>::run(lds, tid, T, tw);
 }
 
+// Stockham transform of B columns whose first stage reads its operands straight from
+// global memory through `load(i, r, j, c)` (operand r of the thread's butterfly i, element
+// j of column c) and whose last stage writes straight to global
+// memory through `store(j, c, v)`; only the middle stages go through LDS.  Each thread
+// issues all of its E loads before it uses any of them, so a work-group keeps its whole
+// tile in flight.
+template <int N, int DIR, int E, int B, int LS, int TWS, int S, int NS>
+struct GStages {
+  template <class Load, class Store>
+  static __device__ __forceinline__ void run(float2* lds, int tid, int T, const float2* tw,
+                                             Load& load, Store& store) {
+    constexpr int nst = Plan<N>::nst;
+    if constexpr (S < nst) {
+      constexpr int R = Plan<N>::rad[S];
+      constexpr int NB = E / R;
+      float2 v[NB][R];
+      if constexpr (S == 0) {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int b = tid + i * T;
+          const int c = b % B, j = b / B;
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[i][r] = load(i, r, j + r * (N / R), c);
+        }
+      } else {
+#pragma unroll
+        for (int i = 0; i < NB; ++i) {
+          const int b = tid + i * T;
+          const int c = b % B, j = b / B;
+#pragma unroll
+          for (int r = 0; r < R; ++r) v[i][r] = lds[(j + r * (N / R)) * LS + c];
+        }
+        if constexpr (S + 1 < nst) __syncthreads();   // all reads before the in-place writes
+      }
+#pragma unroll
+      for (int i = 0; i < NB; ++i) {
+        const int b = tid + i * T;
+        const int c = b % B, j = b / B;
+        const int k = j % NS;
+        if (NS > 1) {
+#pragma unroll
+          for (int r = 1; r < R; ++r) {
+            float2 w = tw[(r * k * (N / (NS * R))) * TWS];
+            if (DIR > 0) w.y = -w.y;
+            v[i][r] = cmul(v[i][r], w);
+          }
+        }
+        Dft<R, DIR>::run(v[i]);
+        const int idxD = (j / NS) * NS * R + k;
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+          if constexpr (S + 1 == nst)
+            store(idxD + r * NS, c, v[i][r]);
+          else
+            lds[(idxD + r * NS) * LS + c] = v[i][r];
+        }
+      }
+      if constexpr (S + 1 < nst) {
+        __syncthreads();
+        GStages<N, DIR, E, B, LS, TWS, S + 1, NS * R>::run(lds, tid, T, tw, load, store);
+      }
+    }
+  }
+};
+
 // ------------------------------------------------------------------ column passes
-// Columns per tile for the strided passes (128 B per element row when B = 16).
+// Columns per tile for the strided passes: at most 64 KB of LDS per work-group, so two
+// work-groups share a CU and one streams its tile while the other computes.
 template <int N>
 struct ColCfg {
   static constexpr int E = Plan<N>::E;
-  static constexpr int B = (N * 16 * 8 <= 131072 && N * 16 / E <= 1024) ? 16 : 8;
+  static constexpr int B0 = 65536 / (8 * N);
+  static constexpr int B = B0 >= 16 ? 16 : (B0 >= 8 ? 8 : 4);
   static constexpr int T = N * B / E;
+  static_assert(T <= 1024, "column tile needs too many threads");
 };
 
 // Strided pass: tile t covers columns [col0, col0 + B) of block t / tilesPerBlock,
@@ -202,29 +270,63 @@ k_fft_col(float2* __restrict__ data, int64_t elemStride, int64_t tilesPerBlock,
   constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
   __shared__ float2 lds[N * B];
   const int tid = threadIdx.x;
-  const int64_t tile = blockIdx.x;
+  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles share an L2
   const int64_t colInBlock = (tile % tilesPerBlock) * B;
   const int64_t base = (tile / tilesPerBlock) * blockStride + colInBlock;
-#pragma unroll 4
-  for (int e = tid; e < N * B; e += T) {
-    const int c = e % B, j = e / B;
+  const float2* src = (KIND == K_COPY && op.a) ? op.a : data;
+  auto load = [&](int, int, int j, int c) -> float2 {
     const int64_t idx = base + j * elemStride + c;
-    float2 v;
     if constexpr (KIND == K_COPY) {
-      v = (op.a ? op.a : data)[idx];
+      return src[idx];
     } else {
       // X pass of an inverse transform: element j is nu_x, column (y, z)
       const int64_t col = colInBlock + c;
-      v = kspace_eval<KIND>(op, j, (int)(col / op.pitch), (int)(col % op.pitch), idx);
+      return kspace_eval<KIND>(op, j, (int)(col / op.pitch), (int)(col % op.pitch), idx);
     }
-    lds[j * B + c] = v;
+  };
+  auto store = [&](int j, int c, float2 v) { data[base + j * elemStride + c] = v; };
+  GStages<N, DIR, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load, store);
+}
+
+// X pass of the three inverse force transforms in one sweep: the Green's function
+// g = [g_n/k^2 delta_k + g_5/(k^2 + a^2 m^2) S_k] / M is formed once per element from one
+// read of delta_k and S_k, kept in registers, and each component -i k_c g is transformed
+// in turn through the same LDS tile and written to its own array.
+template <int N>
+__global__ void __launch_bounds__(ColCfg<N>::T)
+k_fft_col_force3(const float2* __restrict__ dk, const float2* __restrict__ sk,
+                 float2* __restrict__ o0, float2* __restrict__ o1, float2* __restrict__ o2,
+                 int64_t elemStride, const float2* __restrict__ tw, KOp op) {
+  constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
+  constexpr int R0 = Plan<N>::rad[0], NB0 = E / R0;
+  __shared__ float2 lds[N * B];
+  const int tid = threadIdx.x;
+  const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * B;   // X pass: one block
+  float2 g[NB0][R0];
+#pragma unroll
+  for (int i = 0; i < NB0; ++i) {
+    const int b = tid + i * T;
+    const int c = b % B, j = b / B;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int jj = j + r * (N / R0);
+      const int64_t col = base + c;
+      const int iy = (int)(col / op.pitch), iz = (int)(col % op.pitch);
+      const int64_t idx = base + jj * elemStride + c;
+      g[i][r] = green_force(op, jj, iy, iz, dk[idx], sk ? sk[idx] : dk[idx]);
+    }
   }
-  __syncthreads();
-  lds_fft<N, DIR, E, B, B, 1>(lds, tid, T, tw);
-#pragma unroll 4
-  for (int e = tid; e < N * B; e += T) {
-    const int c = e % B, j = e / B;
-    data[base + j * elemStride + c] = lds[j * B + c];
+  float2* outs[3] = {o0, o1, o2};
+#pragma unroll
+  for (int comp = 0; comp < 3; ++comp) {
+    float2* out = outs[comp];
+    auto load = [&](int i, int r, int jj, int c) -> float2 {
+      const int64_t col = base + c;
+      return grad_minus_i(op, jj, (int)(col / op.pitch), (int)(col % op.pitch), comp, g[i][r]);
+    };
+    auto store = [&](int j, int c, float2 v) { out[base + j * elemStride + c] = v; };
+    GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load, store);
+    __syncthreads();   // the next component reuses the LDS tile
   }
 }
 
@@ -234,7 +336,7 @@ constexpr int pow2_floor(int x) { return x >= 2 ? 2 * pow2_floor(x / 2) : 1; }
 template <int NC>
 struct RowCfg {
   static constexpr int E = Plan<NC>::E;
-  static constexpr int B0 = pow2_floor(2048 / NC);
+  static constexpr int B0 = pow2_floor(4096 / NC);
   static constexpr int B = B0 < 1 ? 1 : (B0 > 64 ? 64 : B0);
   static constexpr int T = NC * B / E;
   static constexpr int LS = B + 1;   // odd LDS stride: transposed row loads stay conflict-light
@@ -244,17 +346,29 @@ struct RowCfg {
 // of NC + 1 values (pitch `pitch`).  Twiddles tw[t] = exp(-2 pi i t / n).
 template <int NC>
 __global__ void __launch_bounds__(RowCfg<NC>::T)
-k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nrows, int pitch,
-              const float2* __restrict__ tw) {
+k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nrows, int n,
+              int pitch, int64_t plane, const float2* __restrict__ tw) {
   constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
   __shared__ float2 lds[NC * LS];
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * B;
-  for (int e = tid; e < NC * B; e += T) {
-    const int c = e / NC, m = e % NC;
-    float2 v = make_float2(0.f, 0.f);
-    if (r0 + c < nrows) v = reinterpret_cast<const float2*>(in + (r0 + c) * (int64_t)(2 * pitch))[m];
-    lds[m * LS + c] = v;
+  {
+    float2 v[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = tid + i * T;
+      const int c = e / NC, m = e % NC;
+      v[i] = make_float2(0.f, 0.f);
+      if (r0 + c < nrows) {
+        const int64_t r = r0 + c;
+        v[i] = reinterpret_cast<const float2*>(in + 2 * ((r / n) * plane + (r % n) * pitch))[m];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = tid + i * T;
+      lds[(e % NC) * LS + e / NC] = v[i];
+    }
   }
   __syncthreads();
   lds_fft<NC, -1, E, B, LS, 2>(lds, tid, T, tw);
@@ -268,45 +382,148 @@ k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nr
     const float2 od = make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y - zc.y));
     const float2 w = (k == NC) ? make_float2(-1.f, 0.f) : tw[k];
     const float2 t = cmul(w, od);          // w^k (Z_k - conj Z_{NC-k}) / 2
-    out[(r0 + c) * (int64_t)pitch + k] = make_float2(ev.x + t.y, ev.y - t.x);   // ev - i t
+    const int64_t r = r0 + c;
+    out[(r / n) * plane + (r % n) * pitch + k] = make_float2(ev.x + t.y, ev.y - t.x);   // ev - i t
   }
 }
 
 // Inverse Z pass: half-complex rows (NC + 1 values) -> real rows of n = 2 NC floats,
-// unnormalised.  Z_k = (X_k + conj X_{NC-k}) + i w^{-k} (X_k - conj X_{NC-k}),
-// then z = IDFT_NC(Z) gives (x_even + i x_odd) * n/... (unnormalised length-n inverse).
+// unnormalised.  Z_k = (X_k + conj X_{NC-k}) + i w^{-k} (X_k - conj X_{NC-k}), w = e^{-2 pi i/n};
+// the unnormalised NC-point inverse of Z is (x_{2m} + i x_{2m+1}) with x the unnormalised
+// length-n inverse of X.
 template <int NC>
 __global__ void __launch_bounds__(RowCfg<NC>::T)
-k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nrows, int pitch,
-              const float2* __restrict__ tw) {
+k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nrows, int n,
+              int pitch, int64_t plane, const float2* __restrict__ tw) {
   constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
   __shared__ float2 lds[NC * LS];
-  __shared__ float2 xin[(NC + 1) * B];
   const int tid = threadIdx.x;
   const int64_t r0 = (int64_t)blockIdx.x * B;
-  for (int e = tid; e < (NC + 1) * B; e += T) {
-    const int c = e / (NC + 1), k = e % (NC + 1);
-    float2 v = make_float2(0.f, 0.f);
-    if (r0 + c < nrows) v = in[(r0 + c) * (int64_t)pitch + k];
-    xin[c * (NC + 1) + k] = v;
-  }
-  __syncthreads();
-  for (int e = tid; e < NC * B; e += T) {
+  // X_k and X_{NC-k} come straight from the row (the mirrored read hits the same lines);
+  // all loads are issued before any is used
+  float2 xk[E], xc[E];
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = tid + i * T;
     const int c = e / NC, k = e % NC;
-    const float2 xk = xin[c * (NC + 1) + k];
-    const float2 xc = cconj(xin[c * (NC + 1) + NC - k]);
-    const float2 s = cadd(xk, xc);
-    const float2 d = csub(xk, xc);
+    xk[i] = make_float2(0.f, 0.f);
+    xc[i] = make_float2(0.f, 0.f);
+    if (r0 + c < nrows) {
+      const int64_t r = r0 + c;
+      const float2* row = in + (r / n) * plane + (r % n) * pitch;
+      xk[i] = row[k];
+      xc[i] = cconj(row[NC - k]);
+    }
+  }
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = tid + i * T;
+    const int c = e / NC, k = e % NC;
+    const float2 sm = cadd(xk[i], xc[i]);
+    const float2 d = csub(xk[i], xc[i]);
     const float2 w = cconj(tw[k]);           // exp(+2 pi i k / n)
     const float2 t = cmul(w, d);
-    lds[k * LS + c] = make_float2(s.x - t.y, s.y + t.x);   // s + i t
+    lds[k * LS + c] = make_float2(sm.x - t.y, sm.y + t.x);   // sm + i t
   }
   __syncthreads();
   lds_fft<NC, +1, E, B, LS, 2>(lds, tid, T, tw);
   for (int e = tid; e < NC * B; e += T) {
     const int c = e / NC, m = e % NC;
     if (r0 + c >= nrows) continue;
-    reinterpret_cast<float2*>(out + (r0 + c) * (int64_t)(2 * pitch))[m] = lds[m * LS + c];
+    const int64_t r = r0 + c;
+    reinterpret_cast<float2*>(out + 2 * ((r / n) * plane + (r % n) * pitch))[m] = lds[m * LS + c];
+  }
+}
+
+// Screening in one row pass (Sec. 6): inverse Z transform of the filtered field (the
+// smoothed density contrast for nDGP, the Newtonian potential for f(R)), the real-space
+// screening factor eps and the source S = delta eps, and the forward Z transform of S --
+// the filtered field and S never reach HBM in real space.  S may also be written out in
+// real space (s_out) for diagnostics.
+template <int NC, int MODEL>
+__global__ void __launch_bounds__(RowCfg<NC>::T)
+k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float* __restrict__ s_out,
+                 int64_t nrows, int n, int pitch, int64_t plane, const float2* __restrict__ tw,
+                 float thr, float vx) {
+  constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
+  __shared__ float2 lds[NC * LS];
+  const int tid = threadIdx.x;
+  const int64_t r0 = (int64_t)blockIdx.x * B;
+  {
+    float2 xk[E], xc[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = tid + i * T;
+      const int c = e / NC, k = e % NC;
+      xk[i] = make_float2(0.f, 0.f);
+      xc[i] = make_float2(0.f, 0.f);
+      if (r0 + c < nrows) {
+        const int64_t r = r0 + c;
+        const float2* row = data + (r / n) * plane + (r % n) * pitch;
+        xk[i] = row[k];
+        xc[i] = cconj(row[NC - k]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = tid + i * T;
+      const int c = e / NC, k = e % NC;
+      const float2 sm = cadd(xk[i], xc[i]);
+      const float2 d = csub(xk[i], xc[i]);
+      const float2 t = cmul(cconj(tw[k]), d);
+      lds[k * LS + c] = make_float2(sm.x - t.y, sm.y + t.x);
+    }
+  }
+  __syncthreads();
+  lds_fft<NC, +1, E, B, LS, 2>(lds, tid, T, tw);
+  // S = (rho - 1) eps(field) on the pair (x_2m, x_2m+1) held by element m
+  {
+    float2 rv[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = tid + i * T;
+      const int c = e / NC, m = e % NC;
+      rv[i] = make_float2(1.f, 1.f);
+      if (r0 + c < nrows) {
+        const int64_t r = r0 + c;
+        rv[i] = reinterpret_cast<const float2*>(rho + 2 * ((r / n) * plane + (r % n) * pitch))[m];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = tid + i * T;
+      const int c = e / NC, m = e % NC;
+      const float2 f = lds[m * LS + c];
+      float2 sv;
+      if (MODEL == COLA_FR_HS1) {
+        const float a0 = fabsf(f.x), a1 = fabsf(f.y);
+        sv = make_float2((rv[i].x - 1.f) * (a0 > thr ? thr / a0 : 1.f),
+                         (rv[i].y - 1.f) * (a1 > thr ? thr / a1 : 1.f));
+      } else {
+        const float x0 = vx * fmaxf(0.f, 1.f + f.x), x1 = vx * fmaxf(0.f, 1.f + f.y);
+        sv = make_float2((rv[i].x - 1.f) * (2.f / (1.f + sqrtf(1.f + x0))),
+                         (rv[i].y - 1.f) * (2.f / (1.f + sqrtf(1.f + x1))));
+      }
+      lds[m * LS + c] = sv;
+      if (s_out && r0 + c < nrows) {
+        const int64_t r = r0 + c;
+        reinterpret_cast<float2*>(s_out + 2 * ((r / n) * plane + (r % n) * pitch))[m] = sv;
+      }
+    }
+  }
+  __syncthreads();
+  lds_fft<NC, -1, E, B, LS, 2>(lds, tid, T, tw);
+  for (int e = tid; e < (NC + 1) * B; e += T) {
+    const int c = e / (NC + 1), k = e % (NC + 1);
+    if (r0 + c >= nrows) continue;
+    const float2 zk = lds[(k == NC ? 0 : k) * LS + c];
+    const float2 zc = cconj(lds[(k == 0 ? 0 : NC - k) * LS + c]);
+    const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+    const float2 od = make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y - zc.y));
+    const float2 w = (k == NC) ? make_float2(-1.f, 0.f) : tw[k];
+    const float2 t = cmul(w, od);
+    const int64_t r = r0 + c;
+    data[(r / n) * plane + (r % n) * pitch + k] = make_float2(ev.x + t.y, ev.y - t.x);
   }
 }
 
@@ -339,16 +556,16 @@ static void r2c_impl(const FFTPlan& pl, const float* in, float2* out, hipStream_
     ProfScope ps("fft_r2c_z", s);
     constexpr int B = RowCfg<N / 2>::B;
     hipLaunchKernelGGL((k_fft_r2c_row<N / 2>), dim3((unsigned)((rows + B - 1) / B)),
-                       dim3(RowCfg<N / 2>::T), 0, s, in, out, rows, P, pl.tw);
+                       dim3(RowCfg<N / 2>::T), 0, s, in, out, rows, n, P, pl.plane, pl.tw);
     COLA_LAUNCH_CHECK();
   }
   KOp op;
   constexpr int B = ColCfg<N>::B;
   // Y pass: per x-plane, tiles of B z-columns, element stride = pitch
-  col_pass<N, -1, K_COPY>(out, P, (int64_t)n * (P / B), P / B, (int64_t)n * P, pl.tw, op, s,
+  col_pass<N, -1, K_COPY>(out, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, op, s,
                           "fft_y_fwd");
-  // X pass: tiles of B (y, z) columns, element stride = n * pitch
-  col_pass<N, -1, K_COPY>(out, (int64_t)n * P, (int64_t)n * P / B, (int64_t)n * P / B, 0, pl.tw, op,
+  // X pass: tiles of B (y, z) columns, element stride = plane
+  col_pass<N, -1, K_COPY>(out, pl.plane, (int64_t)n * P / B, (int64_t)n * P / B, 0, pl.tw, op,
                           s, "fft_x_fwd");
 }
 
@@ -361,25 +578,27 @@ static void c2r_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* data
   KOp op = op_in;
   op.n = n;
   op.pitch = P;
+  op.plane = pl.plane;
   const int64_t xtiles = (int64_t)n * P / B;
+  const int64_t ES = pl.plane;
   switch (kind) {
-    case K_COPY: col_pass<N, 1, K_COPY>(data, (int64_t)n * P, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv"); break;
-    case K_FORCE: col_pass<N, 1, K_FORCE>(data, (int64_t)n * P, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_force"); break;
-    case K_POT: col_pass<N, 1, K_POT>(data, (int64_t)n * P, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_pot"); break;
-    case K_SMOOTH: col_pass<N, 1, K_SMOOTH>(data, (int64_t)n * P, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_smooth"); break;
-    case K_LPT: col_pass<N, 1, K_LPT>(data, (int64_t)n * P, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_lpt"); break;
-    case K_HESS: col_pass<N, 1, K_HESS>(data, (int64_t)n * P, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_hess"); break;
-    case K_GRAD: col_pass<N, 1, K_GRAD>(data, (int64_t)n * P, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_grad"); break;
+    case K_COPY: col_pass<N, 1, K_COPY>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv"); break;
+    case K_FORCE: col_pass<N, 1, K_FORCE>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_force"); break;
+    case K_POT: col_pass<N, 1, K_POT>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_pot"); break;
+    case K_SMOOTH: col_pass<N, 1, K_SMOOTH>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_smooth"); break;
+    case K_LPT: col_pass<N, 1, K_LPT>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_lpt"); break;
+    case K_HESS: col_pass<N, 1, K_HESS>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_hess"); break;
+    case K_GRAD: col_pass<N, 1, K_GRAD>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_grad"); break;
     default: throw Error{COLA_E_ARG, "unknown k-space operator"};
   }
   KOp none;
-  col_pass<N, 1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, (int64_t)n * P, pl.tw, none, s,
+  col_pass<N, 1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s,
                          "fft_y_inv");
   {
     ProfScope ps("fft_c2r_z", s);
     constexpr int BR = RowCfg<N / 2>::B;
     hipLaunchKernelGGL((k_fft_c2r_row<N / 2>), dim3((unsigned)((rows + BR - 1) / BR)),
-                       dim3(RowCfg<N / 2>::T), 0, s, data, out, rows, P, pl.tw);
+                       dim3(RowCfg<N / 2>::T), 0, s, data, out, rows, n, P, pl.plane, pl.tw);
     COLA_LAUNCH_CHECK();
   }
 }
@@ -397,6 +616,90 @@ void fft_r2c(const FFTPlan& pl, const float* in, float2* out, hipStream_t s) {
 void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* out, hipStream_t s) {
   switch (pl.n) {
 #define CASE(N_) case N_: c2r_impl<N_>(pl, kind, op, data, out, s); return;
+    CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
+    CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
+#undef CASE
+    default: throw Error{COLA_E_UNSUPPORTED, "FFT size not supported"};
+  }
+}
+
+template <int N>
+static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, const float2* sk,
+                        float2* const out[3], hipStream_t s) {
+  const int n = pl.n, P = pl.pitch;
+  const int64_t rows = (int64_t)n * n;
+  constexpr int B = ColCfg<N>::B;
+  KOp op = op_in;
+  op.n = n;
+  op.pitch = P;
+  op.plane = pl.plane;
+  {
+    ProfScope ps("fft_x_inv_force3", s);
+    hipLaunchKernelGGL((k_fft_col_force3<N>), dim3((unsigned)((int64_t)n * P / B)), dim3(ColCfg<N>::T),
+                       0, s, dk, sk, out[0], out[1], out[2], pl.plane, pl.tw, op);
+    COLA_LAUNCH_CHECK();
+  }
+  KOp none;
+  for (int c = 0; c < 3; ++c) {
+    col_pass<N, 1, K_COPY>(out[c], P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s,
+                           "fft_y_inv");
+    ProfScope ps("fft_c2r_z", s);
+    constexpr int BR = RowCfg<N / 2>::B;
+    hipLaunchKernelGGL((k_fft_c2r_row<N / 2>), dim3((unsigned)((rows + BR - 1) / BR)),
+                       dim3(RowCfg<N / 2>::T), 0, s, out[c], reinterpret_cast<float*>(out[c]), rows, n,
+                       P, pl.plane, pl.tw);
+    COLA_LAUNCH_CHECK();
+  }
+}
+
+template <int N>
+static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* data, const float* rho,
+                        float* s_out, int model, float thr, float vx, hipStream_t s) {
+  const int n = pl.n, P = pl.pitch;
+  const int64_t rows = (int64_t)n * n;
+  constexpr int B = ColCfg<N>::B;
+  KOp op = op_in;
+  op.n = n;
+  op.pitch = P;
+  op.plane = pl.plane;
+  const int64_t xtiles = (int64_t)n * P / B;
+  if (kind == K_POT)
+    col_pass<N, 1, K_POT>(data, pl.plane, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_pot");
+  else
+    col_pass<N, 1, K_SMOOTH>(data, pl.plane, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_smooth");
+  KOp none;
+  col_pass<N, 1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s, "fft_y_inv");
+  {
+    ProfScope ps("fft_z_screen", s);
+    constexpr int BR = RowCfg<N / 2>::B;
+    const dim3 g((unsigned)((rows + BR - 1) / BR)), b(RowCfg<N / 2>::T);
+    if (model == COLA_FR_HS1)
+      hipLaunchKernelGGL((k_fft_screen_row<N / 2, COLA_FR_HS1>), g, b, 0, s, data, rho, s_out, rows, n,
+                         P, pl.plane, pl.tw, thr, vx);
+    else
+      hipLaunchKernelGGL((k_fft_screen_row<N / 2, COLA_NDGP>), g, b, 0, s, data, rho, s_out, rows, n, P,
+                         pl.plane, pl.tw, thr, vx);
+    COLA_LAUNCH_CHECK();
+  }
+  col_pass<N, -1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s, "fft_y_fwd");
+  col_pass<N, -1, K_COPY>(data, pl.plane, xtiles, xtiles, 0, pl.tw, none, s, "fft_x_fwd");
+}
+
+void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* sk,
+                    float2* const out[3], hipStream_t s) {
+  switch (pl.n) {
+#define CASE(N_) case N_: force3_impl<N_>(pl, op, dk, sk, out, s); return;
+    CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
+    CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
+#undef CASE
+    default: throw Error{COLA_E_UNSUPPORTED, "FFT size not supported"};
+  }
+}
+
+void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* data, const float* rho,
+                float* s_out, int model, float thr, float vx, hipStream_t s) {
+  switch (pl.n) {
+#define CASE(N_) case N_: screen_impl<N_>(pl, kind, op, data, rho, s_out, model, thr, vx, s); return;
     CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
     CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
 #undef CASE

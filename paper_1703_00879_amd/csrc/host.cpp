@@ -180,8 +180,10 @@ Layout make_layout(const cola_params& p) {
   L.M = (int64_t)L.nm * L.nm * L.nm;
   L.pitch_p = half_pitch(L.np);
   L.pitch_m = half_pitch(L.nm);
-  L.pgrid_elems = (size_t)L.np * L.np * L.pitch_p;
-  L.mesh_elems = (size_t)L.nm * L.nm * L.pitch_m;
+  L.plane_p = plane_stride(L.np);
+  L.plane_m = plane_stride(L.nm);
+  L.pgrid_elems = (size_t)L.np * L.plane_p;
+  L.mesh_elems = (size_t)L.nm * L.plane_m;
   L.kdep = (p.model == COLA_FR_HS1 && p.growth_mode == 0);
   L.n_k = L.kdep ? 3 * (int64_t)(L.np / 2) * (L.np / 2) + 1 : 1;
   L.n_steps = p.n_steps;
@@ -209,6 +211,13 @@ Layout make_layout(const cola_params& p) {
     L.off_pfield[i] = o;
     if (L.kdep) o += pfield_bytes;
   }
+  L.tile = (L.nm % 16 == 0 && L.nm / 16 >= 2) ? 16 : (L.nm % 8 == 0 && L.nm / 8 >= 2) ? 8 : 4;
+  L.nt1 = L.nm / L.tile;
+  L.ntiles = (int64_t)L.nt1 * L.nt1 * L.nt1;
+  L.off_bins = o;
+  o += bins_bytes(L.ntiles);
+  L.off_entries = o;
+  o += align_up((size_t)L.N * sizeof(float4));
   L.work_bytes = o;
   L.disp_bytes = align_up((size_t)3 * L.N * sizeof(float));
   L.lpt_bytes = L.kdep ? 2 * pfield_bytes : 2 * L.disp_bytes;

@@ -166,7 +166,7 @@ __device__ __forceinline__ float unit_open(uint64_t z) {   // ((z >> 11) + 1/2) 
   return ((float)(z >> 11) + 0.5f) * 0x1p-53f;
 }
 
-__global__ void k_noise(uint64_t seed, int n, int rpitch, float* __restrict__ padded,
+__global__ void k_noise(uint64_t seed, int n, int rpitch, int64_t rplane, float* __restrict__ padded,
                         float* __restrict__ flat) {
   const int64_t total = (int64_t)n * n * n;
   for (int64_t j = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; j < total;
@@ -176,17 +176,19 @@ __global__ void k_noise(uint64_t seed, int n, int rpitch, float* __restrict__ pa
     const float g = sqrtf(-2.f * logf(u0)) * cospif(2.f * u1);
     if (padded) {
       const int64_t r = j / n;
-      padded[r * rpitch + (j - r * n)] = g;
+      padded[(r / n) * rplane + (r % n) * rpitch + (j - r * n)] = g;
     }
     if (flat) flat[j] = g;
   }
 }
 
-void launch_noise(const cola_params& p, int n, int pitch, float* padded, float* flat, hipStream_t s) {
+void launch_noise(const cola_params& p, int n, int pitch, int64_t plane, float* padded, float* flat,
+                  hipStream_t s) {
   ProfScope ps("noise", s);
   const int64_t total = (int64_t)n * n * n;
   const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
-  hipLaunchKernelGGL(k_noise, dim3(g), dim3(256), 0, s, p.seed, n, 2 * pitch, padded, flat);
+  hipLaunchKernelGGL(k_noise, dim3(g), dim3(256), 0, s, p.seed, n, 2 * pitch, 2 * plane, padded,
+                     flat);
   COLA_LAUNCH_CHECK();
 }
 
@@ -208,7 +210,8 @@ __device__ __forceinline__ float eh_T(const EHDev& e, float k) {
 
 // phi1_k = W_k sqrt(N P_ini(k) / L^3) / k^2 ; zero at k = 0 and in row padding
 __global__ void k_ic_phi1(const float2* __restrict__ wk, float2* __restrict__ phi1, int n, int pitch,
-                          float kf, float norm, EHDev eh, const double* __restrict__ ref) {
+                          int64_t plane, float kf, float norm, EHDev eh,
+                          const double* __restrict__ ref) {
   const float d1 = (float)ref[0];
   const float inv_d1sq = 1.f / (d1 * d1);
   const int h = n / 2;
@@ -220,6 +223,7 @@ __global__ void k_ic_phi1(const float2* __restrict__ wk, float2* __restrict__ ph
     const int iy = (int)(r % n), ix = (int)(r / n);
     const int nx = ix < h ? ix : ix - n, ny = iy < h ? iy : iy - n;
     const int n2 = nx * nx + ny * ny + iz * iz;
+    const int64_t idx = ix * plane + (int64_t)iy * pitch + iz;
     float2 out = make_float2(0.f, 0.f);
     if (iz <= h && n2 > 0) {
       const float k2 = kf * kf * (float)n2;
@@ -227,10 +231,10 @@ __global__ void k_ic_phi1(const float2* __restrict__ wk, float2* __restrict__ ph
       const float T = eh_T(eh, k);
       const float P = eh.A * powf(k, eh.ns) * T * T * inv_d1sq;
       const float amp = sqrtf(norm * P) / k2;
-      const float2 w = wk[e];
+      const float2 w = wk[idx];
       out = make_float2(amp * w.x, amp * w.y);
     }
-    phi1[e] = out;
+    phi1[idx] = out;
   }
 }
 
@@ -252,7 +256,7 @@ void launch_ic_phi1(const cola_params& p, const Layout& L, const float2* wk, flo
   const float norm = (float)(N / (p.box * p.box * p.box));
   const int64_t total = (int64_t)L.np * L.np * L.pitch_p;
   const unsigned g = (unsigned)std::min<int64_t>((total + 255) / 256, 1 << 20);
-  hipLaunchKernelGGL(k_ic_phi1, dim3(g), dim3(256), 0, s, wk, phi1, L.np, L.pitch_p,
+  hipLaunchKernelGGL(k_ic_phi1, dim3(g), dim3(256), 0, s, wk, phi1, L.np, L.pitch_p, L.plane_p,
                      (float)(2.0 * M_PI / p.box), norm, e, ref);
   COLA_LAUNCH_CHECK();
 }

@@ -34,6 +34,16 @@ struct ProfScope {
   hipEvent_t a_ = nullptr, b_ = nullptr;
 };
 
+// ------------------------------------------------------------------ XCD-aware block order
+// Work-groups are dispatched round-robin over the 8 XCDs (each with its own L2), so
+// block b runs on XCD b % 8.  xcd_block() renumbers blocks so that each XCD works on one
+// contiguous range of logical blocks: neighbouring tiles or particle chunks, which share
+// cache lines, then meet in the same L2.  It is a bijection on [0, nblocks).
+__device__ __forceinline__ unsigned xcd_block(unsigned b, unsigned nblocks) {
+  const unsigned q = nblocks >> 3, r = nblocks & 7, x = b & 7, l = b >> 3;
+  return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + l;
+}
+
 // ------------------------------------------------------------------ layout
 constexpr size_t kAlign = 256;
 inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a; }
@@ -41,13 +51,19 @@ inline size_t align_up(size_t x, size_t a = kAlign) { return (x + a - 1) / a * a
 // Half-complex row pitch (complex elements): n/2 + 1 rounded up to 16, so every row of
 // a padded real or half-complex mesh starts on a 128-byte boundary.
 inline int half_pitch(int n) { return (n / 2 + 1 + 15) / 16 * 16; }
+// x-plane stride (complex elements): n * pitch plus 16 elements (128 B).  Without the pad
+// the stride of the X pass is 33 * 2^17 bytes at n = 1024, and all 1024 elements of a
+// column sit at addresses congruent modulo 128 KB (same HBM channel); the odd multiple of
+// 128 B spreads them over the channels.
+inline int64_t plane_stride(int n) { return (int64_t)n * half_pitch(n) + 16; }
 
 struct Layout {
   int np, nm;               // particle grid and mesh sizes (per dimension)
   double box;               // L, Mpc/h
   float inv_cell;           // nmesh / L
   int64_t N, M;             // particles, mesh cells
-  int pitch_p, pitch_m;     // half-complex pitches
+  int pitch_p, pitch_m;     // half-complex row pitches
+  int64_t plane_p, plane_m; // half-complex x-plane strides
   size_t pgrid_elems;       // float2 elements of a particle-grid half-complex field
   size_t mesh_elems;        // float2 elements of a PM mesh half-complex field
   bool kdep;                // scale-dependent LPT (k-space store)
@@ -58,6 +74,11 @@ struct Layout {
   size_t scratch_bytes;
   // offsets (bytes) inside `work`
   size_t off_mesh[5], off_pfield[6], work_bytes;
+  // binned deposit: tile edge (cells), tiles per axis, tile count, and the offsets of
+  // the per-tile counters and of the particle-index list sorted by home tile
+  int tile, nt1;
+  int64_t ntiles;
+  size_t off_bins, off_entries;
   size_t lpt_bytes, disp_bytes;
 };
 Layout make_layout(const cola_params& p);
@@ -107,13 +128,15 @@ struct KOp {
   float r_smooth = 0.f;
   int filter = 0;
   int n = 0, pitch = 0;
+  int64_t plane = 0;
   int kdep = 0;                    // growth table indexed by |nu|^2 (else entry 0)
 };
 
 // ------------------------------------------------------------------ FFT
 struct FFTPlan {
   int n = 0;            // transform size per dimension
-  int pitch = 0;        // half-complex pitch
+  int pitch = 0;        // half-complex row pitch
+  int64_t plane = 0;    // half-complex x-plane stride
   const float2* tw = nullptr;   // exp(-2 pi i t / n), t = 0..n-1 (device)
 };
 bool fft_size_supported(int n);
@@ -125,12 +148,24 @@ void fft_r2c(const FFTPlan& pl, const float* in, float2* out, hipStream_t s);
 void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* out,
              hipStream_t s);
 
+// The three force components in one go: an X pass that reads delta_k and S_k once
+// (S_k = delta_k when sk is null) and writes -i k_c [Green's function] into out[c], then
+// per component the Y pass and the real Z pass (in place, real result in out[c]).
+void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* sk,
+                    float2* const out[3], hipStream_t s);
+// Screened source in Fourier space: X pass through `kind` (K_POT: Newtonian potential for
+// f(R); K_SMOOTH: smoothed density for nDGP) reading op.a and writing `data`, inverse Y
+// pass, one row pass doing inverse Z -> S = (rho - 1) eps -> forward Z, then forward Y and
+// X passes: `data` ends holding S_k.  s_out (optional, padded real) receives S.
+void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* data, const float* rho,
+                float* s_out, int model, float thr, float vx, hipStream_t s);
+
 // ------------------------------------------------------------------ kernels (launchers)
 void launch_fill(float* p, size_t n, float v, hipStream_t s);
 void launch_growth_ode(const cola_params& p, const Layout& L, double* table, double* ref,
                        hipStream_t s);
-void launch_noise(const cola_params& p, int n, int pitch, float* dst_padded, float* dst_flat,
-                  hipStream_t s);
+void launch_noise(const cola_params& p, int n, int pitch, int64_t plane, float* dst_padded,
+                  float* dst_flat, hipStream_t s);
 void launch_ic_phi1(const cola_params& p, const Layout& L, const float2* wk, float2* phi1,
                     double A_norm, const double* ref, hipStream_t s);
 void launch_kspace(int kind, const KOp& op, float2* out, hipStream_t s);
@@ -141,7 +176,11 @@ void launch_unpad3(const Layout& L, const float* const f0[3], const float* const
                    float alpha, float beta, float* out, hipStream_t s);
 void launch_combine_u0(const Layout& L, const float* psi1, const float* psi2,
                        const double* table, float* disp, hipStream_t s);
-void launch_deposit(const Layout& L, const float* disp, float* rho_padded, hipStream_t s);
+// CIC deposit into the padded real mesh.  `bins` is the work area at off_bins, `entries`
+// the packed per-particle CIC records sorted by home tile (float4 each).
+void launch_deposit(const Layout& L, const float* disp, float* rho_padded, void* bins,
+                    float4* entries, hipStream_t s);
+size_t bins_bytes(int64_t ntiles);
 void launch_screen(const cola_params& p, const Layout& L, const StepScalars& sc,
                    const float* rho, float* field_inout, hipStream_t s);
 struct GatherArgs {

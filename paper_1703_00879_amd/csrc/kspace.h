@@ -32,20 +32,24 @@ __device__ __forceinline__ float2 kspace_eval(const KOp& op, int ix, int iy, int
   const int ny = iy < h ? iy : iy - n;
   const int nz = iz;
   const int n2 = nx * nx + ny * ny + nz * nz;
-  // component selection without dynamically indexed local arrays (no scratch spills)
-  auto nyq = [&](int c) { return c == 0 ? ix == h : (c == 1 ? iy == h : iz == h); };
-  auto kc = [&](int c) { return op.kf * (float)(c == 0 ? nx : (c == 1 ? ny : nz)); };
+  // component selection by value (no captured or dynamically indexed locals, which the
+  // compiler would otherwise keep in private scratch memory)
+  const int ic = op.comp == 0 ? ix : (op.comp == 1 ? iy : iz);
+  const int jc = op.comp2 == 0 ? ix : (op.comp2 == 1 ? iy : iz);
+  const bool nyq_c = ic == h, nyq_c2 = jc == h;
+  const float k_c = op.kf * (float)(op.comp == 0 ? nx : (op.comp == 1 ? ny : nz));
+  const float k_c2 = op.kf * (float)(op.comp2 == 0 ? nx : (op.comp2 == 1 ? ny : nz));
   if constexpr (KIND == K_COPY) {
     const float2 a = op.a[idx];
     return make_float2(op.scale * a.x, op.scale * a.y);
   } else if constexpr (KIND == K_FORCE) {
-    if (n2 == 0 || nyq(op.comp)) return make_float2(0.f, 0.f);
+    if (n2 == 0 || nyq_c) return make_float2(0.f, 0.f);
     const float k2 = op.kf * op.kf * (float)n2;
     const float2 a = op.a[idx];
     const float2 b = op.b ? op.b[idx] : a;
     const float gn = op.g_n / k2, g5 = op.g_5 / (k2 + op.a2m2);
     const float2 g = make_float2(gn * a.x + g5 * b.x, gn * a.y + g5 * b.y);
-    const float f = kc(op.comp) * op.scale;   // -i k_c g
+    const float f = k_c * op.scale;   // -i k_c g
     return make_float2(f * g.y, -f * g.x);
   } else if constexpr (KIND == K_POT) {
     if (n2 == 0) return make_float2(0.f, 0.f);
@@ -60,7 +64,7 @@ __device__ __forceinline__ float2 kspace_eval(const KOp& op, int ix, int iy, int
     const float2 a = op.a[idx];
     return make_float2(f * a.x, f * a.y);
   } else if constexpr (KIND == K_LPT) {
-    if (n2 == 0 || nyq(op.comp)) return make_float2(0.f, 0.f);
+    if (n2 == 0 || nyq_c) return make_float2(0.f, 0.f);
     const int64_t e = (int64_t)(op.kdep ? n2 : 0) * 6;
     const double* t0 = op.table + op.tab_slice0 + e;
     const double* t1 = op.table + op.tab_slice1 + e;
@@ -78,21 +82,44 @@ __device__ __forceinline__ float2 kspace_eval(const KOp& op, int ix, int iy, int
     const float2 a = op.a[idx];
     const float2 b = op.b[idx];
     const float2 g = make_float2(x1 * a.x + x2 * b.x, x1 * a.y + x2 * b.y);
-    const float f = kc(op.comp) * op.scale;   // +i k_c g
+    const float f = k_c * op.scale;   // +i k_c g
     return make_float2(-f * g.y, f * g.x);
   } else if constexpr (KIND == K_HESS) {
-    if (op.comp != op.comp2 && (nyq(op.comp) || nyq(op.comp2))) return make_float2(0.f, 0.f);
-    const float f = -kc(op.comp) * kc(op.comp2) * op.scale;
+    if (op.comp != op.comp2 && (nyq_c || nyq_c2)) return make_float2(0.f, 0.f);
+    const float f = -k_c * k_c2 * op.scale;
     const float2 a = op.a[idx];
     return make_float2(f * a.x, f * a.y);
   } else if constexpr (KIND == K_GRAD) {
-    if (nyq(op.comp)) return make_float2(0.f, 0.f);
-    const float f = kc(op.comp) * op.scale;
+    if (nyq_c) return make_float2(0.f, 0.f);
+    const float f = k_c * op.scale;
     const float2 a = op.a[idx];
     return make_float2(-f * a.y, f * a.x);
   } else {
     return make_float2(0.f, 0.f);
   }
+}
+
+// Potential part of the force operator: [g_n/k^2 a + g_5/(k^2 + a2m2) b] * scale
+// (zero at k = 0 and in row padding).
+__device__ __forceinline__ float2 green_force(const KOp& op, int ix, int iy, int iz, float2 a, float2 b) {
+  const int n = op.n, h = n >> 1;
+  if (iz > h) return make_float2(0.f, 0.f);
+  const int nx = ix < h ? ix : ix - n, ny = iy < h ? iy : iy - n;
+  const int n2 = nx * nx + ny * ny + iz * iz;
+  if (n2 == 0) return make_float2(0.f, 0.f);
+  const float k2 = op.kf * op.kf * (float)n2;
+  const float gn = op.g_n / k2 * op.scale, g5 = op.g_5 / (k2 + op.a2m2) * op.scale;
+  return make_float2(gn * a.x + g5 * b.x, gn * a.y + g5 * b.y);
+}
+
+// -i k_comp g, zero on the Nyquist plane of axis comp.
+__device__ __forceinline__ float2 grad_minus_i(const KOp& op, int ix, int iy, int iz, int comp, float2 g) {
+  const int n = op.n, h = n >> 1;
+  const int ic = comp == 0 ? ix : (comp == 1 ? iy : iz);
+  if (ic == h) return make_float2(0.f, 0.f);
+  const int nu = comp == 2 ? ic : (ic < h ? ic : ic - n);
+  const float k = op.kf * (float)nu;
+  return make_float2(k * g.y, -k * g.x);
 }
 
 }  // namespace cola

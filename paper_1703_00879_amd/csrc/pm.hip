@@ -62,40 +62,350 @@ void launch_fill(float* p, size_t n, float v, hipStream_t s) {
 
 // ------------------------------------------------------------------ CIC deposit
 // rho_j = sum_p m W(x_p - x_j), m = (nmesh/np)^3 so that rho averages to 1.
+//
+// Device-wide float atomics on a multi-GB mesh resolve beyond the per-XCD L2 caches and
+// run far below HBM bandwidth, so the deposit is a counting sort instead:
+//  1. count: every particle finds its home tile (the T^3-cell tile holding its lower CIC
+//     corner i0) and its class c = bitmask of the axes on which i0 sits on the tile's
+//     last layer (c != 0: some corners spill into the next tile).  Work-groups take
+//     Lagrangian bricks of 4x8x8 particles, which land in few tiles, and aggregate their
+//     counts in an LDS hash table before one global add per (tile, class);
+//  2. scan: exclusive prefix over tiles, then per-class cursors inside each tile;
+//  3. scatter: the same bricks write particle indices into the tile/class segments;
+//  4. deposit: one work-group per tile accumulates in LDS the corners that fall inside it
+//     -- from every particle of its own tile and from the class-c particles of the seven
+//     lower neighbour tiles T - delta with (c & delta) == delta -- and writes the tile
+//     once with plain stores, so the mesh needs no zeroing pass.
+constexpr int kBrickX = 4, kBrickY = 8, kBrickZ = 8;   // 256 particles per work-group
+constexpr int kHash = 512;                              // > 256 distinct keys: never full
+constexpr int kScanBlock = 1024;                        // tiles per scan block
+
+size_t bins_bytes(int64_t ntiles) {
+  const int64_t nblk = (ntiles + kScanBlock - 1) / kScanBlock;
+  return align_up((size_t)(17 * ntiles + 2 * nblk + 64) * sizeof(uint32_t));
+}
+
+struct BinGeo {
+  int np, nm, ratio, nt1, tile;
+  float inv_cell;
+  int64_t N;
+};
+
+// Lower CIC corner (cell) and offset of one axis; the same arithmetic as cic_axis().
+__device__ __forceinline__ int axis_cell(int ixq, float u, const BinGeo& g, float& d) {
+  const float f = 0.5f + u * g.inv_cell;
+  const float fl = floorf(f);
+  d = f - fl;
+  int i = (ixq * g.ratio + (int)fl) % g.nm;
+  return i < 0 ? i + g.nm : i;
+}
+
+__device__ __forceinline__ int lds_slot(int* keys, int key) {
+  unsigned h = ((unsigned)key * 2654435761u) >> (32 - 9);
+  while (true) {
+    const int prev = atomicCAS(&keys[h], -1, key);
+    if (prev == -1 || prev == key) return (int)h;
+    h = (h + 1) & (kHash - 1);
+  }
+}
+
+__device__ __forceinline__ bool brick_particle(const BinGeo& g, int& ix, int& iy, int& iz, int64_t& p) {
+  const int nbz = (g.np + kBrickZ - 1) / kBrickZ, nby = (g.np + kBrickY - 1) / kBrickY;
+  const int b = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int bz = b % nbz, by = (b / nbz) % nby, bx = b / (nbz * nby);
+  const int t = threadIdx.x;
+  ix = bx * kBrickX + (t >> 6);
+  iy = by * kBrickY + ((t >> 3) & 7);
+  iz = bz * kBrickZ + (t & 7);
+  if (ix >= g.np || iy >= g.np || iz >= g.np) return false;
+  p = ((int64_t)ix * g.np + iy) * g.np + iz;
+  return true;
+}
+
+// MODE 0: count into cnt[tile*8 + cls];  MODE 1: scatter the particle's CIC record
+// (dx, dy, dz, lower corner relative to its home tile) to entries[cur[tile*8 + cls]++].
+template <int MODE>
 __global__ void __launch_bounds__(256)
-k_deposit(const float* __restrict__ disp, float* __restrict__ rho, int64_t N, int np, int nm,
-          int ratio, float inv_cell, int rpitch, float mass) {
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
-  if (p >= N) return;
-  CicCell c;
-  cic_cell(p, np, nm, ratio, inv_cell, disp, N, c);
+k_bin(const float* __restrict__ disp, BinGeo g, uint32_t* __restrict__ cnt,
+      uint32_t* __restrict__ cur, float4* __restrict__ entries) {
+  __shared__ int keys[kHash];
+  __shared__ unsigned cls_cnt[kHash][8];
+  for (int i = threadIdx.x; i < kHash; i += blockDim.x) {
+    keys[i] = -1;
 #pragma unroll
-  for (int ox = 0; ox < 2; ++ox) {
-    const int64_t x = ox ? c.i1[0] : c.i0[0];
-    const float wx = mass * (ox ? c.w1[0] : c.w0[0]);
-#pragma unroll
-    for (int oy = 0; oy < 2; ++oy) {
-      const int64_t y = oy ? c.i1[1] : c.i0[1];
-      const float wxy = wx * (oy ? c.w1[1] : c.w0[1]);
-      float* row = rho + (x * nm + y) * rpitch;
-      unsafeAtomicAdd(row + c.i0[2], wxy * c.w0[2]);
-      unsafeAtomicAdd(row + c.i1[2], wxy * c.w1[2]);
+    for (int c = 0; c < 8; ++c) cls_cnt[i][c] = 0u;
+  }
+  __syncthreads();
+  int ix, iy, iz, tile = 0, cls = 0, slot = -1;
+  int64_t p = 0;
+  unsigned rank = 0;
+  float dx = 0.f, dy = 0.f, dz = 0.f;
+  unsigned local = 0;
+  if (brick_particle(g, ix, iy, iz, p)) {
+    const int cx = axis_cell(ix, disp[p], g, dx);
+    const int cy = axis_cell(iy, disp[g.N + p], g, dy);
+    const int cz = axis_cell(iz, disp[2 * g.N + p], g, dz);
+    const int T = g.tile;
+    tile = ((cx / T) * g.nt1 + cy / T) * g.nt1 + cz / T;
+    cls = ((cx % T == T - 1) ? 1 : 0) | ((cy % T == T - 1) ? 2 : 0) | ((cz % T == T - 1) ? 4 : 0);
+    local = (unsigned)(cx % T) | ((unsigned)(cy % T) << 8) | ((unsigned)(cz % T) << 16);
+    slot = lds_slot(keys, tile);
+    rank = atomicAdd(&cls_cnt[slot][cls], 1u);
+  }
+  __syncthreads();
+  // one global add per (tile, class) present in this brick; for the scatter its return
+  // value is the brick's base inside the class segment
+  for (int i = threadIdx.x; i < kHash * 8; i += blockDim.x) {
+    const int s = i >> 3, c = i & 7;
+    const int key = keys[s];
+    if (key < 0) continue;
+    const unsigned n = cls_cnt[s][c];
+    if (n == 0) continue;
+    if (MODE == 0)
+      atomicAdd(&cnt[(int64_t)key * 8 + c], n);
+    else
+      cls_cnt[s][c] = atomicAdd(&cur[(int64_t)key * 8 + c], n);
+  }
+  if (MODE == 1) {
+    __syncthreads();
+    if (slot >= 0)
+      entries[cls_cnt[slot][cls] + rank] = make_float4(dx, dy, dz, __uint_as_float(local));
+  }
+}
+
+// Tile totals -> per-block sums (block of kScanBlock tiles).
+__global__ void __launch_bounds__(256)
+k_scan_reduce(const uint32_t* __restrict__ cnt, uint32_t* __restrict__ bsum, int64_t ntiles) {
+  __shared__ uint32_t red[256];
+  const int64_t t0 = (int64_t)blockIdx.x * kScanBlock;
+  uint32_t s = 0;
+  for (int i = threadIdx.x; i < kScanBlock; i += 256) {
+    const int64_t t = t0 + i;
+    if (t < ntiles) {
+      const uint4* c4 = reinterpret_cast<const uint4*>(cnt + t * 8);
+      const uint4 a = c4[0], b = c4[1];
+      s += a.x + a.y + a.z + a.w + b.x + b.y + b.z + b.w;
+    }
+  }
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int o = 128; o > 0; o >>= 1) {
+    if (threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) bsum[blockIdx.x] = red[0];
+}
+
+// Exclusive scan of the block sums (one work-group; nblk <= 4096 for nmesh <= 2048).
+__global__ void __launch_bounds__(1024) k_scan_top(uint32_t* __restrict__ bsum, int nblk) {
+  __shared__ uint32_t part[1024];
+  const int t = threadIdx.x;
+  const int per = (nblk + 1023) / 1024;
+  uint32_t s = 0;
+  for (int i = 0; i < per; ++i) {
+    const int j = t * per + i;
+    if (j < nblk) s += bsum[j];
+  }
+  part[t] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  uint32_t run = part[t] - s;
+  for (int i = 0; i < per; ++i) {
+    const int j = t * per + i;
+    if (j < nblk) {
+      const uint32_t v = bsum[j];
+      bsum[j] = run;
+      run += v;
     }
   }
 }
 
-void launch_deposit(const Layout& L, const float* disp, float* rho, hipStream_t s) {
+// Per block: scan of tile totals + block offset -> start[tile]; per-class cursors.
+__global__ void __launch_bounds__(kScanBlock)
+k_scan_apply(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ boff,
+             uint32_t* __restrict__ start, uint32_t* __restrict__ cur, int64_t ntiles) {
+  __shared__ uint32_t part[kScanBlock];
+  const int t = threadIdx.x;
+  const int64_t tile = (int64_t)blockIdx.x * kScanBlock + t;
+  uint32_t c[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  if (tile < ntiles) {
+    const uint4* c4 = reinterpret_cast<const uint4*>(cnt + tile * 8);
+    const uint4 a = c4[0], b = c4[1];
+    c[0] = a.x; c[1] = a.y; c[2] = a.z; c[3] = a.w; c[4] = b.x; c[5] = b.y; c[6] = b.z; c[7] = b.w;
+  }
+  const uint32_t tot = c[0] + c[1] + c[2] + c[3] + c[4] + c[5] + c[6] + c[7];
+  part[t] = tot;
+  __syncthreads();
+  for (int off = 1; off < kScanBlock; off <<= 1) {
+    const uint32_t v = t >= off ? part[t - off] : 0u;
+    __syncthreads();
+    part[t] += v;
+    __syncthreads();
+  }
+  if (tile < ntiles) {
+    uint32_t run = boff[blockIdx.x] + part[t] - tot;
+    start[tile] = run;
+    uint32_t cc[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+      cc[k] = run;
+      run += c[k];
+    }
+    uint4* o4 = reinterpret_cast<uint4*>(cur + tile * 8);
+    o4[0] = make_uint4(cc[0], cc[1], cc[2], cc[3]);
+    o4[1] = make_uint4(cc[4], cc[5], cc[6], cc[7]);
+  }
+}
+
+template <int T>
+__global__ void __launch_bounds__(256)
+k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__ start,
+                const uint32_t* __restrict__ cnt, BinGeo g, float* __restrict__ rho, int rpitch,
+                int64_t rplane, float mass) {
+  __shared__ float acc[T * T * T];
+  __shared__ uint32_t seg[8][9];   // per offset d: start of the source tile, 8 class counts
+  const int nt1 = g.nt1;
+  const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
+  const int tx = tile / (nt1 * nt1), ty = (tile / nt1) % nt1, tz = tile % nt1;
+  if (threadIdx.x < 72) {
+    const int d = threadIdx.x / 9, k = threadIdx.x % 9;
+    const int sx = (tx - (d & 1) + nt1) % nt1, sy = (ty - ((d >> 1) & 1) + nt1) % nt1,
+              sz = (tz - ((d >> 2) & 1) + nt1) % nt1;
+    const int64_t src = ((int64_t)sx * nt1 + sy) * nt1 + sz;
+    seg[d][k] = k == 0 ? start[src] : cnt[src * 8 + k - 1];
+  }
+  for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) acc[i] = 0.f;
+  // Flatten the (offset d, class c) segments that reach this tile into one list, so the
+  // entries are read in a single strided sweep (at most 1 + 3*4 + 3*2 + 1 = 20 segments).
+  __shared__ uint32_t sb[24], so[25];
+  __shared__ int sdd[24], nseg;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int k = 0;
+    uint32_t tot = 0;
+    uint32_t n0 = 0;
+    for (int c = 0; c < 8; ++c) n0 += seg[0][c + 1];
+    if (n0) {
+      sb[k] = seg[0][0];
+      so[k] = tot;
+      sdd[k++] = 0;
+      tot += n0;
+    }
+    for (int d = 1; d < 8; ++d) {
+      uint32_t b = seg[d][0];
+      for (int c = 0; c < 8; ++c) {
+        const uint32_t n = seg[d][c + 1];
+        if ((c & d) == d && n) {
+          sb[k] = b;
+          so[k] = tot;
+          sdd[k++] = d;
+          tot += n;
+        }
+        b += n;
+      }
+    }
+    so[k] = tot;
+    nseg = k;
+  }
+  __syncthreads();
+  const uint32_t total = so[nseg];
+  int sg = 0;
+  // batches of KB records per thread: all loads are issued before the LDS accumulation
+  constexpr int KB = 4;
+  for (uint32_t e0 = threadIdx.x; e0 < total; e0 += KB * blockDim.x) {
+    float4 r[KB];
+    int dd[KB];
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const uint32_t e = e0 + k * blockDim.x;
+      dd[k] = -1;
+      r[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      if (e < total) {
+        while (so[sg + 1] <= e) ++sg;
+        dd[k] = sdd[sg];
+        r[k] = entries[sb[sg] + (e - so[sg])];
+      }
+    }
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+      const int d = dd[k];
+      if (d < 0) continue;
+      // the lower corner of a particle of tile T - d lies at (home-tile coordinate - T)
+      // on every axis where d is set
+      const unsigned loc = __float_as_uint(r[k].w);
+      const int lx0 = (int)(loc & 255u) - ((d & 1) ? T : 0);
+      const int ly0 = (int)((loc >> 8) & 255u) - (((d >> 1) & 1) ? T : 0);
+      const int lz0 = (int)((loc >> 16) & 255u) - (((d >> 2) & 1) ? T : 0);
+      const float wx[2] = {1.f - r[k].x, r[k].x}, wy[2] = {1.f - r[k].y, r[k].y},
+                  wz[2] = {1.f - r[k].z, r[k].z};
+#pragma unroll
+      for (int o = 0; o < 8; ++o) {
+        const int lx = lx0 + (o & 1), ly = ly0 + ((o >> 1) & 1), lz = lz0 + ((o >> 2) & 1);
+        if (lx >= 0 && lx < T && ly >= 0 && ly < T && lz >= 0 && lz < T)
+          atomicAdd(&acc[(lx * T + ly) * T + lz],
+                    mass * wx[o & 1] * wy[(o >> 1) & 1] * wz[(o >> 2) & 1]);
+      }
+    }
+  }
+  __syncthreads();
+  const int ox = tx * T, oy = ty * T, oz = tz * T;
+  for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) {
+    const int lx = i / (T * T), ly = (i / T) % T, lz = i % T;
+    rho[(int64_t)(ox + lx) * rplane + (int64_t)(oy + ly) * rpitch + oz + lz] = acc[i];
+  }
+}
+
+void launch_deposit(const Layout& L, const float* disp, float* rho, void* bins, float4* entries,
+                    hipStream_t s) {
+  BinGeo g;
+  g.np = L.np;
+  g.nm = L.nm;
+  g.ratio = L.nm / L.np;
+  g.nt1 = L.nt1;
+  g.tile = L.tile;
+  g.inv_cell = L.inv_cell;
+  g.N = L.N;
+  const int64_t nblk = (L.ntiles + kScanBlock - 1) / kScanBlock;
+  uint32_t* cnt = static_cast<uint32_t*>(bins);
+  uint32_t* cur = cnt + 8 * L.ntiles;
+  uint32_t* start = cur + 8 * L.ntiles;
+  uint32_t* bsum = start + L.ntiles;
+  const unsigned bricks = (unsigned)(((L.np + kBrickX - 1) / kBrickX) *
+                                     ((L.np + kBrickY - 1) / kBrickY) *
+                                     ((L.np + kBrickZ - 1) / kBrickZ));
   {
-    ProfScope ps("deposit_zero", s);
-    const int64_t n = (int64_t)L.mesh_elems * 2;
-    hipLaunchKernelGGL(k_fill, dim3(grid_for(n, 256)), dim3(256), 0, s, rho, n, 0.f);
+    ProfScope ps("bin_count", s);
+    hipLaunchKernelGGL(k_fill, dim3(grid_for(8 * L.ntiles, 256)), dim3(256), 0, s,
+                       reinterpret_cast<float*>(cnt), 8 * L.ntiles, 0.f);
+    hipLaunchKernelGGL(k_bin<0>, dim3(bricks), dim3(256), 0, s, disp, g, cnt, cur, entries);
+    COLA_LAUNCH_CHECK();
+  }
+  {
+    ProfScope ps("bin_scan", s);
+    hipLaunchKernelGGL(k_scan_reduce, dim3((unsigned)nblk), dim3(256), 0, s, cnt, bsum, L.ntiles);
+    hipLaunchKernelGGL(k_scan_top, dim3(1), dim3(1024), 0, s, bsum, (int)nblk);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nblk), dim3(kScanBlock), 0, s, cnt, bsum, start,
+                       cur, L.ntiles);
+    COLA_LAUNCH_CHECK();
+  }
+  {
+    ProfScope ps("bin_scatter", s);
+    hipLaunchKernelGGL(k_bin<1>, dim3(bricks), dim3(256), 0, s, disp, g, cnt, cur, entries);
     COLA_LAUNCH_CHECK();
   }
   ProfScope ps("deposit", s);
-  const int ratio = L.nm / L.np;
-  const float mass = (float)ratio * ratio * ratio;
-  hipLaunchKernelGGL(k_deposit, dim3((unsigned)((L.N + 255) / 256)), dim3(256), 0, s, disp, rho,
-                     L.N, L.np, L.nm, ratio, L.inv_cell, 2 * L.pitch_m, mass);
+  const float mass = (float)g.ratio * g.ratio * g.ratio;
+  const dim3 grid((unsigned)L.ntiles), block(256);
+  switch (L.tile) {
+    case 16: hipLaunchKernelGGL(k_deposit_tiles<16>, grid, block, 0, s, entries, start, cnt, g, rho, 2 * L.pitch_m, 2 * L.plane_m, mass); break;
+    case 8: hipLaunchKernelGGL(k_deposit_tiles<8>, grid, block, 0, s, entries, start, cnt, g, rho, 2 * L.pitch_m, 2 * L.plane_m, mass); break;
+    default: hipLaunchKernelGGL(k_deposit_tiles<4>, grid, block, 0, s, entries, start, cnt, g, rho, 2 * L.pitch_m, 2 * L.plane_m, mass); break;
+  }
   COLA_LAUNCH_CHECK();
 }
 
@@ -106,13 +416,13 @@ void launch_deposit(const Layout& L, const float* disp, float* rho, hipStream_t 
 template <int MODEL>
 __global__ void __launch_bounds__(256)
 k_screen(const float* __restrict__ rho, float* __restrict__ field, int64_t rows, int n,
-         int rpitch, float thr, float vx) {
+         int rpitch, int64_t rplane, float thr, float vx) {
   const int64_t total = rows * n;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / n;
     const int z = (int)(e - r * n);
-    const int64_t i = r * rpitch + z;
+    const int64_t i = (r / n) * rplane + (r % n) * rpitch + z;
     const float delta = rho[i] - 1.f;
     const float g = field[i];
     float eps;
@@ -134,10 +444,10 @@ void launch_screen(const cola_params& p, const Layout& L, const StepScalars& sc,
   const unsigned g = grid_for(rows * L.nm, 256);
   if (p.model == COLA_FR_HS1)
     hipLaunchKernelGGL(k_screen<COLA_FR_HS1>, dim3(g), dim3(256), 0, s, rho, field, rows, L.nm,
-                       2 * L.pitch_m, sc.cham_thr, 0.f);
+                       2 * L.pitch_m, 2 * L.plane_m, sc.cham_thr, 0.f);
   else
     hipLaunchKernelGGL(k_screen<COLA_NDGP>, dim3(g), dim3(256), 0, s, rho, field, rows, L.nm,
-                       2 * L.pitch_m, 0.f, sc.vx_pref);
+                       2 * L.pitch_m, 2 * L.plane_m, 0.f, sc.vx_pref);
   COLA_LAUNCH_CHECK();
 }
 
@@ -161,8 +471,9 @@ struct GatherDev {
 template <int MODE>
 __global__ void __launch_bounds__(256)
 k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int rpitch,
-         int ppitch) {
-  const int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+         int64_t rplane, int ppitch, int64_t pplane) {
+  // consecutive particle chunks read overlapping mesh rows: keep them on one XCD
+  const int64_t p = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   if (p >= N) return;
   CicCell c;
   cic_cell(p, np, nm, ratio, inv_cell, g.disp, N, c);
@@ -175,7 +486,7 @@ k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int 
     for (int oy = 0; oy < 2; ++oy) {
       const int64_t y = oy ? c.i1[1] : c.i0[1];
       const float wxy = wx * (oy ? c.w1[1] : c.w0[1]);
-      const int64_t row = (x * nm + y) * rpitch;
+      const int64_t row = x * rplane + y * rpitch;
       const int64_t a0 = row + c.i0[2], a1 = row + c.i1[2];
       const float wa = wxy * c.w0[2], wb = wxy * c.w1[2];
       f0 += wa * g.F0[a0] + wb * g.F0[a1];
@@ -203,7 +514,7 @@ k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int 
     }
   } else {
     const int ip = (int)p;
-    const int64_t q = ((int64_t)(ip / (np * np)) * np + (ip / np) % np) * ppitch + ip % np;
+    const int64_t q = (int64_t)(ip / (np * np)) * pplane + (int64_t)((ip / np) % np) * ppitch + ip % np;
     l[0] = g.l0[q]; l[1] = g.l1[q]; l[2] = g.l2[q];
     d[0] = g.d0[q]; d[1] = g.d1[q]; d[2] = g.d2[q];
   }
@@ -231,15 +542,15 @@ void launch_gather(const Layout& L, const GatherArgs& a, hipStream_t s) {
   if (a.force_out) {
     ProfScope ps("gather_force", s);
     hipLaunchKernelGGL(k_gather<2>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_m, 2 * L.pitch_p);
+                       2 * L.pitch_m, 2 * L.plane_m, 2 * L.pitch_p, 2 * L.plane_p);
   } else if (a.psi1) {
     ProfScope ps("gather_kick_drift", s);
     hipLaunchKernelGGL(k_gather<0>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_m, 2 * L.pitch_p);
+                       2 * L.pitch_m, 2 * L.plane_m, 2 * L.pitch_p, 2 * L.plane_p);
   } else {
     ProfScope ps("gather_kick_drift", s);
     hipLaunchKernelGGL(k_gather<1>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_m, 2 * L.pitch_p);
+                       2 * L.pitch_m, 2 * L.plane_m, 2 * L.pitch_p, 2 * L.plane_p);
   }
   COLA_LAUNCH_CHECK();
 }
@@ -253,7 +564,8 @@ __global__ void __launch_bounds__(256) k_kspace(KOp op, float2* __restrict__ out
     const int64_t r = e / op.pitch;
     const int iy = (int)(r % op.n);
     const int ix = (int)(r / op.n);
-    out[e] = kspace_eval<KIND>(op, ix, iy, iz, e);
+    const int64_t idx = ix * op.plane + (int64_t)iy * op.pitch + iz;
+    out[idx] = kspace_eval<KIND>(op, ix, iy, iz, idx);
   }
 }
 
@@ -303,11 +615,12 @@ void launch_2lpt_sub(float* acc, const float* d, size_t n, hipStream_t s) {
 __global__ void k_unpad3(const float* __restrict__ a0, const float* __restrict__ a1,
                          const float* __restrict__ a2, const float* __restrict__ b0,
                          const float* __restrict__ b1, const float* __restrict__ b2, float alpha,
-                         float beta, float* __restrict__ out, int64_t N, int np, int ppitch) {
+                         float beta, float* __restrict__ out, int64_t N, int np, int ppitch,
+                         int64_t pplane) {
   for (int64_t p = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; p < N;
        p += (int64_t)gridDim.x * blockDim.x) {
     const int ip = (int)p;
-    const int64_t q = ((int64_t)(ip / (np * np)) * np + (ip / np) % np) * ppitch + ip % np;
+    const int64_t q = (int64_t)(ip / (np * np)) * pplane + (int64_t)((ip / np) % np) * ppitch + ip % np;
     float x = alpha * a0[q], y = alpha * a1[q], z = alpha * a2[q];
     if (b0) {
       x += beta * b0[q];
@@ -325,7 +638,7 @@ void launch_unpad3(const Layout& L, const float* const f0[3], const float* const
   ProfScope ps("unpad", s);
   hipLaunchKernelGGL(k_unpad3, dim3(grid_for(L.N, 256)), dim3(256), 0, s, f0[0], f0[1], f0[2],
                      f1 ? f1[0] : nullptr, f1 ? f1[1] : nullptr, f1 ? f1[2] : nullptr, alpha, beta,
-                     out, L.N, L.np, 2 * L.pitch_p);
+                     out, L.N, L.np, 2 * L.pitch_p, 2 * L.plane_p);
   COLA_LAUNCH_CHECK();
 }
 
@@ -347,19 +660,19 @@ void launch_combine_u0(const Layout& L, const float* psi1, const float* psi2, co
 }
 
 __global__ void k_unpad_mesh(const float* __restrict__ in, float* __restrict__ out, int n,
-                             int rpitch, float sub) {
+                             int rpitch, int64_t rplane, float sub) {
   const int64_t total = (int64_t)n * n * n;
   for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
        e += (int64_t)gridDim.x * blockDim.x) {
     const int64_t r = e / n;
-    out[e] = in[r * rpitch + (e - r * n)] - sub;
+    out[e] = in[(r / n) * rplane + (r % n) * rpitch + (e - r * n)] - sub;
   }
 }
 
 void launch_unpad_mesh(const Layout& L, const float* padded, float* flat, hipStream_t s, float sub) {
   ProfScope ps("unpad_mesh", s);
   hipLaunchKernelGGL(k_unpad_mesh, dim3(grid_for(L.M, 256)), dim3(256), 0, s, padded, flat, L.nm,
-                     2 * L.pitch_m, sub);
+                     2 * L.pitch_m, 2 * L.plane_m, sub);
   COLA_LAUNCH_CHECK();
 }
 
@@ -407,7 +720,8 @@ constexpr int kPkMaxBins = 2048;
 
 // Per block: LDS shell sums of w, w P and w |k| over a grid-stride share of the modes.
 __global__ void __launch_bounds__(256)
-k_pk_partial(const float2* __restrict__ dk, int n, int pitch, int nbins, float kf, float vol,
+k_pk_partial(const float2* __restrict__ dk, int n, int pitch, int64_t plane, int nbins, float kf,
+             float vol,
              float* __restrict__ part_p, float* __restrict__ part_k,
              unsigned* __restrict__ part_w) {
   __shared__ float sp[kPkMaxBins], sk[kPkMaxBins];
@@ -431,7 +745,7 @@ k_pk_partial(const float2* __restrict__ dk, int n, int pitch, int nbins, float k
     if (n2 == 0) continue;
     const int b = shell_of(n2);
     if (b >= nbins) continue;
-    const float2 v = dk[r * pitch + iz];
+    const float2 v = dk[ix * plane + (int64_t)iy * pitch + iz];
     const float wx = sincf_pi((float)nx / n), wy = sincf_pi((float)ny / n),
                 wz = sincf_pi((float)iz / n);
     const float W = wx * wx * wy * wy * wz * wz;
@@ -486,7 +800,7 @@ void launch_pk(const Layout& L, const float2* dk, int nbins, void* scratch, floa
   const float vol = (float)(L.box * L.box * L.box);
   {
     ProfScope ps("pk_bin", s);
-    hipLaunchKernelGGL(k_pk_partial, dim3(kPkBlocks), dim3(256), 0, s, dk, L.nm, L.pitch_m, nbins,
+    hipLaunchKernelGGL(k_pk_partial, dim3(kPkBlocks), dim3(256), 0, s, dk, L.nm, L.pitch_m, L.plane_m, nbins,
                        kf, vol, part_p, part_k, part_w);
     COLA_LAUNCH_CHECK();
   }

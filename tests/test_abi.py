@@ -31,13 +31,17 @@ def test_query_sizes_and_layout():
     N = 512 ** 3
     assert s["disp_bytes"] == s["vel_bytes"] >= 12 * N
     assert s["lpt_bytes"] >= 24 * N                     # Psi1, Psi2 per particle
-    mesh = 1024 * 1024 * 528 * 8                        # padded half-complex mesh
-    assert s["work_bytes"] == 5 * mesh
+    up = lambda x: -(-x // 256) * 256                   # noqa: E731
+    mesh = up(1024 * (1024 * 528 + 16) * 8)             # padded half-complex mesh
+    ntiles = (1024 // 16) ** 3                          # 16^3-cell deposit tiles
+    nblk = -(-ntiles // 1024)
+    bins = -(-(17 * ntiles + 2 * nblk + 64) * 4 // 256) * 256
+    assert s["work_bytes"] == 5 * mesh + bins + 16 * N  # + counters + sorted CIC records
     assert s["total_bytes"] == sum(v for k, v in s.items() if k != "total_bytes")
     # scale-dependent f(R) stores phi1_k, phi2_k and six particle-grid LPT fields
     sf = C.cola_query_sizes(p.with_(model=C.FR_HS1))
-    pg = 512 * 512 * 272 * 8
-    assert sf["lpt_bytes"] == 2 * pg and sf["work_bytes"] == 5 * mesh + 6 * pg
+    pg = up(512 * (512 * 272 + 16) * 8)
+    assert sf["lpt_bytes"] == 2 * pg and sf["work_bytes"] == 5 * mesh + 6 * pg + bins + 16 * N
 
 
 @pytest.mark.parametrize("bad", [dict(np1d=30), dict(np1d=40), dict(nmesh1d=96, np1d=64),
