@@ -57,7 +57,8 @@ typedef int32_t cola_status;
  * growth factors with the modified force (Sec. 7.1).
  * Valid ranges (else COLA_E_ARG): 0 < omega_m <= 1, 0 <= omega_b < omega_m, h > 0,
  * sigma8 > 0, t_cmb > 0, np1d and nmesh1d of the form 2^a 3^b with b <= 1,
- * 8 <= np1d <= nmesh1d <= 2048, nmesh1d a multiple of np1d, box > 0, z_init > 0,
+ * 8 <= np1d <= 1024, np1d <= nmesh1d <= min(2048, 4 np1d), nmesh1d a multiple of np1d,
+ * box > 0, z_init > 0,
  * 1 <= n_steps <= 4096, fr0_abs > 0 for f(R), rc_h0 > 0 for nDGP, r_smooth >= 0,
  * filter in 0..2, model in 0..2, growth_mode in 0..1, screening in 0..1. */
 typedef struct cola_params {

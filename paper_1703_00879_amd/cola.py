@@ -13,7 +13,7 @@ from dataclasses import dataclass, fields, replace
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "_lib", "libcola.so")
+LIB_PATH = os.environ.get("COLA_LIBRARY") or os.path.join(_PKG, "_lib", "libcola.so")
 
 COLA_OK = 0
 LCDM, FR_HS1, NDGP = 0, 1, 2

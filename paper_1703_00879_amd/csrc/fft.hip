@@ -263,13 +263,18 @@ struct ColCfg {
 
 // Strided pass: tile t covers columns [col0, col0 + B) of block t / tilesPerBlock,
 // element j of column c at base + j * elemStride + c.
+// Strided pass: tile t covers columns [col0, col0 + B) of block t / tilesPerBlock, element
+// j of column c at base + j * elemStride + c.  The twiddles are staged in LDS so that no
+// butterfly stage waits on the global-load queue.
 template <int N, int DIR, int KIND>
 __global__ void __launch_bounds__(ColCfg<N>::T)
 k_fft_col(float2* __restrict__ data, int64_t elemStride, int64_t tilesPerBlock,
-          int64_t blockStride, const float2* __restrict__ tw, KOp op) {
+          int64_t blockStride, int64_t ntiles, const float2* __restrict__ tw_g, KOp op) {
   constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
   __shared__ float2 lds[N * B];
+  __shared__ float2 tw[N];
   const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += T) tw[i] = tw_g[i];   // first read after stage 0's barrier
   const int64_t tile = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles share an L2
   const int64_t colInBlock = (tile % tilesPerBlock) * B;
   const int64_t base = (tile / tilesPerBlock) * blockStride + colInBlock;
@@ -300,7 +305,9 @@ k_fft_col_force3(const float2* __restrict__ dk, const float2* __restrict__ sk,
   constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
   constexpr int R0 = Plan<N>::rad[0], NB0 = E / R0;
   __shared__ float2 lds[N * B];
+  __shared__ float2 twl[N];
   const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += T) twl[i] = tw[i];
   const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * B;   // X pass: one block
   float2 g[NB0][R0];
 #pragma unroll
@@ -325,7 +332,7 @@ k_fft_col_force3(const float2* __restrict__ dk, const float2* __restrict__ sk,
       return grad_minus_i(op, jj, (int)(col / op.pitch), (int)(col % op.pitch), comp, g[i][r]);
     };
     auto store = [&](int j, int c, float2 v) { out[base + j * elemStride + c] = v; };
-    GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load, store);
+    GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, twl, load, store);
     __syncthreads();   // the next component reuses the LDS tile
   }
 }
@@ -544,7 +551,7 @@ static void col_pass(float2* data, int64_t elemStride, int64_t tiles, int64_t ti
                      const char* name) {
   ProfScope ps(name, s);
   hipLaunchKernelGGL((k_fft_col<N, DIR, KIND>), dim3((unsigned)tiles), dim3(ColCfg<N>::T), 0, s,
-                     data, elemStride, tilesPerBlock, blockStride, tw, op);
+                     data, elemStride, tilesPerBlock, blockStride, tiles, tw, op);
   COLA_LAUNCH_CHECK();
 }
 

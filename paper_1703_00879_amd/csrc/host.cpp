@@ -164,6 +164,7 @@ void validate(const cola_params& p) {
   if (p.np1d < 8 || p.np1d > 1024) bad("np1d must be in [8, 1024]");
   if (p.nmesh1d < p.np1d || p.nmesh1d > 2048) bad("nmesh1d must be in [np1d, 2048]");
   if (p.nmesh1d % p.np1d) bad("nmesh1d must be a multiple of np1d");
+  if (p.nmesh1d > 4 * p.np1d) bad("nmesh1d must be at most 4 np1d");
   if (!fft_size_supported(p.np1d) || !fft_size_supported(p.nmesh1d)) bad("FFT size not supported");
   if (!(p.box > 0) || !(p.z_init > 0)) bad("box and z_init must be > 0");
   if (p.n_steps < 1 || p.n_steps > 4096) bad("n_steps must be in [1, 4096]");

@@ -24,8 +24,10 @@ __device__ __forceinline__ float smooth_window(float k2R2, int filter) {
   return 3.f * (s - x * c) / (x * x * x);
 }
 
+// Value of operator KIND at mode (ix, iy, iz) given the raw source values a (and b).
 template <int KIND>
-__device__ __forceinline__ float2 kspace_eval(const KOp& op, int ix, int iy, int iz, int64_t idx) {
+__device__ __forceinline__ float2 kspace_apply(const KOp& op, int ix, int iy, int iz, float2 a,
+                                               float2 b) {
   const int n = op.n, h = n >> 1;
   if (iz > h) return make_float2(0.f, 0.f);
   const int nx = ix < h ? ix : ix - n;
@@ -40,13 +42,10 @@ __device__ __forceinline__ float2 kspace_eval(const KOp& op, int ix, int iy, int
   const float k_c = op.kf * (float)(op.comp == 0 ? nx : (op.comp == 1 ? ny : nz));
   const float k_c2 = op.kf * (float)(op.comp2 == 0 ? nx : (op.comp2 == 1 ? ny : nz));
   if constexpr (KIND == K_COPY) {
-    const float2 a = op.a[idx];
     return make_float2(op.scale * a.x, op.scale * a.y);
   } else if constexpr (KIND == K_FORCE) {
     if (n2 == 0 || nyq_c) return make_float2(0.f, 0.f);
     const float k2 = op.kf * op.kf * (float)n2;
-    const float2 a = op.a[idx];
-    const float2 b = op.b ? op.b[idx] : a;
     const float gn = op.g_n / k2, g5 = op.g_5 / (k2 + op.a2m2);
     const float2 g = make_float2(gn * a.x + g5 * b.x, gn * a.y + g5 * b.y);
     const float f = k_c * op.scale;   // -i k_c g
@@ -54,14 +53,12 @@ __device__ __forceinline__ float2 kspace_eval(const KOp& op, int ix, int iy, int
   } else if constexpr (KIND == K_POT) {
     if (n2 == 0) return make_float2(0.f, 0.f);
     const float k2 = op.kf * op.kf * (float)n2;
-    const float2 a = op.a[idx];
     const float f = op.g_n / k2 * op.scale;
     return make_float2(f * a.x, f * a.y);
   } else if constexpr (KIND == K_SMOOTH) {
     if (n2 == 0) return make_float2(0.f, 0.f);
     const float k2 = op.kf * op.kf * (float)n2;
     const float f = smooth_window(k2 * op.r_smooth * op.r_smooth, op.filter) * op.scale;
-    const float2 a = op.a[idx];
     return make_float2(f * a.x, f * a.y);
   } else if constexpr (KIND == K_LPT) {
     if (n2 == 0 || nyq_c) return make_float2(0.f, 0.f);
@@ -79,24 +76,33 @@ __device__ __forceinline__ float2 kspace_eval(const KOp& op, int ix, int iy, int
       x1 = (float)t0[0];
       x2 = (float)t0[3];
     }
-    const float2 a = op.a[idx];
-    const float2 b = op.b[idx];
     const float2 g = make_float2(x1 * a.x + x2 * b.x, x1 * a.y + x2 * b.y);
     const float f = k_c * op.scale;   // +i k_c g
     return make_float2(-f * g.y, f * g.x);
   } else if constexpr (KIND == K_HESS) {
     if (op.comp != op.comp2 && (nyq_c || nyq_c2)) return make_float2(0.f, 0.f);
     const float f = -k_c * k_c2 * op.scale;
-    const float2 a = op.a[idx];
     return make_float2(f * a.x, f * a.y);
   } else if constexpr (KIND == K_GRAD) {
     if (nyq_c) return make_float2(0.f, 0.f);
     const float f = k_c * op.scale;
-    const float2 a = op.a[idx];
     return make_float2(-f * a.y, f * a.x);
   } else {
     return make_float2(0.f, 0.f);
   }
+}
+
+// Sources an operator reads (a always; b for K_FORCE with a screened source and K_LPT).
+template <int KIND>
+__device__ __forceinline__ bool kspace_uses_b(const KOp& op) {
+  return (KIND == K_LPT) || (KIND == K_FORCE && op.b != nullptr);
+}
+
+template <int KIND>
+__device__ __forceinline__ float2 kspace_eval(const KOp& op, int ix, int iy, int iz, int64_t idx) {
+  const float2 a = op.a[idx];
+  const float2 b = kspace_uses_b<KIND>(op) ? op.b[idx] : a;
+  return kspace_apply<KIND>(op, ix, iy, iz, a, b);
 }
 
 // Potential part of the force operator: [g_n/k^2 a + g_5/(k^2 + a2m2) b] * scale

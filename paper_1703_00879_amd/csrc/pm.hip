@@ -79,6 +79,7 @@ void launch_fill(float* p, size_t n, float v, hipStream_t s) {
 constexpr int kBrickX = 4, kBrickY = 8, kBrickZ = 8;   // 256 particles per work-group
 constexpr int kHash = 512;                              // > 256 distinct keys: never full
 constexpr int kScanBlock = 1024;                        // tiles per scan block
+constexpr float kFix = 16777216.f;                      // 2^24: deposit fixed-point unit
 
 size_t bins_bytes(int64_t ntiles) {
   const int64_t nblk = (ntiles + kScanBlock - 1) / kScanBlock;
@@ -267,7 +268,12 @@ __global__ void __launch_bounds__(256)
 k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__ start,
                 const uint32_t* __restrict__ cnt, BinGeo g, float* __restrict__ rho, int rpitch,
                 int64_t rplane, float mass) {
-  __shared__ float acc[T * T * T];
+  // 64-bit fixed-point accumulation in units of 2^-24: integer LDS atomics run several
+  // times faster than float ones here, and integer sums do not depend on the order of
+  // the particles, so the density mesh is bitwise reproducible.  A contribution is at
+  // most the particle mass (nmesh/np)^3 <= 64 (< 2^32 units), and a cell overflows only
+  // beyond ~10^12 in mean-density units.
+  __shared__ unsigned long long acc[T * T * T];
   __shared__ uint32_t seg[8][9];   // per offset d: start of the source tile, 8 class counts
   const int nt1 = g.nt1;
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
@@ -279,7 +285,7 @@ k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__
     const int64_t src = ((int64_t)sx * nt1 + sy) * nt1 + sz;
     seg[d][k] = k == 0 ? start[src] : cnt[src * 8 + k - 1];
   }
-  for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) acc[i] = 0.f;
+  for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) acc[i] = 0ull;
   // Flatten the (offset d, class c) segments that reach this tile into one list, so the
   // entries are read in a single strided sweep (at most 1 + 3*4 + 3*2 + 1 = 20 segments).
   __shared__ uint32_t sb[24], so[25];
@@ -348,7 +354,8 @@ k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__
         const int lx = lx0 + (o & 1), ly = ly0 + ((o >> 1) & 1), lz = lz0 + ((o >> 2) & 1);
         if (lx >= 0 && lx < T && ly >= 0 && ly < T && lz >= 0 && lz < T)
           atomicAdd(&acc[(lx * T + ly) * T + lz],
-                    mass * wx[o & 1] * wy[(o >> 1) & 1] * wz[(o >> 2) & 1]);
+                    (unsigned long long)__float2uint_rn(
+                        mass * wx[o & 1] * wy[(o >> 1) & 1] * wz[(o >> 2) & 1] * kFix));
       }
     }
   }
@@ -356,7 +363,8 @@ k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__
   const int ox = tx * T, oy = ty * T, oz = tz * T;
   for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) {
     const int lx = i / (T * T), ly = (i / T) % T, lz = i % T;
-    rho[(int64_t)(ox + lx) * rplane + (int64_t)(oy + ly) * rpitch + oz + lz] = acc[i];
+    rho[(int64_t)(ox + lx) * rplane + (int64_t)(oy + ly) * rpitch + oz + lz] =
+        (float)acc[i] * (1.f / kFix);
   }
 }
 

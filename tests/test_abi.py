@@ -47,7 +47,8 @@ def test_query_sizes_and_layout():
 @pytest.mark.parametrize("bad", [dict(np1d=30), dict(np1d=40), dict(nmesh1d=96, np1d=64),
                                  dict(np1d=64, nmesh1d=32), dict(box=0.0), dict(n_steps=0),
                                  dict(model=1, fr0_abs=0.0), dict(model=2, rc_h0=-1.0),
-                                 dict(omega_m=1.5), dict(filter=3), dict(np1d=2048, nmesh1d=2048)])
+                                 dict(omega_m=1.5), dict(filter=3), dict(np1d=2048, nmesh1d=2048),
+                                 dict(np1d=16, nmesh1d=96)])
 def test_invalid_parameters_rejected(bad):
     p = C.Params().with_(**bad)
     with pytest.raises(C.ColaError) as e:
