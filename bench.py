@@ -38,32 +38,38 @@ def workload_params(C):
 
 def algorithmic_bytes(name, p):
     """Bytes a kernel must move per launch (single-precision fields, unpadded):
-    mesh M = n^3 real cells, half-complex H = n^2 (n/2 + 1) complex values."""
+    mesh M = n^3 real cells, half-complex H = n^2 (n/2 + 1) complex values, N particles."""
     n = p.nmesh1d
     M = n ** 3
     H = n * n * (n // 2 + 1)
     N = p.np1d ** 3
     table = {
-        "fft_r2c_z": 4 * M + 8 * H,                 # read real mesh, write half-complex
+        "bin_count": 12 * N,                         # read u; tile counts are negligible
+        "bin_scan": 0,
+        "bin_scatter": 12 * N + 16 * N,              # read u, write one 16-byte entry each
+        "deposit": 16 * N + 4 * M,                   # read entries, write the density once
+        "fft_r2c_z": 4 * M + 8 * H,                  # read real mesh, write half-complex
         "fft_c2r_z": 8 * H + 4 * M,
         "fft_y_fwd": 16 * H, "fft_x_fwd": 16 * H, "fft_y_inv": 16 * H,
         "fft_x_inv_smooth": 16 * H,                  # read delta_k, write W delta_k pass
-        "fft_x_inv_force": 24 * H,                   # read delta_k and S_k, write F_k pass
-        "deposit": 12 * N + 4 * M,                   # read u, write the density once
-        "deposit_zero": 4 * M,
-        "screen": 12 * M,                            # read rho and delta_R, write S
+        "fft_x_inv_pot": 16 * H,
+        "fft_z_screen": 8 * H + 4 * M + 8 * H,       # read delta_R and rho, write S_k pass
+        "fft_x_inv_force3": 16 * H + 24 * H,         # read delta_k, S_k; write 3 force passes
         "gather_kick_drift": 12 * M + 72 * N,        # 3 force meshes; u, v, Psi1, Psi2 in; u, v out
     }
     return table.get(name)
 
 
 def yardstick_bytes_per_step(p):
-    """Algorithmic bytes of one screened, scale-independent step with 3-pass FFTs:
-    deposit, 2 forward and 4 inverse FFTs, screening, gather+kick+drift."""
-    names_counts = {"deposit": 1, "deposit_zero": 1, "fft_r2c_z": 2, "fft_c2r_z": 4,
-                    "fft_y_fwd": 2, "fft_x_fwd": 2, "fft_y_inv": 4, "fft_x_inv_smooth": 1,
-                    "fft_x_inv_force": 3, "screen": 1, "gather_kick_drift": 1}
-    return sum(algorithmic_bytes(k, p) * c for k, c in names_counts.items())
+    """Algorithmic bytes of one screened, scale-independent step: deposit (12N + 4M),
+    a forward R2C (16M), screening (C2R of W delta_k, the real-space factor and the R2C
+    of S: 52M), the fused Green's function (20M), three force C2Rs (48M) and the
+    gather with kick and drift (12M + 72N); 152M + 84N in total, counting each 3D FFT
+    as one read and one write of a real-sized mesh per pair of passes."""
+    n = p.nmesh1d
+    M = n ** 3
+    N = p.np1d ** 3
+    return 152 * M + 84 * N
 
 
 def source_hash():

@@ -193,8 +193,9 @@ static void do_prepare(const cola_params& p, cola_state* st, const Bufs& b, hipS
 
 // ------------------------------------------------------------------ PM force core
 // Writes the three force meshes (real, padded) into mesh[0], mesh[3], mesh[4].
-// mesh[0] holds rho after the deposit; mesh[1] delta_k; mesh[2] the screening field and
-// then S_k.  If flat_out is given, rho and S are copied there before being overwritten.
+// mesh[0] holds rho after the deposit; mesh[1] delta after the forward Z and Y passes,
+// then delta_k; mesh[2] the screening field and then S after the forward Z and Y passes;
+// the force components end in mesh[0], mesh[3] and mesh[4].  If flat_out is given, rho and S are copied there before being overwritten.
 static void pm_core(const cola_params& p, const Bufs& b, const float* disp, double a,
                     float* flat_out, hipStream_t s) {
   const Layout& L = b.L;
@@ -204,13 +205,13 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
   const float invM = (float)(1.0 / (double)L.M);
   launch_deposit(L, disp, R(M[0]), b.bins, b.entries, s);
   if (flat_out) launch_unpad_mesh(L, R(M[0]), flat_out, s);
-  fft_r2c(pl, R(M[0]), M[1], s);
-  const float2* src = nullptr;
+  fft_r2c_zy(pl, R(M[0]), M[1], s);   // the X pass is fused into what follows
+  const float2* dk = nullptr;
+  float2* src = M[1];
   KOp base;
   base.kf = (float)(2.0 * M_PI / p.box);
   if (sc.screen) {
     KOp op = base;
-    op.a = M[1];
     op.scale = invM;
     int kind = K_SMOOTH;
     if (p.model == COLA_FR_HS1) {
@@ -220,9 +221,10 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
       op.r_smooth = (float)p.r_smooth;
       op.filter = p.filter;
     }
-    fft_screen(pl, kind, op, M[2], R(M[0]), flat_out ? R(M[3]) : nullptr, p.model, sc.cham_thr,
-               sc.vx_pref, s);
+    fft_screen(pl, kind, op, M[1], M[2], R(M[0]), flat_out ? R(M[3]) : nullptr, p.model,
+               sc.cham_thr, sc.vx_pref, s);
     if (flat_out) launch_unpad_mesh(L, R(M[3]), flat_out + L.M, s);
+    dk = M[1];
     src = M[2];
   } else if (flat_out) {
     launch_unpad_mesh(L, R(M[0]), flat_out + L.M, s, 1.f);   // S = delta = rho - 1
@@ -233,7 +235,7 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
   op.a2m2 = sc.a2m2;
   op.scale = invM;
   float2* const outs[3] = {M[0], M[3], M[4]};
-  fft_c2r_force3(pl, op, M[1], src, outs, s);
+  fft_c2r_force3(pl, op, dk, src, outs, s);
 }
 
 }  // namespace cola

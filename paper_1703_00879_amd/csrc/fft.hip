@@ -19,10 +19,17 @@
 // Conventions: forward e^{-i k x}, inverse e^{+i k x}, both unnormalised.  Twiddles come
 // from a table exp(-2 pi i t / n) built on the host in double precision.
 
+#include <type_traits>
+
 #include "internal.h"
 #include "kspace.h"
 
 namespace cola {
+
+// Element offsets: 32-bit while a whole mesh of n^3 half-complex values (with padding)
+// stays below 2^32 elements (n <= 1536), so addresses are one register plus a scalar base.
+template <int N>
+using Off = typename std::conditional<(N <= 1536), uint32_t, uint64_t>::type;
 
 // ------------------------------------------------------------------ complex helpers
 __device__ __forceinline__ float2 cadd(float2 a, float2 b) { return make_float2(a.x + b.x, a.y + b.y); }
@@ -184,13 +191,17 @@ __device__ __forceinline__ void lds_fft(float2* lds, int tid, int T, const float
   Stages<N, DIR, E, B, LS, TWS, 0, 1>::run(lds, tid, T, tw);
 }
 
-// Stockham transform of B columns whose first stage reads its operands straight from
-// global memory through `load(i, r, j, c)` (operand r of the thread's butterfly i, element
-// j of column c) and whose last stage writes straight to global
-// memory through `store(j, c, v)`; only the middle stages go through LDS.  Each thread
-// issues all of its E loads before it uses any of them, so a work-group keeps its whole
-// tile in flight.
-template <int N, int DIR, int E, int B, int LS, int TWS, int S, int NS>
+// Stockham transform of B columns whose first stage reads its operands through
+// `load(i, r, j, c)` (operand r of the thread's butterfly i, element j of column c) and
+// whose last stage writes through `store(j, c, v)`; only the middle stages go through LDS.
+// Each thread issues all of its E loads before it uses any of them, so a work-group keeps
+// its whole tile in flight.  FL says whether `load` reads the LDS tile (kFirstFromLds) or
+// `store` writes it (kLastToLds), so that the stage in question separates its reads from
+// its in-place writes by a barrier; after a kLastToLds transform the caller must
+// synchronise before reading the tile.
+constexpr int kFirstFromLds = 1, kLastToLds = 2;
+
+template <int N, int DIR, int E, int B, int LS, int TWS, int S, int NS, int FL = 0>
 struct GStages {
   template <class Load, class Store>
   static __device__ __forceinline__ void run(float2* lds, int tid, int T, const float2* tw,
@@ -200,6 +211,8 @@ struct GStages {
       constexpr int R = Plan<N>::rad[S];
       constexpr int NB = E / R;
       float2 v[NB][R];
+      constexpr bool reads_lds = S > 0 || (FL & kFirstFromLds);
+      constexpr bool writes_lds = S + 1 < nst || (FL & kLastToLds);
       if constexpr (S == 0) {
 #pragma unroll
         for (int i = 0; i < NB; ++i) {
@@ -216,8 +229,8 @@ struct GStages {
 #pragma unroll
           for (int r = 0; r < R; ++r) v[i][r] = lds[(j + r * (N / R)) * LS + c];
         }
-        if constexpr (S + 1 < nst) __syncthreads();   // all reads before the in-place writes
       }
+      if constexpr (reads_lds && writes_lds) __syncthreads();   // all reads before the in-place writes
 #pragma unroll
       for (int i = 0; i < NB; ++i) {
         const int b = tid + i * T;
@@ -243,7 +256,7 @@ struct GStages {
       }
       if constexpr (S + 1 < nst) {
         __syncthreads();
-        GStages<N, DIR, E, B, LS, TWS, S + 1, NS * R>::run(lds, tid, T, tw, load, store);
+        GStages<N, DIR, E, B, LS, TWS, S + 1, NS * R, FL>::run(lds, tid, T, tw, load, store);
       }
     }
   }
@@ -254,15 +267,15 @@ struct GStages {
 // work-groups share a CU and one streams its tile while the other computes.
 template <int N>
 struct ColCfg {
-  static constexpr int E = Plan<N>::E;
+  // 8 elements per thread where the plan allows it: twice the waves of E = 16 for the
+  // same tile, and half the registers per wave
+  static constexpr int E = Plan<N>::E == 16 ? 8 : Plan<N>::E;
   static constexpr int B0 = 65536 / (8 * N);
   static constexpr int B = B0 >= 16 ? 16 : (B0 >= 8 ? 8 : 4);
   static constexpr int T = N * B / E;
   static_assert(T <= 1024, "column tile needs too many threads");
 };
 
-// Strided pass: tile t covers columns [col0, col0 + B) of block t / tilesPerBlock,
-// element j of column c at base + j * elemStride + c.
 // Strided pass: tile t covers columns [col0, col0 + B) of block t / tilesPerBlock, element
 // j of column c at base + j * elemStride + c.  The twiddles are staged in LDS so that no
 // butterfly stage waits on the global-load queue.
@@ -275,64 +288,112 @@ k_fft_col(float2* __restrict__ data, int64_t elemStride, int64_t tilesPerBlock,
   __shared__ float2 tw[N];
   const int tid = threadIdx.x;
   for (int i = tid; i < N; i += T) tw[i] = tw_g[i];   // first read after stage 0's barrier
-  const int64_t tile = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles share an L2
-  const int64_t colInBlock = (tile % tilesPerBlock) * B;
-  const int64_t base = (tile / tilesPerBlock) * blockStride + colInBlock;
+  using O = Off<N>;
+  const unsigned tile = xcd_block(blockIdx.x, gridDim.x);   // neighbouring tiles share an L2
+  const unsigned tpb = (unsigned)tilesPerBlock;
+  const O colInBlock = (O)(tile % tpb) * B;
+  const O base = (O)(tile / tpb) * (O)blockStride + colInBlock;
+  const O es = (O)elemStride;
   const float2* src = (KIND == K_COPY && op.a) ? op.a : data;
+  static_assert(T % B == 0, "a thread's butterflies must share one column");
+  // X pass of an inverse transform: element j is nu_x; the thread's (y, z) column
+  const int col = (int)colInBlock + tid % B;
+  const int iy = KIND == K_COPY ? 0 : col / op.pitch, iz = KIND == K_COPY ? 0 : col % op.pitch;
   auto load = [&](int, int, int j, int c) -> float2 {
-    const int64_t idx = base + j * elemStride + c;
-    if constexpr (KIND == K_COPY) {
+    const O idx = base + (O)j * es + c;
+    if constexpr (KIND == K_COPY)
       return src[idx];
-    } else {
-      // X pass of an inverse transform: element j is nu_x, column (y, z)
-      const int64_t col = colInBlock + c;
-      return kspace_eval<KIND>(op, j, (int)(col / op.pitch), (int)(col % op.pitch), idx);
-    }
+    else
+      return kspace_eval<KIND>(op, j, iy, iz, idx);
   };
-  auto store = [&](int j, int c, float2 v) { data[base + j * elemStride + c] = v; };
+  auto store = [&](int j, int c, float2 v) { data[base + (O)j * es + c] = v; };
   GStages<N, DIR, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load, store);
 }
 
-// X pass of the three inverse force transforms in one sweep: the Green's function
-// g = [g_n/k^2 delta_k + g_5/(k^2 + a^2 m^2) S_k] / M is formed once per element from one
-// read of delta_k and S_k, kept in registers, and each component -i k_c g is transformed
-// in turn through the same LDS tile and written to its own array.
+// X pass of a forward transform fused with the X pass of the inverse transform through a
+// k-space operator: the forward result (delta_k) is written back in place and, multiplied
+// by the operator (smoothing window or Newtonian potential), transformed back through the
+// same LDS tile into `out`.  One read and two writes of the field instead of two reads
+// and two writes.  It keeps the plan's own element count per thread (16 at n = 1024):
+// with half as many threads two work-groups fit on a CU, which measured faster here
+// than one work-group of twice the waves.
+template <int N, int KIND>
+__global__ void __launch_bounds__(N * ColCfg<N>::B / Plan<N>::E)
+k_fft_col_fwd_op(float2* __restrict__ data, float2* __restrict__ out, int64_t elemStride,
+                 const float2* __restrict__ tw_g, KOp op) {
+  constexpr int B = ColCfg<N>::B, E = Plan<N>::E, T = N * B / E;
+  static_assert(T % B == 0, "a thread's butterflies must share one column");
+  __shared__ float2 lds[N * B];
+  __shared__ float2 tw[N];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += T) tw[i] = tw_g[i];
+  using O = Off<N>;
+  const O base = (O)xcd_block(blockIdx.x, gridDim.x) * B, es = (O)elemStride;
+  const int col = (int)base + tid % B;   // (y, z) column of every element this thread touches
+  const int iy = col / op.pitch, iz = col % op.pitch;
+  auto load = [&](int, int, int j, int c) -> float2 { return data[base + (O)j * es + c]; };
+  auto store = [&](int j, int c, float2 v) {
+    data[base + (O)j * es + c] = v;
+    lds[j * B + c] = kspace_apply<KIND>(op, j, iy, iz, v, v);
+  };
+  GStages<N, -1, E, B, B, 1, 0, 1, kLastToLds>::run(lds, tid, T, tw, load, store);
+  __syncthreads();
+  auto load2 = [&](int, int, int j, int c) -> float2 { return lds[j * B + c]; };
+  auto store2 = [&](int j, int c, float2 v) { out[base + (O)j * es + c] = v; };
+  GStages<N, +1, E, B, B, 1, 0, 1, kFirstFromLds>::run(lds, tid, T, tw, load2, store2);
+}
+
+// X pass of the forward transform of the (screened) source fused with the X passes of the
+// three inverse force transforms.  The forward X transform of `src` gives S_k in the LDS
+// tile; the Green's function g = [g_n/k^2 delta_k + g_5/(k^2 + a^2 m^2) S_k] / M is formed
+// once per element (delta_k read from dk, or S_k itself when dk is null), kept in
+// registers, and each component -i k_c g is transformed in turn through the same tile and
+// written to its own array.  o0 may alias src and o1 may alias dk: every read of a column
+// precedes the first write to it.
 template <int N>
 __global__ void __launch_bounds__(ColCfg<N>::T)
-k_fft_col_force3(const float2* __restrict__ dk, const float2* __restrict__ sk,
-                 float2* __restrict__ o0, float2* __restrict__ o1, float2* __restrict__ o2,
-                 int64_t elemStride, const float2* __restrict__ tw, KOp op) {
+k_fft_col_fwd_force3(const float2* dk, const float2* src, float2* o0, float2* o1,
+                     float2* __restrict__ o2, int64_t elemStride, const float2* __restrict__ tw_g,
+                     KOp op) {
   constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
   constexpr int R0 = Plan<N>::rad[0], NB0 = E / R0;
+  static_assert(T % B == 0, "a thread's butterflies must share one column");
   __shared__ float2 lds[N * B];
-  __shared__ float2 twl[N];
+  __shared__ float2 tw[N];
   const int tid = threadIdx.x;
-  for (int i = tid; i < N; i += T) twl[i] = tw[i];
-  const int64_t base = (int64_t)xcd_block(blockIdx.x, gridDim.x) * B;   // X pass: one block
+  for (int i = tid; i < N; i += T) tw[i] = tw_g[i];
+  using O = Off<N>;
+  const O base = (O)xcd_block(blockIdx.x, gridDim.x) * B, es = (O)elemStride;   // X pass
+  const int c0 = tid % B;
+  const int col = (int)base + c0;
+  const int iy = col / op.pitch, iz = col % op.pitch;
+  {
+    auto load = [&](int, int, int j, int c) -> float2 { return src[base + (O)j * es + c]; };
+    auto store = [&](int j, int c, float2 v) { lds[j * B + c] = v; };
+    GStages<N, -1, E, B, B, 1, 0, 1, kLastToLds>::run(lds, tid, T, tw, load, store);
+  }
+  __syncthreads();
   float2 g[NB0][R0];
 #pragma unroll
   for (int i = 0; i < NB0; ++i) {
-    const int b = tid + i * T;
-    const int c = b % B, j = b / B;
+    const int j = (tid + i * T) / B;
 #pragma unroll
     for (int r = 0; r < R0; ++r) {
       const int jj = j + r * (N / R0);
-      const int64_t col = base + c;
-      const int iy = (int)(col / op.pitch), iz = (int)(col % op.pitch);
-      const int64_t idx = base + jj * elemStride + c;
-      g[i][r] = green_force(op, jj, iy, iz, dk[idx], sk ? sk[idx] : dk[idx]);
+      const float2 sv = lds[jj * B + c0];
+      const float2 dv = dk ? dk[base + (O)jj * es + c0] : sv;
+      g[i][r] = green_force(op, jj, iy, iz, dv, sv);
     }
   }
-  float2* outs[3] = {o0, o1, o2};
+  __syncthreads();   // the tile is reused by the inverse transforms
 #pragma unroll
   for (int comp = 0; comp < 3; ++comp) {
-    float2* out = outs[comp];
-    auto load = [&](int i, int r, int jj, int c) -> float2 {
-      const int64_t col = base + c;
-      return grad_minus_i(op, jj, (int)(col / op.pitch), (int)(col % op.pitch), comp, g[i][r]);
+    float2* out = comp == 0 ? o0 : (comp == 1 ? o1 : o2);
+    auto load = [&](int i, int r, int jj, int) -> float2 {
+      return grad_minus_i(op, jj, iy, iz, comp, g[i][r]);
     };
-    auto store = [&](int j, int c, float2 v) { out[base + j * elemStride + c] = v; };
-    GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, twl, load, store);
+    auto store = [&](int j, int c, float2 v) { out[base + (O)j * es + c] = v; };
+    GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load, store);
     __syncthreads();   // the next component reuses the LDS tile
   }
 }
@@ -353,12 +414,14 @@ struct RowCfg {
 // of NC + 1 values (pitch `pitch`).  Twiddles tw[t] = exp(-2 pi i t / n).
 template <int NC>
 __global__ void __launch_bounds__(RowCfg<NC>::T)
-k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nrows, int n,
+k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nrows, int /*n*/,
               int pitch, int64_t plane, const float2* __restrict__ tw) {
   constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
   __shared__ float2 lds[NC * LS];
   const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * B;
+  using O = Off<2 * NC>;
+  constexpr int kN = 2 * NC;   // real row length
+  const O r0 = (O)blockIdx.x * B;
   {
     float2 v[E];
 #pragma unroll
@@ -366,9 +429,9 @@ k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nr
       const int e = tid + i * T;
       const int c = e / NC, m = e % NC;
       v[i] = make_float2(0.f, 0.f);
-      if (r0 + c < nrows) {
-        const int64_t r = r0 + c;
-        v[i] = reinterpret_cast<const float2*>(in + 2 * ((r / n) * plane + (r % n) * pitch))[m];
+      if (r0 + c < (O)nrows) {
+        const O r = r0 + c;
+        v[i] = reinterpret_cast<const float2*>(in + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[m];
       }
     }
 #pragma unroll
@@ -382,15 +445,15 @@ k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nr
   // X_k = (Z_k + conj Z_{NC-k})/2 - (i/2) w^k (Z_k - conj Z_{NC-k}),  w = exp(-2 pi i / n)
   for (int e = tid; e < (NC + 1) * B; e += T) {
     const int c = e / (NC + 1), k = e % (NC + 1);
-    if (r0 + c >= nrows) continue;
+    if (r0 + c >= (O)nrows) continue;
     const float2 zk = lds[(k == NC ? 0 : k) * LS + c];
     const float2 zc = cconj(lds[(k == 0 ? 0 : NC - k) * LS + c]);
     const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
     const float2 od = make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y - zc.y));
     const float2 w = (k == NC) ? make_float2(-1.f, 0.f) : tw[k];
     const float2 t = cmul(w, od);          // w^k (Z_k - conj Z_{NC-k}) / 2
-    const int64_t r = r0 + c;
-    out[(r / n) * plane + (r % n) * pitch + k] = make_float2(ev.x + t.y, ev.y - t.x);   // ev - i t
+    const O r = r0 + c;
+    out[(r / kN) * (O)plane + (r % kN) * (O)pitch + k] = make_float2(ev.x + t.y, ev.y - t.x);   // ev - i t
   }
 }
 
@@ -400,12 +463,14 @@ k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nr
 // length-n inverse of X.
 template <int NC>
 __global__ void __launch_bounds__(RowCfg<NC>::T)
-k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nrows, int n,
+k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nrows, int /*n*/,
               int pitch, int64_t plane, const float2* __restrict__ tw) {
   constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
   __shared__ float2 lds[NC * LS];
   const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * B;
+  using O = Off<2 * NC>;
+  constexpr int kN = 2 * NC;   // real row length
+  const O r0 = (O)blockIdx.x * B;
   // X_k and X_{NC-k} come straight from the row (the mirrored read hits the same lines);
   // all loads are issued before any is used
   float2 xk[E], xc[E];
@@ -415,9 +480,9 @@ k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nr
     const int c = e / NC, k = e % NC;
     xk[i] = make_float2(0.f, 0.f);
     xc[i] = make_float2(0.f, 0.f);
-    if (r0 + c < nrows) {
-      const int64_t r = r0 + c;
-      const float2* row = in + (r / n) * plane + (r % n) * pitch;
+    if (r0 + c < (O)nrows) {
+      const O r = r0 + c;
+      const float2* row = in + (r / kN) * (O)plane + (r % kN) * (O)pitch;
       xk[i] = row[k];
       xc[i] = cconj(row[NC - k]);
     }
@@ -436,9 +501,9 @@ k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nr
   lds_fft<NC, +1, E, B, LS, 2>(lds, tid, T, tw);
   for (int e = tid; e < NC * B; e += T) {
     const int c = e / NC, m = e % NC;
-    if (r0 + c >= nrows) continue;
-    const int64_t r = r0 + c;
-    reinterpret_cast<float2*>(out + 2 * ((r / n) * plane + (r % n) * pitch))[m] = lds[m * LS + c];
+    if (r0 + c >= (O)nrows) continue;
+    const O r = r0 + c;
+    reinterpret_cast<float2*>(out + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[m] = lds[m * LS + c];
   }
 }
 
@@ -450,12 +515,17 @@ k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nr
 template <int NC, int MODEL>
 __global__ void __launch_bounds__(RowCfg<NC>::T)
 k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float* __restrict__ s_out,
-                 int64_t nrows, int n, int pitch, int64_t plane, const float2* __restrict__ tw,
+                 int64_t nrows, int /*n*/, int pitch, int64_t plane, const float2* __restrict__ tw,
                  float thr, float vx) {
   constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
   __shared__ float2 lds[NC * LS];
   const int tid = threadIdx.x;
-  const int64_t r0 = (int64_t)blockIdx.x * B;
+  using O = Off<2 * NC>;
+  constexpr int kN = 2 * NC;   // real row length
+  const O r0 = (O)blockIdx.x * B;
+  // the density pairs (x_2m, x_2m+1) of element m are loaded with the row, so that their
+  // latency hides behind the inverse transform
+  float2 rv[E];
   {
     float2 xk[E], xc[E];
 #pragma unroll
@@ -464,11 +534,13 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
       const int c = e / NC, k = e % NC;
       xk[i] = make_float2(0.f, 0.f);
       xc[i] = make_float2(0.f, 0.f);
-      if (r0 + c < nrows) {
-        const int64_t r = r0 + c;
-        const float2* row = data + (r / n) * plane + (r % n) * pitch;
+      rv[i] = make_float2(1.f, 1.f);
+      if (r0 + c < (O)nrows) {
+        const O r = r0 + c;
+        const float2* row = data + (r / kN) * (O)plane + (r % kN) * (O)pitch;
         xk[i] = row[k];
         xc[i] = cconj(row[NC - k]);
+        rv[i] = reinterpret_cast<const float2*>(rho + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[k];
       }
     }
 #pragma unroll
@@ -485,17 +557,6 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
   lds_fft<NC, +1, E, B, LS, 2>(lds, tid, T, tw);
   // S = (rho - 1) eps(field) on the pair (x_2m, x_2m+1) held by element m
   {
-    float2 rv[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = tid + i * T;
-      const int c = e / NC, m = e % NC;
-      rv[i] = make_float2(1.f, 1.f);
-      if (r0 + c < nrows) {
-        const int64_t r = r0 + c;
-        rv[i] = reinterpret_cast<const float2*>(rho + 2 * ((r / n) * plane + (r % n) * pitch))[m];
-      }
-    }
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int e = tid + i * T;
@@ -512,9 +573,9 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
                          (rv[i].y - 1.f) * (2.f / (1.f + sqrtf(1.f + x1))));
       }
       lds[m * LS + c] = sv;
-      if (s_out && r0 + c < nrows) {
-        const int64_t r = r0 + c;
-        reinterpret_cast<float2*>(s_out + 2 * ((r / n) * plane + (r % n) * pitch))[m] = sv;
+      if (s_out && r0 + c < (O)nrows) {
+        const O r = r0 + c;
+        reinterpret_cast<float2*>(s_out + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[m] = sv;
       }
     }
   }
@@ -522,15 +583,15 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
   lds_fft<NC, -1, E, B, LS, 2>(lds, tid, T, tw);
   for (int e = tid; e < (NC + 1) * B; e += T) {
     const int c = e / (NC + 1), k = e % (NC + 1);
-    if (r0 + c >= nrows) continue;
+    if (r0 + c >= (O)nrows) continue;
     const float2 zk = lds[(k == NC ? 0 : k) * LS + c];
     const float2 zc = cconj(lds[(k == 0 ? 0 : NC - k) * LS + c]);
     const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
     const float2 od = make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y - zc.y));
     const float2 w = (k == NC) ? make_float2(-1.f, 0.f) : tw[k];
     const float2 t = cmul(w, od);
-    const int64_t r = r0 + c;
-    data[(r / n) * plane + (r % n) * pitch + k] = make_float2(ev.x + t.y, ev.y - t.x);
+    const O r = r0 + c;
+    data[(r / kN) * (O)plane + (r % kN) * (O)pitch + k] = make_float2(ev.x + t.y, ev.y - t.x);
   }
 }
 
@@ -556,7 +617,7 @@ static void col_pass(float2* data, int64_t elemStride, int64_t tiles, int64_t ti
 }
 
 template <int N>
-static void r2c_impl(const FFTPlan& pl, const float* in, float2* out, hipStream_t s) {
+static void r2c_impl(const FFTPlan& pl, const float* in, float2* out, bool x_pass, hipStream_t s) {
   const int n = pl.n, P = pl.pitch;
   const int64_t rows = (int64_t)n * n;
   {
@@ -572,8 +633,9 @@ static void r2c_impl(const FFTPlan& pl, const float* in, float2* out, hipStream_
   col_pass<N, -1, K_COPY>(out, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, op, s,
                           "fft_y_fwd");
   // X pass: tiles of B (y, z) columns, element stride = plane
-  col_pass<N, -1, K_COPY>(out, pl.plane, (int64_t)n * P / B, (int64_t)n * P / B, 0, pl.tw, op,
-                          s, "fft_x_fwd");
+  if (x_pass)
+    col_pass<N, -1, K_COPY>(out, pl.plane, (int64_t)n * P / B, (int64_t)n * P / B, 0, pl.tw, op,
+                            s, "fft_x_fwd");
 }
 
 template <int N>
@@ -610,14 +672,22 @@ static void c2r_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* data
   }
 }
 
-void fft_r2c(const FFTPlan& pl, const float* in, float2* out, hipStream_t s) {
+static void r2c_dispatch(const FFTPlan& pl, const float* in, float2* out, bool x_pass, hipStream_t s) {
   switch (pl.n) {
-#define CASE(N_) case N_: r2c_impl<N_>(pl, in, out, s); return;
+#define CASE(N_) case N_: r2c_impl<N_>(pl, in, out, x_pass, s); return;
     CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
     CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
 #undef CASE
     default: throw Error{COLA_E_UNSUPPORTED, "FFT size not supported"};
   }
+}
+
+void fft_r2c(const FFTPlan& pl, const float* in, float2* out, hipStream_t s) {
+  r2c_dispatch(pl, in, out, true, s);
+}
+
+void fft_r2c_zy(const FFTPlan& pl, const float* in, float2* out, hipStream_t s) {
+  r2c_dispatch(pl, in, out, false, s);
 }
 
 void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* out, hipStream_t s) {
@@ -631,7 +701,7 @@ void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* ou
 }
 
 template <int N>
-static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, const float2* sk,
+static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, const float2* src,
                         float2* const out[3], hipStream_t s) {
   const int n = pl.n, P = pl.pitch;
   const int64_t rows = (int64_t)n * n;
@@ -641,9 +711,9 @@ static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, c
   op.pitch = P;
   op.plane = pl.plane;
   {
-    ProfScope ps("fft_x_inv_force3", s);
-    hipLaunchKernelGGL((k_fft_col_force3<N>), dim3((unsigned)((int64_t)n * P / B)), dim3(ColCfg<N>::T),
-                       0, s, dk, sk, out[0], out[1], out[2], pl.plane, pl.tw, op);
+    ProfScope ps("fft_x_fwd_force3", s);
+    hipLaunchKernelGGL((k_fft_col_fwd_force3<N>), dim3((unsigned)((int64_t)n * P / B)),
+                       dim3(ColCfg<N>::T), 0, s, dk, src, out[0], out[1], out[2], pl.plane, pl.tw, op);
     COLA_LAUNCH_CHECK();
   }
   KOp none;
@@ -660,8 +730,8 @@ static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, c
 }
 
 template <int N>
-static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* data, const float* rho,
-                        float* s_out, int model, float thr, float vx, hipStream_t s) {
+static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* dk, float2* data,
+                        const float* rho, float* s_out, int model, float thr, float vx, hipStream_t s) {
   const int n = pl.n, P = pl.pitch;
   const int64_t rows = (int64_t)n * n;
   constexpr int B = ColCfg<N>::B;
@@ -670,10 +740,17 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
   op.pitch = P;
   op.plane = pl.plane;
   const int64_t xtiles = (int64_t)n * P / B;
-  if (kind == K_POT)
-    col_pass<N, 1, K_POT>(data, pl.plane, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_pot");
-  else
-    col_pass<N, 1, K_SMOOTH>(data, pl.plane, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_smooth");
+  {
+    const dim3 g((unsigned)xtiles), b(N * B / Plan<N>::E);
+    if (kind == K_POT) {
+      ProfScope ps("fft_x_fwd_pot", s);
+      hipLaunchKernelGGL((k_fft_col_fwd_op<N, K_POT>), g, b, 0, s, dk, data, pl.plane, pl.tw, op);
+    } else {
+      ProfScope ps("fft_x_fwd_smooth", s);
+      hipLaunchKernelGGL((k_fft_col_fwd_op<N, K_SMOOTH>), g, b, 0, s, dk, data, pl.plane, pl.tw, op);
+    }
+    COLA_LAUNCH_CHECK();
+  }
   KOp none;
   col_pass<N, 1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s, "fft_y_inv");
   {
@@ -689,13 +766,12 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
     COLA_LAUNCH_CHECK();
   }
   col_pass<N, -1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s, "fft_y_fwd");
-  col_pass<N, -1, K_COPY>(data, pl.plane, xtiles, xtiles, 0, pl.tw, none, s, "fft_x_fwd");
 }
 
-void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* sk,
+void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* src,
                     float2* const out[3], hipStream_t s) {
   switch (pl.n) {
-#define CASE(N_) case N_: force3_impl<N_>(pl, op, dk, sk, out, s); return;
+#define CASE(N_) case N_: force3_impl<N_>(pl, op, dk, src, out, s); return;
     CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
     CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
 #undef CASE
@@ -703,10 +779,10 @@ void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const fl
   }
 }
 
-void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* data, const float* rho,
+void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* dk, float2* data, const float* rho,
                 float* s_out, int model, float thr, float vx, hipStream_t s) {
   switch (pl.n) {
-#define CASE(N_) case N_: screen_impl<N_>(pl, kind, op, data, rho, s_out, model, thr, vx, s); return;
+#define CASE(N_) case N_: screen_impl<N_>(pl, kind, op, dk, data, rho, s_out, model, thr, vx, s); return;
     CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
     CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
 #undef CASE

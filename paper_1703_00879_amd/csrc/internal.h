@@ -142,23 +142,29 @@ struct FFTPlan {
 bool fft_size_supported(int n);
 // forward real-to-complex 3D transform (unnormalised, e^{-ikx}); in may alias out
 void fft_r2c(const FFTPlan& pl, const float* in, float2* out, hipStream_t s);
+// its Z and Y passes only: the X pass is left to fft_screen / fft_c2r_force3
+void fft_r2c_zy(const FFTPlan& pl, const float* in, float2* out, hipStream_t s);
 // inverse complex-to-real 3D transform (unnormalised, e^{+ikx}).  The first pass reads
 // through the k-space operator `op` (kind) and writes `data`; later passes are in place;
 // the real result goes to `out` (may alias data).
 void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* out,
              hipStream_t s);
 
-// The three force components in one go: an X pass that reads delta_k and S_k once
-// (S_k = delta_k when sk is null) and writes -i k_c [Green's function] into out[c], then
-// per component the Y pass and the real Z pass (in place, real result in out[c]).
-void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* sk,
+// Forward X pass of `src` (Z and Y passes done) fused with the three inverse force
+// transforms: one X pass that forms -i k_c [Green's function of delta_k and S_k] (delta_k
+// read from dk; S_k is the forward transform of src; S_k = delta_k when dk is null) into
+// out[c], then per component the Y pass and the real Z pass (in place, real result in
+// out[c]).  out[0] may alias src and out[1] may alias dk.
+void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* src,
                     float2* const out[3], hipStream_t s);
-// Screened source in Fourier space: X pass through `kind` (K_POT: Newtonian potential for
-// f(R); K_SMOOTH: smoothed density for nDGP) reading op.a and writing `data`, inverse Y
-// pass, one row pass doing inverse Z -> S = (rho - 1) eps -> forward Z, then forward Y and
-// X passes: `data` ends holding S_k.  s_out (optional, padded real) receives S.
-void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* data, const float* rho,
-                float* s_out, int model, float thr, float vx, hipStream_t s);
+// Screened source in Fourier space.  dk holds the density contrast after the forward Z
+// and Y passes: one X pass completes delta_k in place and applies `kind` (K_POT: Newtonian
+// potential for f(R); K_SMOOTH: smoothed density for nDGP) on the way back into `data`;
+// then the inverse Y pass, one row pass doing inverse Z -> S = (rho - 1) eps -> forward Z,
+// and the forward Y pass: `data` ends holding S after the forward Z and Y passes (its X
+// pass is done by fft_c2r_force3).  s_out (optional, padded real) receives S.
+void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* dk, float2* data,
+                const float* rho, float* s_out, int model, float thr, float vx, hipStream_t s);
 
 // ------------------------------------------------------------------ kernels (launchers)
 void launch_fill(float* p, size_t n, float v, hipStream_t s);
