@@ -107,7 +107,8 @@ struct Bufs {
   void* pk_scratch;
   float4* pk_out;
   unsigned long long* pk_cnt;
-  float2* mesh[5];
+  float2* mesh[6];
+  float* force;       // interleaved force mesh over slots 3-5
   float2* pf[6];
   float2* phi1;
   float2* phi2;
@@ -145,7 +146,8 @@ static Bufs carve(const cola_params& p, const cola_state* st) {
   b.pk_scratch = at<void>(st->tables, L.off_scratch);
   b.pk_out = at<float4>(st->tables, L.off_scratch + pk_scratch_bytes(L, 2048));
   b.pk_cnt = reinterpret_cast<unsigned long long*>(b.pk_out + 2048);
-  for (int i = 0; i < 5; ++i) b.mesh[i] = at<float2>(st->work, L.off_mesh[i]);
+  for (int i = 0; i < 6; ++i) b.mesh[i] = at<float2>(st->work, L.off_mesh[i]);
+  b.force = at<float>(st->work, L.off_mesh[3]);
   for (int i = 0; i < 6; ++i) b.pf[i] = L.kdep ? at<float2>(st->work, L.off_pfield[i]) : nullptr;
   b.bins = at<void>(st->work, L.off_bins);
   b.entries = at<float4>(st->work, L.off_entries);
@@ -192,10 +194,11 @@ static void do_prepare(const cola_params& p, cola_state* st, const Bufs& b, hipS
 }
 
 // ------------------------------------------------------------------ PM force core
-// Writes the three force meshes (real, padded) into mesh[0], mesh[3], mesh[4].
+// Writes the interleaved force mesh (b.force, over slots 3-5).
 // mesh[0] holds rho after the deposit; mesh[1] delta after the forward Z and Y passes,
 // then delta_k; mesh[2] the screening field and then S after the forward Z and Y passes;
-// the force components end in mesh[0], mesh[3] and mesh[4].  If flat_out is given, rho and S are copied there before being overwritten.
+// the three complex force components then take slots 0-2.  If flat_out is given, rho and
+// S are copied there before being overwritten.
 static void pm_core(const cola_params& p, const Bufs& b, const float* disp, double a,
                     float* flat_out, hipStream_t s) {
   const Layout& L = b.L;
@@ -234,8 +237,8 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
   op.g_5 = sc.fifth ? -sc.coupling * sc.kappa : 0.f;
   op.a2m2 = sc.a2m2;
   op.scale = invM;
-  float2* const outs[3] = {M[0], M[3], M[4]};
-  fft_c2r_force3(pl, op, dk, src, outs, s);
+  float2* const work[3] = {M[0], M[1], M[2]};
+  fft_c2r_force3(pl, op, dk, src, work, b.force, s);
 }
 
 }  // namespace cola
@@ -380,16 +383,10 @@ cola_status cola_pm_force(const cola_params* p, cola_state* st, double a, float*
     if (!st->prepared) throw Error{COLA_E_STATE, "state not prepared"};
     if (!(a > 0.0 && a <= 10.0)) throw Error{COLA_E_ARG, "a must be in (0, 10]"};
     pm_core(*p, b, st->disp, a, mesh_out, s);
-    if (mesh_out) {
-      launch_unpad_mesh(b.L, R(b.mesh[0]), mesh_out + 2 * b.L.M, s);
-      launch_unpad_mesh(b.L, R(b.mesh[3]), mesh_out + 3 * b.L.M, s);
-      launch_unpad_mesh(b.L, R(b.mesh[4]), mesh_out + 4 * b.L.M, s);
-    }
+    if (mesh_out) launch_split3(b.L, b.force, mesh_out + 2 * b.L.M, s);
     if (force_out) {
       GatherArgs g{};
-      g.F[0] = R(b.mesh[0]);
-      g.F[1] = R(b.mesh[3]);
-      g.F[2] = R(b.mesh[4]);
+      g.F3 = b.force;
       g.disp = st->disp;
       g.vel = st->vel;
       g.force_out = force_out;
@@ -442,9 +439,7 @@ cola_status cola_step(const cola_params* p, cola_state* st, int32_t i, hipStream
       g.psi2 = b.psi2;
     }
     pm_core(*p, b, st->disp, ai, nullptr, s);
-    g.F[0] = R(b.mesh[0]);
-    g.F[1] = R(b.mesh[3]);
-    g.F[2] = R(b.mesh[4]);
+    g.F3 = b.force;
     g.disp = st->disp;
     g.vel = st->vel;
     launch_gather(L, g, s);

@@ -348,13 +348,12 @@ k_fft_col_fwd_op(float2* __restrict__ data, float2* __restrict__ out, int64_t el
 // tile; the Green's function g = [g_n/k^2 delta_k + g_5/(k^2 + a^2 m^2) S_k] / M is formed
 // once per element (delta_k read from dk, or S_k itself when dk is null), kept in
 // registers, and each component -i k_c g is transformed in turn through the same tile and
-// written to its own array.  o0 may alias src and o1 may alias dk: every read of a column
+// written to its own array.  The outputs may alias dk and src: every read of a column
 // precedes the first write to it.
 template <int N>
 __global__ void __launch_bounds__(ColCfg<N>::T)
-k_fft_col_fwd_force3(const float2* dk, const float2* src, float2* o0, float2* o1,
-                     float2* __restrict__ o2, int64_t elemStride, const float2* __restrict__ tw_g,
-                     KOp op) {
+k_fft_col_fwd_force3(const float2* dk, const float2* src, float2* o0, float2* o1, float2* o2,
+                     int64_t elemStride, const float2* __restrict__ tw_g, KOp op) {
   constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
   constexpr int R0 = Plan<N>::rad[0], NB0 = E / R0;
   static_assert(T % B == 0, "a thread's butterflies must share one column");
@@ -504,6 +503,85 @@ k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nr
     if (r0 + c >= (O)nrows) continue;
     const O r = r0 + c;
     reinterpret_cast<float2*>(out + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[m] = lds[m * LS + c];
+  }
+}
+
+// Inverse Z pass of the three force components in one sweep, written as one interleaved
+// (F_x, F_y, F_z) mesh (unpadded rows), so that the CIC gather reads 24 contiguous bytes
+// per pair of cells instead of three separate meshes.  The work-group splits into three
+// thread groups, one per component, each transforming the same B rows through its own
+// LDS tile as in k_fft_c2r_row; then all threads write the B interleaved rows -- one
+// contiguous block -- with 16-byte stores read out of the three tiles.
+template <int NC>
+struct Row3Cfg {
+  static constexpr int E = Plan<NC>::E;
+  static constexpr int B = RowCfg<NC>::B >= 2 ? RowCfg<NC>::B / 2 : 1;
+  static constexpr int TC = NC * B / E;   // threads per component
+  static constexpr int T = 3 * TC;
+  static constexpr int LS = B + 1;
+};
+
+template <int NC>
+__global__ void __launch_bounds__(Row3Cfg<NC>::T)
+k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
+               const float2* __restrict__ in2, float* __restrict__ out, int64_t nrows,
+               int pitch, int64_t plane, const float2* __restrict__ tw) {
+  constexpr int B = Row3Cfg<NC>::B, E = Row3Cfg<NC>::E, TC = Row3Cfg<NC>::TC;
+  constexpr int T = Row3Cfg<NC>::T, LS = Row3Cfg<NC>::LS;
+  using O = Off<2 * NC>;
+  using O3 = typename std::conditional<(3ull * 8 * NC * NC * NC < (1ull << 32)), uint32_t,
+                                       uint64_t>::type;
+  constexpr int kN = 2 * NC;
+  constexpr int kRowF = 3 * kN;   // floats per interleaved row (a multiple of 4)
+  static_assert(kRowF % 4 == 0, "interleaved rows must hold whole float4s");
+  __shared__ float2 lds[3][NC * LS];
+  const int tid = threadIdx.x;
+  const int comp = tid / TC, lt = tid - comp * TC;
+  const float2* in = comp == 0 ? in0 : (comp == 1 ? in1 : in2);
+  float2* tile = lds[comp];
+  const O r0 = (O)blockIdx.x * B;
+  {
+    float2 xk[E], xc[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = lt + i * TC;
+      const int c = e / NC, k = e % NC;
+      xk[i] = make_float2(0.f, 0.f);
+      xc[i] = make_float2(0.f, 0.f);
+      if (r0 + c < (O)nrows) {
+        const O r = r0 + c;
+        const float2* row = in + (r / kN) * (O)plane + (r % kN) * (O)pitch;
+        xk[i] = row[k];
+        xc[i] = cconj(row[NC - k]);
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = lt + i * TC;
+      const int c = e / NC, k = e % NC;
+      const float2 sm = cadd(xk[i], xc[i]);
+      const float2 d = csub(xk[i], xc[i]);
+      const float2 t = cmul(cconj(tw[k]), d);   // exp(+2 pi i k / n) d
+      tile[k * LS + c] = make_float2(sm.x - t.y, sm.y + t.x);
+    }
+  }
+  __syncthreads();
+  lds_fft<NC, +1, E, B, LS, 2>(tile, lt, TC, tw);   // ends with a barrier
+  // element m of row c in tile t holds cells (2m, 2m + 1) of component t
+  const O rows_here = (O)nrows - r0 < (O)B ? (O)nrows - r0 : (O)B;
+  const int nq = (int)rows_here * (kRowF / 4);
+  float4* dst = reinterpret_cast<float4*>(out + (O3)r0 * kRowF);
+  for (int q = tid; q < nq; q += T) {
+    float v[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const int f = 4 * q + j;
+      const int c = f / kRowF, w = f % kRowF;
+      const int cell = w / 3, t = w % 3;
+      const float2 pr = lds[t][(cell >> 1) * LS + c];
+      v[j] = (cell & 1) ? pr.y : pr.x;
+    }
+    dst[q] = make_float4(v[0], v[1], v[2], v[3]);
   }
 }
 
@@ -702,7 +780,7 @@ void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* ou
 
 template <int N>
 static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, const float2* src,
-                        float2* const out[3], hipStream_t s) {
+                        float2* const work[3], float* f3, hipStream_t s) {
   const int n = pl.n, P = pl.pitch;
   const int64_t rows = (int64_t)n * n;
   constexpr int B = ColCfg<N>::B;
@@ -713,18 +791,20 @@ static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, c
   {
     ProfScope ps("fft_x_fwd_force3", s);
     hipLaunchKernelGGL((k_fft_col_fwd_force3<N>), dim3((unsigned)((int64_t)n * P / B)),
-                       dim3(ColCfg<N>::T), 0, s, dk, src, out[0], out[1], out[2], pl.plane, pl.tw, op);
+                       dim3(ColCfg<N>::T), 0, s, dk, src, work[0], work[1], work[2], pl.plane, pl.tw,
+                       op);
     COLA_LAUNCH_CHECK();
   }
   KOp none;
-  for (int c = 0; c < 3; ++c) {
-    col_pass<N, 1, K_COPY>(out[c], P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s,
+  for (int c = 0; c < 3; ++c)
+    col_pass<N, 1, K_COPY>(work[c], P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s,
                            "fft_y_inv");
-    ProfScope ps("fft_c2r_z", s);
-    constexpr int BR = RowCfg<N / 2>::B;
-    hipLaunchKernelGGL((k_fft_c2r_row<N / 2>), dim3((unsigned)((rows + BR - 1) / BR)),
-                       dim3(RowCfg<N / 2>::T), 0, s, out[c], reinterpret_cast<float*>(out[c]), rows, n,
-                       P, pl.plane, pl.tw);
+  {
+    ProfScope ps("fft_c2r_z3", s);
+    constexpr int BR = Row3Cfg<N / 2>::B;
+    hipLaunchKernelGGL((k_fft_c2r_row3<N / 2>), dim3((unsigned)((rows + BR - 1) / BR)),
+                       dim3(Row3Cfg<N / 2>::T), 0, s, work[0], work[1], work[2], f3, rows, P,
+                       pl.plane, pl.tw);
     COLA_LAUNCH_CHECK();
   }
 }
@@ -769,9 +849,9 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
 }
 
 void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* src,
-                    float2* const out[3], hipStream_t s) {
+                    float2* const work[3], float* f3, hipStream_t s) {
   switch (pl.n) {
-#define CASE(N_) case N_: force3_impl<N_>(pl, op, dk, src, out, s); return;
+#define CASE(N_) case N_: force3_impl<N_>(pl, op, dk, src, work, f3, s); return;
     CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
     CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
 #undef CASE

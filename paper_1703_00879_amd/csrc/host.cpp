@@ -204,7 +204,7 @@ Layout make_layout(const cola_params& p) {
   const size_t mesh_bytes = align_up(L.mesh_elems * sizeof(float2));
   const size_t pfield_bytes = align_up(L.pgrid_elems * sizeof(float2));
   o = 0;
-  for (int i = 0; i < 5; ++i) {
+  for (int i = 0; i < 6; ++i) {
     L.off_mesh[i] = o;
     o += mesh_bytes;
   }
@@ -217,8 +217,13 @@ Layout make_layout(const cola_params& p) {
   L.ntiles = (int64_t)L.nt1 * L.nt1 * L.nt1;
   L.off_bins = o;
   o += bins_bytes(L.ntiles);
-  L.off_entries = o;
-  o += align_up((size_t)L.N * sizeof(float4));
+  const size_t entries_bytes = align_up((size_t)L.N * sizeof(float4));
+  if (entries_bytes <= mesh_bytes) {
+    L.off_entries = L.off_mesh[5];   // dead before the force mesh is written
+  } else {
+    L.off_entries = o;
+    o += entries_bytes;
+  }
   L.work_bytes = o;
   L.disp_bytes = align_up((size_t)3 * L.N * sizeof(float));
   L.lpt_bytes = L.kdep ? 2 * pfield_bytes : 2 * L.disp_bytes;

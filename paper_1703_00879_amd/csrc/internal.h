@@ -72,8 +72,10 @@ struct Layout {
   // offsets (bytes) inside `tables`
   size_t off_growth, off_ref, off_tw_m, off_tw_p, off_scratch, tables_bytes;
   size_t scratch_bytes;
-  // offsets (bytes) inside `work`
-  size_t off_mesh[5], off_pfield[6], work_bytes;
+  // offsets (bytes) inside `work`: six mesh slots (padded half-complex / real meshes);
+  // the interleaved force mesh [nm][nm][nm][3] spans slots 3-5, and the sorted CIC
+  // records of the deposit reuse slot 5 when they fit there
+  size_t off_mesh[6], off_pfield[6], work_bytes;
   // binned deposit: tile edge (cells), tiles per axis, tile count, and the offsets of
   // the per-tile counters and of the particle-index list sorted by home tile
   int tile, nt1;
@@ -153,10 +155,11 @@ void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* ou
 // Forward X pass of `src` (Z and Y passes done) fused with the three inverse force
 // transforms: one X pass that forms -i k_c [Green's function of delta_k and S_k] (delta_k
 // read from dk; S_k is the forward transform of src; S_k = delta_k when dk is null) into
-// out[c], then per component the Y pass and the real Z pass (in place, real result in
-// out[c]).  out[0] may alias src and out[1] may alias dk.
+// work[c] (which may alias dk and src), the inverse Y pass of each component in place,
+// and one real Z pass over all three that writes the interleaved force mesh
+// f3[((x nm + y) nm + z) 3 + c] (unpadded).
 void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* src,
-                    float2* const out[3], hipStream_t s);
+                    float2* const work[3], float* f3, hipStream_t s);
 // Screened source in Fourier space.  dk holds the density contrast after the forward Z
 // and Y passes: one X pass completes delta_k in place and applies `kind` (K_POT: Newtonian
 // potential for f(R); K_SMOOTH: smoothed density for nDGP) on the way back into `data`;
@@ -190,7 +193,7 @@ size_t bins_bytes(int64_t ntiles);
 void launch_screen(const cola_params& p, const Layout& L, const StepScalars& sc,
                    const float* rho, float* field_inout, hipStream_t s);
 struct GatherArgs {
-  const float* F[3];
+  const float* F3;            // interleaved force mesh (F_x, F_y, F_z) per cell
   float* disp;
   float* vel;
   const float* psi1;          // scale-independent LPT (else null)
@@ -203,6 +206,8 @@ struct GatherArgs {
   float* force_out;           // cola_pm_force: write F_p instead of updating
 };
 void launch_gather(const Layout& L, const GatherArgs& g, hipStream_t s);
+// the three components of the interleaved force mesh into flat [3][nm^3]
+void launch_split3(const Layout& L, const float* f3, float* flat, hipStream_t s);
 // flat = padded - sub over the n^3 valid cells
 void launch_unpad_mesh(const Layout& L, const float* padded, float* flat, hipStream_t s,
                        float sub = 0.f);

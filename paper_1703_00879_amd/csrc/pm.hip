@@ -461,7 +461,7 @@ void launch_screen(const cola_params& p, const Layout& L, const StepScalars& sc,
 
 // ------------------------------------------------------------------ gather + kick + drift
 struct GatherDev {
-  const float* F0; const float* F1; const float* F2;
+  const float* F3;   // interleaved force mesh, 3 floats per cell, unpadded rows
   float* disp; float* vel;
   const float* psi1; const float* psi2;
   const float* l0; const float* l1; const float* l2;
@@ -478,8 +478,8 @@ struct GatherDev {
 // MODE 2: force only (write F_p).
 template <int MODE>
 __global__ void __launch_bounds__(256)
-k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int rpitch,
-         int64_t rplane, int ppitch, int64_t pplane) {
+k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int ppitch,
+         int64_t pplane) {
   // consecutive particle chunks read overlapping mesh rows: keep them on one XCD
   const int64_t p = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
   if (p >= N) return;
@@ -494,12 +494,13 @@ k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int 
     for (int oy = 0; oy < 2; ++oy) {
       const int64_t y = oy ? c.i1[1] : c.i0[1];
       const float wxy = wx * (oy ? c.w1[1] : c.w0[1]);
-      const int64_t row = x * rplane + y * rpitch;
-      const int64_t a0 = row + c.i0[2], a1 = row + c.i1[2];
+      const int64_t row = (x * nm + y) * nm;
+      const float* a = g.F3 + 3 * (row + c.i0[2]);
+      const float* b = g.F3 + 3 * (row + c.i1[2]);
       const float wa = wxy * c.w0[2], wb = wxy * c.w1[2];
-      f0 += wa * g.F0[a0] + wb * g.F0[a1];
-      f1 += wa * g.F1[a0] + wb * g.F1[a1];
-      f2 += wa * g.F2[a0] + wb * g.F2[a1];
+      f0 += wa * a[0] + wb * b[0];
+      f1 += wa * a[1] + wb * b[1];
+      f2 += wa * a[2] + wb * b[2];
     }
   }
   if (MODE == 2) {
@@ -537,7 +538,7 @@ k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int 
 
 void launch_gather(const Layout& L, const GatherArgs& a, hipStream_t s) {
   GatherDev g;
-  g.F0 = a.F[0]; g.F1 = a.F[1]; g.F2 = a.F[2];
+  g.F3 = a.F3;
   g.disp = a.disp; g.vel = a.vel;
   g.psi1 = a.psi1; g.psi2 = a.psi2;
   g.l0 = a.lpp[0]; g.l1 = a.lpp[1]; g.l2 = a.lpp[2];
@@ -550,16 +551,32 @@ void launch_gather(const Layout& L, const GatherArgs& a, hipStream_t s) {
   if (a.force_out) {
     ProfScope ps("gather_force", s);
     hipLaunchKernelGGL(k_gather<2>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_m, 2 * L.plane_m, 2 * L.pitch_p, 2 * L.plane_p);
+                       2 * L.pitch_p, 2 * L.plane_p);
   } else if (a.psi1) {
     ProfScope ps("gather_kick_drift", s);
     hipLaunchKernelGGL(k_gather<0>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_m, 2 * L.plane_m, 2 * L.pitch_p, 2 * L.plane_p);
+                       2 * L.pitch_p, 2 * L.plane_p);
   } else {
     ProfScope ps("gather_kick_drift", s);
     hipLaunchKernelGGL(k_gather<1>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_m, 2 * L.plane_m, 2 * L.pitch_p, 2 * L.plane_p);
+                       2 * L.pitch_p, 2 * L.plane_p);
   }
+  COLA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ force mesh read-out
+__global__ void k_split3(const float* __restrict__ f3, float* __restrict__ flat, int64_t M) {
+  for (int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; i < M;
+       i += (int64_t)gridDim.x * blockDim.x) {
+    flat[i] = f3[3 * i];
+    flat[M + i] = f3[3 * i + 1];
+    flat[2 * M + i] = f3[3 * i + 2];
+  }
+}
+
+void launch_split3(const Layout& L, const float* f3, float* flat, hipStream_t s) {
+  ProfScope ps("split3", s);
+  hipLaunchKernelGGL(k_split3, dim3(grid_for(L.M, 256)), dim3(256), 0, s, f3, flat, L.M);
   COLA_LAUNCH_CHECK();
 }
 
