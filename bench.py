@@ -51,11 +51,13 @@ def algorithmic_bytes(name, p):
         "fft_r2c_z": 4 * M + 8 * H,                  # read real mesh, write half-complex
         "fft_c2r_z": 8 * H + 4 * M,
         "fft_y_fwd": 16 * H, "fft_x_fwd": 16 * H, "fft_y_inv": 16 * H,
-        "fft_x_inv_smooth": 16 * H,                  # read delta_k, write W delta_k pass
-        "fft_x_inv_pot": 16 * H,
-        "fft_z_screen": 8 * H + 4 * M + 8 * H,       # read delta_R and rho, write S_k pass
-        "fft_x_inv_force3": 16 * H + 24 * H,         # read delta_k, S_k; write 3 force passes
-        "gather_kick_drift": 12 * M + 72 * N,        # 3 force meshes; u, v, Psi1, Psi2 in; u, v out
+        "fft_x_fwd_smooth": 8 * H + 16 * H,          # read delta; write delta_k and W delta_k
+        "fft_x_fwd_pot": 8 * H + 16 * H,
+        "fft_z_screen": 8 * H + 4 * M + 8 * H,       # read delta_R and rho, write S
+        "fft_x_fwd_force3": 16 * H + 24 * H,         # read S and delta_k; write 3 force passes
+        "fft_c2r_z3": 24 * H + 12 * M,               # read 3 force passes, write (Fx, Fy, Fz)
+        "gather_kick_drift": 12 * M + 72 * N,        # force mesh; u, v, Psi1, Psi2 in; u, v out
+        "fill": 0,
     }
     return table.get(name)
 
@@ -94,7 +96,117 @@ def traffic_for(kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
-def cpu_baseline(steps=3):
+# rocprofv3 kernel symbols of one step -> the names the library's HIP-event profiler uses
+_SYMBOLS = [("k_fft_col_fwd_force3", "fft_x_fwd_force3"), ("k_fft_col_fwd_op<{n}, 3>", "fft_x_fwd_smooth"),
+            ("k_fft_col_fwd_op<{n}, 2>", "fft_x_fwd_pot"), ("k_fft_col<{n}, -1, 0>", "fft_y_fwd"),
+            ("k_fft_col<{n}, 1, 0>", "fft_y_inv"), ("k_fft_c2r_row3", "fft_c2r_z3"),
+            ("k_fft_screen_row", "fft_z_screen"), ("k_fft_r2c_row", "fft_r2c_z"),
+            ("k_gather", "gather_kick_drift"), ("k_deposit_tiles", "deposit"), ("k_bin<0>", "bin_count"),
+            ("k_bin<1>", "bin_scatter"), ("k_scan_", "bin_scan"), ("k_fill", "fill")]
+
+
+def _profile_name(symbol, n):
+    for pat, name in _SYMBOLS:
+        if pat.format(n=n) in symbol:
+            return name
+    return symbol.split("(")[0].replace("void ", "")
+
+
+def summarize_rocprof(d, out_dir):
+    """Condense the rocprofv3 runs of `python3 bench.py --steps 2 --warmup 1 --no-profile`
+    under directory d (trace/, fetch/, write/: kernel trace and FETCH_SIZE / WRITE_SIZE
+    counters; cfetch/, cwrite/: the same counters for `bench.py --calibrate-copy`) into
+    per-kernel figures of the two timed steps, written to out_dir as a markdown table and
+    the traffic file bench.py reads."""
+    import csv
+    from collections import defaultdict
+    from paper_1703_00879_amd import cola as C
+    p = workload_params(C)
+    n = p.nmesh1d
+
+    def rows(path):
+        with open(path) as f:
+            return list(csv.DictReader(f))
+
+    def step_window(recs, key):
+        """Dispatch ids after the first gather (end of the warm-up step) up to the last."""
+        ids = sorted(int(r["Dispatch_Id"]) for r in recs if "k_gather" in r[key])
+        return ids[0], ids[-1], len(ids) - 1
+
+    tr = rows(os.path.join(d, "trace", "trace_kernel_trace.csv"))
+    lo, hi, nsteps = step_window(tr, "Kernel_Name")
+    dur = defaultdict(list)
+    for r in tr:
+        i = int(r["Dispatch_Id"])
+        if lo < i <= hi:
+            dur[_profile_name(r["Kernel_Name"], n)].append(
+                (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
+
+    def counter(sub, name):
+        recs = rows(os.path.join(d, sub, f"{sub}_counter_collection.csv"))
+        a, b, _ = step_window(recs, "Kernel_Name")
+        acc = defaultdict(list)
+        for r in recs:
+            if a < int(r["Dispatch_Id"]) <= b and r["Counter_Name"] == name:
+                acc[_profile_name(r["Kernel_Name"], n)].append(float(r["Counter_Value"]))
+        return acc
+
+    def copy_factor(sub, name):
+        recs = rows(os.path.join(d, sub, f"{sub}_counter_collection.csv"))
+        v = [float(r["Counter_Value"]) for r in recs
+             if "copyBuffer" in r["Kernel_Name"] and r["Counter_Name"] == name]
+        v = [x for x in v if x > 1e5]   # the 1 GiB copies, not small staging copies
+        return (4 * (1 << 28) / 1024) / (sum(v) / len(v))
+
+    fetch, write = counter("fetch", "FETCH_SIZE"), counter("write", "WRITE_SIZE")
+    kf, kw = copy_factor("cfetch", "FETCH_SIZE"), copy_factor("cwrite", "WRITE_SIZE")
+    kern = {}
+    for name, ds in dur.items():
+        fb = 1024 * kf * sum(fetch[name]) / len(fetch[name]) if fetch.get(name) else None
+        wb = 1024 * kw * sum(write[name]) / len(write[name]) if write.get(name) else None
+        kern[name] = {"launches_per_step": len(ds) / nsteps, "avg_ms": sum(ds) / len(ds),
+                      "ms_per_step": sum(ds) / nsteps,
+                      "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
+                      "bytes_per_launch": (fb + wb) if fb is not None and wb is not None else None,
+                      "algorithmic_bytes_per_launch": algorithmic_bytes(name, p)}
+    cmd = ("cd /tmp && export TMPDIR=/tmp; B=\"python3 $REPO/bench.py --steps 2 --warmup 1 "
+           "--no-cpu-baseline --no-profile\"; "
+           "rocprofv3 --kernel-trace --stats --output-format csv -d $D/trace -o trace -- $B; "
+           "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $D/fetch -o fetch -- $B; "
+           "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $D/write -o write -- $B; "
+           "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $D/cfetch -o cfetch -- "
+           "python3 $REPO/bench.py --calibrate-copy; "
+           "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $D/cwrite -o cwrite -- "
+           "python3 $REPO/bench.py --calibrate-copy; "
+           "python3 $REPO/bench.py --summarize-rocprof $D")
+    traffic = {"source_hash": source_hash(), "workload": "nDGP 512^3 particles, 1024^3 mesh",
+               "fetch_scale": kf, "write_scale": kw, "command": cmd, "kernels": kern}
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, "traffic_ndgp_512_1024.json"), "w") as f:
+        json.dump(traffic, f, indent=1)
+    tot = sum(k["ms_per_step"] for k in kern.values())
+    lines = ["# PM step kernels, nDGP 512^3 particles / 1024^3 mesh (rocprofv3)", "",
+             f"Source hash {traffic['source_hash']}; {nsteps} timed steps after one warm-up step.",
+             "", "Command (from the repository root on the GPU host, D = output directory):", "",
+             "```", cmd.replace("; ", "\n"), "```", "",
+             f"HBM bytes = FETCH_SIZE x {kf:.3f} + WRITE_SIZE x {kw:.3f} (KiB per dispatch), the "
+             "factors that make the counters of a plain 1 GiB device copy read 1 GiB each.", "",
+             "| kernel | launches/step | avg ms | ms/step | % | HBM GB/launch | algorithmic GB/launch "
+             "| HBM GB/s | algorithmic GB/s |", "|---|---|---|---|---|---|---|---|---|"]
+    for name, k in sorted(kern.items(), key=lambda kv: -kv[1]["ms_per_step"]):
+        hb, ab = k["bytes_per_launch"], k["algorithmic_bytes_per_launch"]
+        g = lambda x: "-" if x is None else f"{x / 1e9:.2f}"  # noqa: E731
+        r = lambda x: "-" if x is None else f"{x / 1e9 / (k['avg_ms'] / 1e3):.0f}"  # noqa: E731
+        lines.append(f"| {name} | {k['launches_per_step']:g} | {k['avg_ms']:.3f} | "
+                     f"{k['ms_per_step']:.2f} | {100 * k['ms_per_step'] / tot:.1f} | {g(hb)} | {g(ab)} "
+                     f"| {r(hb)} | {r(ab)} |")
+    lines += ["", f"Sum of kernel time per step: {tot:.2f} ms."]
+    with open(os.path.join(out_dir, "pm_step_ndgp_512_1024.md"), "w") as f:
+        f.write("\n".join(lines) + "\n")
+    return traffic
+
+
+def cpu_baseline(steps=8):
     """The FP64 oracle on the host: the same workload (nDGP r_c H0 = 1, screened,
     2 Mpc/h particle spacing, 1 Mpc/h cells, 30-step time grid, same seed) on a
     128^3-particle / 256^3-mesh / 256 Mpc/h sub-box, timing `steps` COLA steps."""
@@ -124,10 +236,16 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not record per-kernel HIP events in the timed region")
+    ap.add_argument("--summarize-rocprof", metavar="DIR",
+                    help="condense rocprofv3 output under DIR into profiles/ and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (three times), the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
     args = ap.parse_args()
+    if args.summarize_rocprof:
+        t = summarize_rocprof(args.summarize_rocprof, os.path.join(ROOT, "profiles"))
+        print(json.dumps({k: v["bytes_per_launch"] for k, v in t["kernels"].items()}))
+        return
     if args.calibrate_copy:
         import torch
         n = 1 << 28
