@@ -77,7 +77,10 @@ typedef struct cola_params {
 typedef struct cola_sizes {
   size_t disp_bytes;    /* float [3][N] */
   size_t vel_bytes;     /* float [3][N] */
-  size_t lpt_bytes;     /* LPT store: Psi1, Psi2 per particle, or phi1_k, phi2_k */
+  size_t lpt_bytes;     /* LPT store.  k-independent growth: Psi1 float [3][N] at byte 0
+                           and Psi2 float [3][N] at byte disp_bytes.  Scale-dependent
+                           growth: phi1_k and phi2_k, padded half-complex fields on the
+                           particle grid, the second at half of lpt_bytes */
   size_t tables_bytes;  /* FP64 growth tables, FFT twiddles, reduction scratch */
   size_t work_bytes;    /* PM meshes and particle-grid temporaries */
   size_t total_bytes;

@@ -1,0 +1,237 @@
+"""Full-size GPU checks at the benchmark workload and at the largest supported mesh.
+
+The benchmark workload runs in the same launch configuration bench.py times: nDGP with
+r_c H0 = 1 and Vainshtein screening (Gaussian smoothing, R = 1 Mpc/h), 512^3 particles,
+a 1024^3 mesh, L = 1024 Mpc/h and 30 steps.
+
+The FP64 oracle cannot run a 1024^3 mesh, so two checks use planar configurations. There
+the oracle's 1D reduction (oracle.planar, pinned against the 3D oracle) gives every cell
+and every particle exactly.
+- PM force: every cell of the density, screened-source and three force meshes and every
+  particle force is compared, for displacements along each of the three axes.
+- One COLA step: every particle's displacement and velocity is compared.
+
+The white noise and the scale-dependent growth table are checked on samples the oracle
+computes one by one.
+
+Tolerances are those of test_gpu_parity:
+- meshes and forces: 1e-5 relative rms (screened source 1e-4);
+- positions: 1e-3 cells rms;
+- growth tables: 1e-10.
+"""
+
+import gc
+import math
+
+import numpy as np
+import pytest
+
+from oracle.growth import solve_growth
+from oracle.models import Model
+from oracle.planar import planar_pm, planar_step
+from oracle.rng import splitmix64, to_unit
+from paper_1703_00879_amd import cola as C
+from tests.test_gpu_parity import record, to_oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+WORKLOAD = C.Params(model=C.NDGP, rc_h0=1.0, screening=1, filter=C.SMOOTH_GAUSS, r_smooth=1.0,
+                    np1d=512, nmesh1d=1024, box=1024.0, z_init=19.0, n_steps=30, seed=1)
+
+
+@pytest.fixture(autouse=True)
+def _release_memory():
+    yield
+    gc.collect()
+    torch.cuda.empty_cache()
+
+
+def profile(n_p, box, seed, amp=1.0):
+    """Per-plane displacement profile (Mpc/h): three sine modes plus seeded jitter."""
+    q = np.arange(n_p) * box / n_p
+    rng = np.random.default_rng(seed)
+    return amp * (5.0 * np.sin(2 * np.pi * 3 * q / box) + 1.5 * np.cos(2 * np.pi * 17 * q / box + 0.4)
+                  + 0.3 * np.sin(2 * np.pi * 150 * q / box) + 0.5 * rng.standard_normal(n_p))
+
+
+def planar_view(x, ax, n):
+    """(n, n, n) view of a flat n^3 tensor and the broadcast shape of a profile along ax."""
+    shape = [1, 1, 1]
+    shape[ax] = n
+    return x.view(n, n, n), shape
+
+
+def fill_planar(dst_flat, prof, ax, n):
+    """dst (n^3 flat) <- prof broadcast along axis ax."""
+    v, shape = planar_view(dst_flat, ax, n)
+    v.copy_(torch.from_numpy(prof.astype(np.float32)).to(v.device).view(shape).expand(n, n, n))
+
+
+def relrms_planar(flat, prof, ax, n, chunk=64):
+    """||flat - broadcast(prof)|| / ||broadcast(prof)|| over the n^3 values, in FP64."""
+    v, shape = planar_view(flat, ax, n)
+    e = torch.from_numpy(np.asarray(prof, dtype=np.float64)).to(flat.device).view(shape)
+    num = den = 0.0
+    for x0 in range(0, n, chunk):
+        blk = v[x0:x0 + chunk].double()
+        eb = e[x0:x0 + chunk] if ax == 0 else e
+        d = blk - eb
+        num += float((d * d).sum())
+        den += float((eb * eb).expand_as(blk).sum())
+    return math.sqrt(num / den)
+
+
+def rms(flat, chunk=1 << 26):
+    s = 0.0
+    for i in range(0, flat.numel(), chunk):
+        b = flat[i:i + chunk].double()
+        s += float((b * b).sum())
+    return math.sqrt(s / flat.numel())
+
+
+@pytest.mark.parametrize("ax", [0, 1, 2])
+def test_fullsize_planar_pm_force(ax):
+    p = WORKLOAD
+    n, n_p = p.nmesh1d, p.np1d
+    N, M = n_p ** 3, n ** 3
+    st = C.State(p)
+    C.cola_prepare(p, st)
+    u1 = profile(n_p, p.box, seed=ax)
+    st.disp_f.zero_()
+    fill_planar(st.disp_f[ax], u1, ax, n_p)
+    F = torch.empty(3, N, dtype=torch.float32, device="cuda")
+    mesh = torch.empty(5, M, dtype=torch.float32, device="cuda")
+    a = 0.75
+    C.cola_pm_force(p, st, a, F, mesh)
+    torch.cuda.synchronize()
+    pl = planar_pm(u1.astype(np.float32).astype(np.float64), to_oracle(p), a)
+    # the fixed-point deposit makes every cell of a plane bitwise equal
+    v, _ = planar_view(mesh[0], ax, n)
+    others = tuple(d for d in range(3) if d != ax)
+    assert float((torch.amax(v, dim=others) - torch.amin(v, dim=others)).abs().max()) == 0.0
+    e = dict(rho=relrms_planar(mesh[0], pl["rho"], ax, n),
+             src=relrms_planar(mesh[1], pl["src"], ax, n),
+             f=relrms_planar(mesh[2 + ax], pl["force"], ax, n),
+             fp=relrms_planar(F[ax], pl["fp"], ax, n_p))
+    scale_mesh, scale_p = rms(mesh[2 + ax]), rms(F[ax])
+    e["f_across"] = max(rms(mesh[2 + o]) for o in others) / scale_mesh
+    e["fp_across"] = max(rms(F[o]) for o in others) / scale_p
+    record(f"fullsize_planar_pm_force_ax{ax}", **e)
+    assert e["rho"] < 1e-5 and e["src"] < 1e-4 and e["f"] < 1e-5 and e["fp"] < 1e-5, e
+    assert e["f_across"] < 1e-5 and e["fp_across"] < 1e-5, e
+
+
+def test_fullsize_planar_step():
+    """One cola_step (step 20 of 30) of the benchmark workload on a planar state: u, v,
+    Psi1, Psi2 along x as functions of the lattice index ix."""
+    p = WORKLOAD
+    n_p, N = p.np1d, p.np1d ** 3
+    st = C.State(p)
+    C.cola_prepare(p, st)
+    u1 = profile(n_p, p.box, seed=5).astype(np.float32).astype(np.float64)
+    v1 = (0.2 * profile(n_p, p.box, seed=6)).astype(np.float32).astype(np.float64)
+    psi1 = (0.6 * profile(n_p, p.box, seed=7)).astype(np.float32).astype(np.float64)
+    psi2 = (-0.1 * profile(n_p, p.box, seed=8)).astype(np.float32).astype(np.float64)
+    st.disp_f.zero_()
+    st.vel_f.zero_()
+    fill_planar(st.disp_f[0], u1, 0, n_p)
+    fill_planar(st.vel_f[0], v1, 0, n_p)
+    # per-particle LPT store of k-independent growth: Psi1 [3][N] at 0, Psi2 at disp_bytes
+    lptf = st.lpt.view(torch.float32)
+    off2 = st.sizes["disp_bytes"] // 4
+    P1, P2 = lptf[:3 * N].view(3, N), lptf[off2:off2 + 3 * N].view(3, N)
+    P1.zero_()
+    P2.zero_()
+    fill_planar(P1[0], psi1, 0, n_p)
+    fill_planar(P2[0], psi2, 0, n_p)
+    i = 20
+    st.c.next_step = i
+    C.cola_step(p, st, i)
+    torch.cuda.synchronize()
+    assert st.next_step == i + 1
+    u_or, v_or = planar_step(u1, v1, psi1, psi2, to_oracle(p), i)
+    cell = p.box / p.nmesh1d
+    e = dict(u_cells=relrms_planar(st.disp_f[0], u_or, 0, n_p) * rms_np(u_or) / cell,
+             v=relrms_planar(st.vel_f[0], v_or, 0, n_p),
+             u_across_cells=max(rms(st.disp_f[1]), rms(st.disp_f[2])) / cell)
+    record("fullsize_planar_step", **e)
+    assert e["u_cells"] < 1e-3 and e["v"] < 1e-5 and e["u_across_cells"] < 1e-3, e
+
+
+def rms_np(x):
+    return float(np.sqrt(np.mean(np.asarray(x, dtype=np.float64) ** 2)))
+
+
+def test_fullsize_white_noise_samples():
+    """The 512^3 particle-grid white noise at 20000 sampled grid points equals the
+    oracle's SplitMix64 / Box-Muller value there (integer stream exact; FP32 Box-Muller)."""
+    p = WORKLOAD
+    N = p.np1d ** 3
+    out = torch.empty(N, dtype=torch.float32, device="cuda")
+    C.cola_white_noise(p, out)
+    torch.cuda.synchronize()
+    j = np.unique(np.random.default_rng(3).integers(0, N, 20000)).astype(np.uint64)
+    j = np.concatenate([j, np.array([0, N - 1], dtype=np.uint64)])
+    u0 = to_unit(splitmix64(p.seed, 2 * j))
+    u1 = to_unit(splitmix64(p.seed, 2 * j + np.uint64(1)))
+    ref = np.sqrt(-2.0 * np.log(u0)) * np.cos(2.0 * np.pi * u1)
+    g = out[torch.from_numpy(j.astype(np.int64)).cuda()].cpu().numpy().astype(np.float64)
+    err = np.max(np.abs(g - ref) / np.maximum(1.0, np.abs(ref)))
+    record("fullsize_white_noise", max_err=err)
+    assert err < 2e-5
+
+
+def test_fullsize_scale_dependent_growth_table_samples():
+    """f(R) F5 on the 512^3 particle grid (196609 distinct |nu|^2 per slice): sampled
+    entries of three slices against the oracle's ODE solution at those k."""
+    p = WORKLOAD.with_(model=C.FR_HS1, fr0_abs=1e-5)
+    st = C.State(p)
+    C.cola_prepare(p, st)
+    po = to_oracle(p)
+    model = Model(po)
+    n2 = np.array([0, 1, 2, 3, 17, 250, 4096, 33333, 100000, 196608])
+    k = 2.0 * np.pi * np.sqrt(n2.astype(np.float64)) / p.box
+    a_grid = po.a_ini + np.arange(p.n_steps + 1) * (1.0 - po.a_ini) / p.n_steps
+    G = solve_growth(k, a_grid, po.omega_m, model.mu, model.gamma2_orth, po.a_ini)
+    worst = 0.0
+    for i in (0, 11, p.n_steps):
+        tab = C.cola_growth_table(p, st, i)
+        assert tab.shape == (3 * (p.np1d // 2) ** 2 + 1, 6)
+        ref = G[i]
+        got = tab[n2]
+        rel = np.abs(got - ref) / np.maximum(np.abs(ref), 1e-300)
+        rel[ref == 0] = np.abs(got[ref == 0])
+        worst = max(worst, float(rel.max()))
+    record("fullsize_growth_table", max_rel=worst)
+    assert worst < 1e-10
+
+
+def test_maximum_size_planar_forces():
+    """The largest supported configuration, 1024^3 particles on a 2048^3 mesh (64-bit
+    element offsets in every FFT pass): per-particle planar forces of nDGP with Vainshtein
+    screening against the oracle's 1D reduction.  Skipped if the device has too little
+    free memory for the ~265 GB state."""
+    p = WORKLOAD.with_(np1d=1024, nmesh1d=2048, box=2048.0)
+    n_p, N = p.np1d, p.np1d ** 3
+    sizes = C.cola_query_sizes(p)
+    gc.collect()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    need = sizes["total_bytes"] + 12 * N + 5 * 256 + (4 << 30)
+    if free < need:
+        pytest.skip(f"needs {need / 1e9:.0f} GB of device memory, {free / 1e9:.0f} GB free")
+    st = C.State(p)
+    C.cola_prepare(p, st)
+    u1 = profile(n_p, p.box, seed=9)
+    st.disp_f.zero_()
+    fill_planar(st.disp_f[0], u1, 0, n_p)
+    F = torch.empty(3, N, dtype=torch.float32, device="cuda")
+    a = 0.9
+    C.cola_pm_force(p, st, a, F, None)
+    torch.cuda.synchronize()
+    pl = planar_pm(u1.astype(np.float32).astype(np.float64), to_oracle(p), a)
+    e = dict(fp=relrms_planar(F[0], pl["fp"], 0, n_p),
+             fp_across=max(rms(F[1]), rms(F[2])) / rms(F[0]))
+    record("maximum_size_planar_forces", **e)
+    assert e["fp"] < 1e-5 and e["fp_across"] < 1e-5, e

@@ -86,3 +86,28 @@ def test_tiny_mode_grows_with_scale_dependent_D1(box):
     if box == 25.0:
         _, D_f = _tiny_mode_run(base.with_(model=MODEL_FR), 1)
         assert D_f / D_l > 1.08
+
+
+def test_planar_step_equals_3d_step():
+    """Two steps of Run.step on a planar configuration (displacement, Psi1 and Psi2 along
+    x, functions of the lattice index ix) equal planar_step on the 1D profiles."""
+    from oracle.pm import lagrangian_index
+    from oracle.planar import planar_step
+    p = Params(model=MODEL_NDGP, rc_h0=1.0, np1d=16, nmesh1d=32, box=64.0, n_steps=6)
+    q = np.arange(p.np1d) * p.box / p.np1d
+    psi1 = 3.0 * np.sin(2 * np.pi * q / p.box) + 0.5 * np.sin(2 * np.pi * 3 * q / p.box)
+    psi2 = -0.7 * np.sin(2 * np.pi * 2 * q / p.box)
+    ix = lagrangian_index(p.np1d)[0]
+    P1 = np.zeros((3, p.n_part))
+    P2 = np.zeros((3, p.n_part))
+    P1[0], P2[0] = psi1[ix], psi2[ix]
+    r = Run(p, lpt=dict(psi1=P1, psi2=P2))
+    u1 = r.G[0, 0, 0] * psi1 + r.G[0, 0, 3] * psi2
+    v1 = np.zeros(p.np1d)
+    for i in range(2):
+        r.step()
+        u1, v1 = planar_step(u1, v1, psi1, psi2, p, i)
+        scale = np.abs(u1).max()
+        assert np.abs(r.u[0] - u1[ix]).max() < 1e-11 * scale
+        assert np.abs(r.v[0] - v1[ix]).max() < 1e-11 * np.abs(v1).max()
+        assert np.abs(r.u[1:]).max() < 1e-11 * scale and np.abs(r.v[1:]).max() < 1e-11 * scale

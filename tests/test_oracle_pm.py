@@ -252,3 +252,57 @@ def test_pair_force_vs_ewald(r):
         errs.append(np.linalg.norm(got - want) / np.linalg.norm(want))
     assert np.mean(ratios) == pytest.approx(1.0, abs=0.02)
     assert np.median(errs) < 0.03
+
+
+# ----------------------------------------------------------------------------- planar reduction
+from oracle.pm import lagrangian_index  # noqa: E402
+from oracle.planar import planar_pm  # noqa: E402
+
+
+def _planar_profile(n_p, box, seed):
+    """Per-plane displacements: two sine modes plus seeded jitter (Mpc/h)."""
+    q = np.arange(n_p) * box / n_p
+    rng = np.random.default_rng(seed)
+    return (2.5 * np.sin(2 * np.pi * 2 * q / box) + 0.8 * np.cos(2 * np.pi * 5 * q / box + 0.3)
+            + 0.4 * rng.standard_normal(n_p))
+
+
+PLANAR_CASES = {
+    "lcdm_r2": dict(model=MODEL_LCDM, np1d=16, nmesh1d=32, box=64.0),
+    "ndgp_gauss_r2": dict(model=MODEL_NDGP, rc_h0=1.0, np1d=16, nmesh1d=32, box=32.0),
+    "ndgp_tophat_r2": dict(model=MODEL_NDGP, rc_h0=2.0, filter=1, r_smooth=2.0, np1d=16,
+                           nmesh1d=32, box=40.0),
+    "fr_screened_r1": dict(model=MODEL_FR, fr0_abs=1e-7, np1d=24, nmesh1d=24, box=60.0),
+    "fr_unscreened_r2": dict(model=MODEL_FR, fr0_abs=1e-5, screening=0, np1d=12, nmesh1d=24,
+                             box=48.0),
+}
+
+
+@pytest.mark.parametrize("name", list(PLANAR_CASES))
+def test_planar_reduction_equals_3d_oracle(name):
+    """Particles displaced along one axis by a function of their lattice index along it:
+    the 3D oracle's density, screened source and force meshes and per-particle forces
+    equal the 1D planar computation broadcast over the other two axes, with zero force
+    across the axis -- for each of the three axes."""
+    p = Params(**PLANAR_CASES[name])
+    n, N = p.nmesh1d, p.n_part
+    u1 = _planar_profile(p.np1d, p.box, seed=sorted(PLANAR_CASES).index(name))
+    idx = lagrangian_index(p.np1d)
+    a = 0.8
+    pl = planar_pm(u1, p, a)
+    scale = np.abs(pl["force"]).max()
+    assert scale > 0
+    for ax in range(3):
+        u = np.zeros((3, N))
+        u[ax] = u1[idx[ax]]
+        Fp, m = pm_force(u, p, a)
+        shape = [n if i == ax else 1 for i in range(3)]
+        b = lambda prof: np.broadcast_to(prof.reshape(shape), (n, n, n))  # noqa: E731
+        assert np.abs(m["rho"] - b(pl["rho"])).max() < 1e-12
+        assert np.abs(m["src"] - b(pl["src"])).max() < 1e-12
+        assert np.abs(m["force"][ax] - b(pl["force"])).max() < 1e-11 * scale
+        assert np.abs(Fp[ax] - pl["fp"][idx[ax]]).max() < 1e-11 * scale
+        for o in range(3):
+            if o != ax:
+                assert np.abs(m["force"][o]).max() < 1e-11 * scale
+                assert np.abs(Fp[o]).max() < 1e-11 * scale
