@@ -54,7 +54,8 @@ def algorithmic_bytes(name, p):
         "fft_x_fwd_smooth": 8 * H + 16 * H,          # read delta; write delta_k and W delta_k
         "fft_x_fwd_pot": 8 * H + 16 * H,
         "fft_z_screen": 8 * H + 4 * M + 8 * H,       # read delta_R and rho, write S
-        "fft_x_fwd_force3": 16 * H + 24 * H,         # read S and delta_k; write 3 force passes
+        "fft_x_fwd_force": 16 * H + 16 * H,          # read S and delta_k; write G0 and G
+        "fft_y_inv_yz": 8 * H + 16 * H,              # read G; write the y and z components
         "fft_c2r_z3": 24 * H + 12 * M,               # read 3 force passes, write (Fx, Fy, Fz)
         "gather_kick_drift": 12 * M + 72 * N,        # force mesh; u, v, Psi1, Psi2 in; u, v out
         "fill": 0,
@@ -97,7 +98,7 @@ def traffic_for(kernel):
 
 
 # rocprofv3 kernel symbols of one step -> the names the library's HIP-event profiler uses
-_SYMBOLS = [("k_fft_col_fwd_force3", "fft_x_fwd_force3"), ("k_fft_col_fwd_op<{n}, 3>", "fft_x_fwd_smooth"),
+_SYMBOLS = [("k_fft_col_fwd_force", "fft_x_fwd_force"), ("k_fft_col_inv_yz", "fft_y_inv_yz"), ("k_fft_col_fwd_op<{n}, 3>", "fft_x_fwd_smooth"),
             ("k_fft_col_fwd_op<{n}, 2>", "fft_x_fwd_pot"), ("k_fft_col<{n}, -1, 0>", "fft_y_fwd"),
             ("k_fft_col<{n}, 1, 0>", "fft_y_inv"), ("k_fft_c2r_row3", "fft_c2r_z3"),
             ("k_fft_screen_row", "fft_z_screen"), ("k_fft_r2c_row", "fft_r2c_z"),

@@ -344,16 +344,17 @@ k_fft_col_fwd_op(float2* __restrict__ data, float2* __restrict__ out, int64_t el
 }
 
 // X pass of the forward transform of the (screened) source fused with the X passes of the
-// three inverse force transforms.  The forward X transform of `src` gives S_k in the LDS
-// tile; the Green's function g = [g_n/k^2 delta_k + g_5/(k^2 + a^2 m^2) S_k] / M is formed
-// once per element (delta_k read from dk, or S_k itself when dk is null), kept in
-// registers, and each component -i k_c g is transformed in turn through the same tile and
-// written to its own array.  The outputs may alias dk and src: every read of a column
-// precedes the first write to it.
+// inverse force transforms.  The forward X transform of `src` gives S_k in the LDS tile;
+// the Green's function g = [g_n/k^2 delta_k + g_5/(k^2 + a^2 m^2) S_k] / M is formed once
+// per element (delta_k read from dk, or S_k itself when dk is null) and kept in registers.
+// F_c = IFFT[-i k_c g]: along an X column k_y and k_z are constants, so they commute with
+// the X transform and only two X transforms are needed, G0 = X^-1[-i k_x g] into o0 and
+// G = X^-1[g] into o1; the Y pass forms the y and z components from G.  The outputs may
+// alias dk and src: every read of a column precedes the first write to it.
 template <int N>
 __global__ void __launch_bounds__(ColCfg<N>::T)
-k_fft_col_fwd_force3(const float2* dk, const float2* src, float2* o0, float2* o1, float2* o2,
-                     int64_t elemStride, const float2* __restrict__ tw_g, KOp op) {
+k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
+                    int64_t elemStride, const float2* __restrict__ tw_g, KOp op) {
   constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
   constexpr int R0 = Plan<N>::rad[0], NB0 = E / R0;
   static_assert(T % B == 0, "a thread's butterflies must share one column");
@@ -386,14 +387,63 @@ k_fft_col_fwd_force3(const float2* dk, const float2* src, float2* o0, float2* o1
   }
   __syncthreads();   // the tile is reused by the inverse transforms
 #pragma unroll
-  for (int comp = 0; comp < 3; ++comp) {
-    float2* out = comp == 0 ? o0 : (comp == 1 ? o1 : o2);
+  for (int t = 0; t < 2; ++t) {
+    float2* out = t == 0 ? o0 : o1;
     auto load = [&](int i, int r, int jj, int) -> float2 {
-      return grad_minus_i(op, jj, iy, iz, comp, g[i][r]);
+      return t == 0 ? grad_minus_i(op, jj, iy, iz, 0, g[i][r]) : g[i][r];
     };
     auto store = [&](int j, int c, float2 v) { out[base + (O)j * es + c] = v; };
     GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load, store);
-    __syncthreads();   // the next component reuses the LDS tile
+    __syncthreads();   // the second transform reuses the LDS tile
+  }
+}
+
+// Inverse Y pass of G = X^-1[g] giving two force components at once: F_y needs the Y
+// transform of -i k_y G (k_y varies along the column) and F_z = -i k_z Y^-1[G] (k_z is
+// the column's constant).  The column is loaded once and kept in registers for both
+// transforms; outA (F_y, may alias data) and outB (F_z) take the results.  Tile t covers
+// columns [col0, col0 + B) of x-plane t / tilesPerBlock, as in k_fft_col.
+template <int N>
+__global__ void __launch_bounds__(ColCfg<N>::T)
+k_fft_col_inv_yz(const float2* data, float2* outA, float2* __restrict__ outB, int64_t elemStride,
+                 int64_t tilesPerBlock, int64_t blockStride, const float2* __restrict__ tw_g,
+                 KOp op) {
+  constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
+  constexpr int R0 = Plan<N>::rad[0], NB0 = E / R0;
+  static_assert(T % B == 0, "a thread's butterflies must share one column");
+  __shared__ float2 lds[N * B];
+  __shared__ float2 tw[N];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += T) tw[i] = tw_g[i];
+  using O = Off<N>;
+  const unsigned tile = xcd_block(blockIdx.x, gridDim.x);
+  const unsigned tpb = (unsigned)tilesPerBlock;
+  const O colInBlock = (O)(tile % tpb) * B;
+  const O base = (O)(tile / tpb) * (O)blockStride + colInBlock;
+  const O es = (O)elemStride;
+  const int c0 = tid % B;
+  const int iz = (int)colInBlock + c0;   // Y pass: the column is z
+  float2 gv[NB0][R0];
+#pragma unroll
+  for (int i = 0; i < NB0; ++i) {
+    const int j = (tid + i * T) / B;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) gv[i][r] = data[base + (O)(j + r * (N / R0)) * es + c0];
+  }
+  {
+    auto load = [&](int i, int r, int jj, int) -> float2 {
+      return grad_minus_i(op, 0, jj, iz, 1, gv[i][r]);
+    };
+    auto store = [&](int j, int c, float2 v) { outA[base + (O)j * es + c] = v; };
+    GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load, store);
+  }
+  __syncthreads();   // the second transform reuses the LDS tile
+  {
+    auto load = [&](int i, int r, int, int) -> float2 { return gv[i][r]; };
+    auto store = [&](int j, int c, float2 v) {
+      outB[base + (O)j * es + c] = grad_minus_i(op, 0, j, iz, 2, v);
+    };
+    GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load, store);
   }
 }
 
@@ -789,16 +839,20 @@ static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, c
   op.pitch = P;
   op.plane = pl.plane;
   {
-    ProfScope ps("fft_x_fwd_force3", s);
-    hipLaunchKernelGGL((k_fft_col_fwd_force3<N>), dim3((unsigned)((int64_t)n * P / B)),
-                       dim3(ColCfg<N>::T), 0, s, dk, src, work[0], work[1], work[2], pl.plane, pl.tw,
-                       op);
+    ProfScope ps("fft_x_fwd_force", s);
+    hipLaunchKernelGGL((k_fft_col_fwd_force<N>), dim3((unsigned)((int64_t)n * P / B)),
+                       dim3(ColCfg<N>::T), 0, s, dk, src, work[0], work[1], pl.plane, pl.tw, op);
     COLA_LAUNCH_CHECK();
   }
   KOp none;
-  for (int c = 0; c < 3; ++c)
-    col_pass<N, 1, K_COPY>(work[c], P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s,
-                           "fft_y_inv");
+  const int64_t ytiles = (int64_t)n * (P / B);
+  col_pass<N, 1, K_COPY>(work[0], P, ytiles, P / B, pl.plane, pl.tw, none, s, "fft_y_inv");
+  {
+    ProfScope ps("fft_y_inv_yz", s);
+    hipLaunchKernelGGL((k_fft_col_inv_yz<N>), dim3((unsigned)ytiles), dim3(ColCfg<N>::T), 0, s,
+                       work[1], work[1], work[2], (int64_t)P, (int64_t)(P / B), pl.plane, pl.tw, op);
+    COLA_LAUNCH_CHECK();
+  }
   {
     ProfScope ps("fft_c2r_z3", s);
     constexpr int BR = Row3Cfg<N / 2>::B;

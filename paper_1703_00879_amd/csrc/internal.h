@@ -152,11 +152,12 @@ void fft_r2c_zy(const FFTPlan& pl, const float* in, float2* out, hipStream_t s);
 void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* out,
              hipStream_t s);
 
-// Forward X pass of `src` (Z and Y passes done) fused with the three inverse force
-// transforms: one X pass that forms -i k_c [Green's function of delta_k and S_k] (delta_k
-// read from dk; S_k is the forward transform of src; S_k = delta_k when dk is null) into
-// work[c] (which may alias dk and src), the inverse Y pass of each component in place,
-// and one real Z pass over all three that writes the interleaved force mesh
+// Forward X pass of `src` (Z and Y passes done) fused with the inverse force transforms:
+// one X pass forms the Green's function g of delta_k and S_k (delta_k read from dk; S_k is
+// the forward transform of src; S_k = delta_k when dk is null) and writes X^-1[-i k_x g]
+// into work[0] and X^-1[g] into work[1] (both may alias dk and src); the inverse Y passes
+// give the x component in work[0] and the y and z components in work[1] and work[2]; one
+// real Z pass over all three writes the interleaved force mesh
 // f3[((x nm + y) nm + z) 3 + c] (unpadded).
 void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* src,
                     float2* const work[3], float* f3, hipStream_t s);
