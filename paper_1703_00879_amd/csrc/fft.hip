@@ -464,9 +464,10 @@ struct RowCfg {
 template <int NC>
 __global__ void __launch_bounds__(RowCfg<NC>::T)
 k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nrows, int /*n*/,
-              int pitch, int64_t plane, const float2* __restrict__ tw) {
+              int pitch, int64_t plane, const float2* __restrict__ tw_g) {
   constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
   __shared__ float2 lds[NC * LS];
+  __shared__ float2 tw[2 * NC];   // twiddles exp(-2 pi i t / n), staged in LDS
   const int tid = threadIdx.x;
   using O = Off<2 * NC>;
   constexpr int kN = 2 * NC;   // real row length
@@ -483,6 +484,7 @@ k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nr
         v[i] = reinterpret_cast<const float2*>(in + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[m];
       }
     }
+    for (int i = tid; i < 2 * NC; i += T) tw[i] = tw_g[i];   // after the row loads issue
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int e = tid + i * T;
@@ -513,9 +515,10 @@ k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nr
 template <int NC>
 __global__ void __launch_bounds__(RowCfg<NC>::T)
 k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nrows, int /*n*/,
-              int pitch, int64_t plane, const float2* __restrict__ tw) {
+              int pitch, int64_t plane, const float2* __restrict__ tw_g) {
   constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
   __shared__ float2 lds[NC * LS];
+  __shared__ float2 tw[2 * NC];   // twiddles exp(-2 pi i t / n), staged in LDS
   const int tid = threadIdx.x;
   using O = Off<2 * NC>;
   constexpr int kN = 2 * NC;   // real row length
@@ -536,6 +539,8 @@ k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nr
       xc[i] = cconj(row[NC - k]);
     }
   }
+  for (int i = tid; i < 2 * NC; i += T) tw[i] = tw_g[i];   // after the row loads issue
+  __syncthreads();
 #pragma unroll
   for (int i = 0; i < E; ++i) {
     const int e = tid + i * T;
@@ -575,7 +580,7 @@ template <int NC>
 __global__ void __launch_bounds__(Row3Cfg<NC>::T)
 k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
                const float2* __restrict__ in2, float* __restrict__ out, int64_t nrows,
-               int pitch, int64_t plane, const float2* __restrict__ tw) {
+               int pitch, int64_t plane, const float2* __restrict__ tw_g) {
   constexpr int B = Row3Cfg<NC>::B, E = Row3Cfg<NC>::E, TC = Row3Cfg<NC>::TC;
   constexpr int T = Row3Cfg<NC>::T, LS = Row3Cfg<NC>::LS;
   using O = Off<2 * NC>;
@@ -585,6 +590,7 @@ k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
   constexpr int kRowF = 3 * kN;   // floats per interleaved row (a multiple of 4)
   static_assert(kRowF % 4 == 0, "interleaved rows must hold whole float4s");
   __shared__ float2 lds[3][NC * LS];
+  __shared__ float2 tw[2 * NC];   // twiddles exp(-2 pi i t / n), staged in LDS
   const int tid = threadIdx.x;
   const int comp = tid / TC, lt = tid - comp * TC;
   const float2* in = comp == 0 ? in0 : (comp == 1 ? in1 : in2);
@@ -605,6 +611,8 @@ k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
         xc[i] = cconj(row[NC - k]);
       }
     }
+    for (int i = tid; i < 2 * NC; i += T) tw[i] = tw_g[i];   // after the row loads issue
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int e = lt + i * TC;
@@ -643,10 +651,11 @@ k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
 template <int NC, int MODEL>
 __global__ void __launch_bounds__(RowCfg<NC>::T)
 k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float* __restrict__ s_out,
-                 int64_t nrows, int /*n*/, int pitch, int64_t plane, const float2* __restrict__ tw,
+                 int64_t nrows, int /*n*/, int pitch, int64_t plane, const float2* __restrict__ tw_g,
                  float thr, float vx) {
   constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
   __shared__ float2 lds[NC * LS];
+  __shared__ float2 tw[2 * NC];   // twiddles exp(-2 pi i t / n), staged in LDS
   const int tid = threadIdx.x;
   using O = Off<2 * NC>;
   constexpr int kN = 2 * NC;   // real row length
@@ -671,6 +680,8 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
         rv[i] = reinterpret_cast<const float2*>(rho + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[k];
       }
     }
+    for (int i = tid; i < 2 * NC; i += T) tw[i] = tw_g[i];   // after the row loads issue
+    __syncthreads();
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int e = tid + i * T;
