@@ -263,14 +263,16 @@ struct GStages {
 };
 
 // ------------------------------------------------------------------ column passes
-// Columns per tile for the strided passes: at most 64 KB of LDS per work-group, so two
-// work-groups share a CU and one streams its tile while the other computes.
+// Columns per tile for the strided passes.  Up to n = 1024 a tile is 16 columns (a
+// 128-byte row segment per element, so every load and store moves whole cache lines)
+// in 128 KB of LDS, one work-group per CU with the plan's own elements per thread.
+// Above that a 64 KB tile of 4-8 columns with 8 elements per thread keeps the fused
+// passes' registers below the spill limit.
 template <int N>
 struct ColCfg {
-  // 8 elements per thread where the plan allows it: twice the waves of E = 16 for the
-  // same tile, and half the registers per wave
-  static constexpr int E = Plan<N>::E == 16 ? 8 : Plan<N>::E;
-  static constexpr int B0 = 65536 / (8 * N);
+  static constexpr bool kWide = N <= 1024;
+  static constexpr int E = kWide ? Plan<N>::E : (Plan<N>::E == 16 ? 8 : Plan<N>::E);
+  static constexpr int B0 = (kWide ? 131072 : 65536) / (8 * N);
   static constexpr int B = B0 >= 16 ? 16 : (B0 >= 8 ? 8 : 4);
   static constexpr int T = N * B / E;
   static_assert(T <= 1024, "column tile needs too many threads");
@@ -314,14 +316,12 @@ k_fft_col(float2* __restrict__ data, int64_t elemStride, int64_t tilesPerBlock,
 // k-space operator: the forward result (delta_k) is written back in place and, multiplied
 // by the operator (smoothing window or Newtonian potential), transformed back through the
 // same LDS tile into `out`.  One read and two writes of the field instead of two reads
-// and two writes.  It keeps the plan's own element count per thread (16 at n = 1024):
-// with half as many threads two work-groups fit on a CU, which measured faster here
-// than one work-group of twice the waves.
+// and two writes.
 template <int N, int KIND>
-__global__ void __launch_bounds__(N * ColCfg<N>::B / Plan<N>::E)
+__global__ void __launch_bounds__(ColCfg<N>::T)
 k_fft_col_fwd_op(float2* __restrict__ data, float2* __restrict__ out, int64_t elemStride,
                  const float2* __restrict__ tw_g, KOp op) {
-  constexpr int B = ColCfg<N>::B, E = Plan<N>::E, T = N * B / E;
+  constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
   static_assert(T % B == 0, "a thread's butterflies must share one column");
   __shared__ float2 lds[N * B];
   __shared__ float2 tw[N];
@@ -886,7 +886,7 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
   op.plane = pl.plane;
   const int64_t xtiles = (int64_t)n * P / B;
   {
-    const dim3 g((unsigned)xtiles), b(N * B / Plan<N>::E);
+    const dim3 g((unsigned)xtiles), b(ColCfg<N>::T);
     if (kind == K_POT) {
       ProfScope ps("fft_x_fwd_pot", s);
       hipLaunchKernelGGL((k_fft_col_fwd_op<N, K_POT>), g, b, 0, s, dk, data, pl.plane, pl.tw, op);
