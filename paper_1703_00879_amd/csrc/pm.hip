@@ -68,16 +68,15 @@ void launch_fill(float* p, size_t n, float v, hipStream_t s) {
 //  1. count: every particle finds its home tile (the T^3-cell tile holding its lower CIC
 //     corner i0) and its class c = bitmask of the axes on which i0 sits on the tile's
 //     last layer (c != 0: some corners spill into the next tile).  Work-groups take
-//     Lagrangian bricks of 4x8x8 particles, which land in few tiles, and aggregate their
-//     counts in an LDS hash table before one global add per (tile, class);
+//     Lagrangian bricks of 4x8x8 particles, which land in few tiles; the lanes of a wave
+//     that share a (tile, class) make one global add between them;
 //  2. scan: exclusive prefix over tiles, then per-class cursors inside each tile;
-//  3. scatter: the same bricks write particle indices into the tile/class segments;
+//  3. scatter: the same bricks write CIC records into the tile/class segments;
 //  4. deposit: one work-group per tile accumulates in LDS the corners that fall inside it
 //     -- from every particle of its own tile and from the class-c particles of the seven
 //     lower neighbour tiles T - delta with (c & delta) == delta -- and writes the tile
 //     once with plain stores, so the mesh needs no zeroing pass.
 constexpr int kBrickX = 4, kBrickY = 8, kBrickZ = 8;   // 256 particles per work-group
-constexpr int kHash = 512;                              // > 256 distinct keys: never full
 constexpr int kScanBlock = 1024;                        // tiles per scan block
 constexpr float kFix = 16777216.f;                      // 2^24: deposit fixed-point unit
 
@@ -101,15 +100,6 @@ __device__ __forceinline__ int axis_cell(int ixq, float u, const BinGeo& g, floa
   return i < 0 ? i + g.nm : i;
 }
 
-__device__ __forceinline__ int lds_slot(int* keys, int key) {
-  unsigned h = ((unsigned)key * 2654435761u) >> (32 - 9);
-  while (true) {
-    const int prev = atomicCAS(&keys[h], -1, key);
-    if (prev == -1 || prev == key) return (int)h;
-    h = (h + 1) & (kHash - 1);
-  }
-}
-
 __device__ __forceinline__ bool brick_particle(const BinGeo& g, int& ix, int& iy, int& iz, int64_t& p) {
   const int nbz = (g.np + kBrickZ - 1) / kBrickZ, nby = (g.np + kBrickY - 1) / kBrickY;
   const int b = (int)xcd_block(blockIdx.x, gridDim.x);
@@ -125,52 +115,62 @@ __device__ __forceinline__ bool brick_particle(const BinGeo& g, int& ix, int& iy
 
 // MODE 0: count into cnt[tile*8 + cls];  MODE 1: scatter the particle's CIC record
 // (dx, dy, dz, lower corner relative to its home tile) to entries[cur[tile*8 + cls]++].
+// The lanes of a wave that share a (tile, class) key are served by one atomic that adds
+// their number; in MODE 1 each lane takes the returned base plus its rank among them.  A
+// wave holds an 8 x 8 patch of one lattice plane, so it meets only a few keys.
 template <int MODE>
 __global__ void __launch_bounds__(256)
 k_bin(const float* __restrict__ disp, BinGeo g, uint32_t* __restrict__ cnt,
       uint32_t* __restrict__ cur, float4* __restrict__ entries) {
-  __shared__ int keys[kHash];
-  __shared__ unsigned cls_cnt[kHash][8];
-  for (int i = threadIdx.x; i < kHash; i += blockDim.x) {
-    keys[i] = -1;
-#pragma unroll
-    for (int c = 0; c < 8; ++c) cls_cnt[i][c] = 0u;
-  }
-  __syncthreads();
-  int ix, iy, iz, tile = 0, cls = 0, slot = -1;
+  int ix, iy, iz;
   int64_t p = 0;
-  unsigned rank = 0;
+  unsigned key = 0xffffffffu;
   float dx = 0.f, dy = 0.f, dz = 0.f;
   unsigned local = 0;
-  if (brick_particle(g, ix, iy, iz, p)) {
+  const bool valid = brick_particle(g, ix, iy, iz, p);
+  if (valid) {
     const int cx = axis_cell(ix, disp[p], g, dx);
     const int cy = axis_cell(iy, disp[g.N + p], g, dy);
     const int cz = axis_cell(iz, disp[2 * g.N + p], g, dz);
     const int T = g.tile;
-    tile = ((cx / T) * g.nt1 + cy / T) * g.nt1 + cz / T;
-    cls = ((cx % T == T - 1) ? 1 : 0) | ((cy % T == T - 1) ? 2 : 0) | ((cz % T == T - 1) ? 4 : 0);
+    const int tile = ((cx / T) * g.nt1 + cy / T) * g.nt1 + cz / T;
+    const int cls = ((cx % T == T - 1) ? 1 : 0) | ((cy % T == T - 1) ? 2 : 0) | ((cz % T == T - 1) ? 4 : 0);
     local = (unsigned)(cx % T) | ((unsigned)(cy % T) << 8) | ((unsigned)(cz % T) << 16);
-    slot = lds_slot(keys, tile);
-    rank = atomicAdd(&cls_cnt[slot][cls], 1u);
+    key = (unsigned)tile * 8u + (unsigned)cls;
   }
-  __syncthreads();
-  // one global add per (tile, class) present in this brick; for the scatter its return
-  // value is the brick's base inside the class segment
-  for (int i = threadIdx.x; i < kHash * 8; i += blockDim.x) {
-    const int s = i >> 3, c = i & 7;
-    const int key = keys[s];
-    if (key < 0) continue;
-    const unsigned n = cls_cnt[s][c];
-    if (n == 0) continue;
+  // group the wave's lanes by key with ballots (no memory traffic); group i's key and
+  // size land in lane i, which then makes the group's one atomic -- all groups' atomics
+  // go out as a single wave instruction
+  const int lane = (int)__lane_id();
+  unsigned long long todo = __ballot(valid);
+  int it = 0, mygroup = 0;
+  uint32_t myrank = 0, gcnt = 0;
+  unsigned gkey = 0;
+  while (todo) {   // wave-uniform: every lane runs the same iterations, at most 64
+    const int leader = __ffsll((unsigned long long)todo) - 1;
+    const unsigned lkey = __shfl(key, leader);
+    const unsigned long long m = __ballot(key == lkey) & todo;
+    if (lane == it) {
+      gkey = lkey;
+      gcnt = (uint32_t)__popcll(m);
+    }
+    if ((m >> lane) & 1ull) {
+      mygroup = it;
+      myrank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    }
+    todo &= ~m;
+    ++it;
+  }
+  uint32_t gbase = 0;
+  if (lane < it) {
     if (MODE == 0)
-      atomicAdd(&cnt[(int64_t)key * 8 + c], n);
+      atomicAdd(&cnt[gkey], gcnt);
     else
-      cls_cnt[s][c] = atomicAdd(&cur[(int64_t)key * 8 + c], n);
+      gbase = atomicAdd(&cur[gkey], gcnt);
   }
   if (MODE == 1) {
-    __syncthreads();
-    if (slot >= 0)
-      entries[cls_cnt[slot][cls] + rank] = make_float4(dx, dy, dz, __uint_as_float(local));
+    const uint32_t base = __shfl(gbase, mygroup);
+    if (valid) entries[base + myrank] = make_float4(dx, dy, dz, __uint_as_float(local));
   }
 }
 
