@@ -596,22 +596,37 @@ k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
   const float2* in = comp == 0 ? in0 : (comp == 1 ? in1 : in2);
   float2* tile = lds[comp];
   const O r0 = (O)blockIdx.x * B;
+  // each row element X_k is read from HBM once; the mirrored X_{NC-k} of the split step
+  // comes back out of the LDS tile (X_NC, the Nyquist value, from a per-row slot)
+  __shared__ float2 nyq[3][B];
   {
-    float2 xk[E], xc[E];
+    float2 xk[E];
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int e = lt + i * TC;
       const int c = e / NC, k = e % NC;
       xk[i] = make_float2(0.f, 0.f);
-      xc[i] = make_float2(0.f, 0.f);
       if (r0 + c < (O)nrows) {
         const O r = r0 + c;
         const float2* row = in + (r / kN) * (O)plane + (r % kN) * (O)pitch;
         xk[i] = row[k];
-        xc[i] = cconj(row[NC - k]);
+        if (k == 0) nyq[comp][c] = row[NC];
       }
     }
     for (int i = tid; i < 2 * NC; i += T) tw[i] = tw_g[i];   // after the row loads issue
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = lt + i * TC;
+      tile[(e % NC) * LS + e / NC] = xk[i];
+    }
+    __syncthreads();
+    float2 xc[E];
+#pragma unroll
+    for (int i = 0; i < E; ++i) {
+      const int e = lt + i * TC;
+      const int c = e / NC, k = e % NC;
+      xc[i] = cconj(k == 0 ? nyq[comp][c] : tile[(NC - k) * LS + c]);
+    }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < E; ++i) {
