@@ -274,49 +274,49 @@ k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__
   // most the particle mass (nmesh/np)^3 <= 64 (< 2^32 units), and a cell overflows only
   // beyond ~10^12 in mean-density units.
   __shared__ unsigned long long acc[T * T * T];
-  __shared__ uint32_t seg[8][9];   // per offset d: start of the source tile, 8 class counts
   const int nt1 = g.nt1;
   const int tile = (int)xcd_block(blockIdx.x, gridDim.x);
   const int tx = tile / (nt1 * nt1), ty = (tile / nt1) % nt1, tz = tile % nt1;
-  if (threadIdx.x < 72) {
-    const int d = threadIdx.x / 9, k = threadIdx.x % 9;
+  for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) acc[i] = 0ull;
+  // Flatten the (offset d, class c) segments that reach this tile into one list, so the
+  // entries are read in a single strided sweep: the whole own tile (d = 0) and, from the
+  // lower neighbour T - d, every class c with (c & d) == d (at most 1 + 19 segments).
+  // Wave 0 builds it with one lane per (d, c): class offsets inside the source tile by an
+  // 8-lane scan, list positions by ballot, list offsets by a wave scan.
+  __shared__ uint32_t sb[20], so[21];
+  __shared__ int sdd[20], nseg;
+  if (threadIdx.x < 64) {
+    const int lane = threadIdx.x, d = lane >> 3, c = lane & 7;
     const int sx = (tx - (d & 1) + nt1) % nt1, sy = (ty - ((d >> 1) & 1) + nt1) % nt1,
               sz = (tz - ((d >> 2) & 1) + nt1) % nt1;
     const int64_t src = ((int64_t)sx * nt1 + sy) * nt1 + sz;
-    seg[d][k] = k == 0 ? start[src] : cnt[src * 8 + k - 1];
-  }
-  for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) acc[i] = 0ull;
-  // Flatten the (offset d, class c) segments that reach this tile into one list, so the
-  // entries are read in a single strided sweep (at most 1 + 3*4 + 3*2 + 1 = 20 segments).
-  __shared__ uint32_t sb[24], so[25];
-  __shared__ int sdd[24], nseg;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    int k = 0;
-    uint32_t tot = 0;
-    uint32_t n0 = 0;
-    for (int c = 0; c < 8; ++c) n0 += seg[0][c + 1];
-    if (n0) {
-      sb[k] = seg[0][0];
-      so[k] = tot;
-      sdd[k++] = 0;
-      tot += n0;
+    const uint32_t nc = cnt[src * 8 + c], st0 = start[src];
+    uint32_t incl = nc;   // inclusive scan over the 8 classes of the source tile
+#pragma unroll
+    for (int o = 1; o < 8; o <<= 1) {
+      const uint32_t t = __shfl_up(incl, o, 8);
+      if (c >= o) incl += t;
     }
-    for (int d = 1; d < 8; ++d) {
-      uint32_t b = seg[d][0];
-      for (int c = 0; c < 8; ++c) {
-        const uint32_t n = seg[d][c + 1];
-        if ((c & d) == d && n) {
-          sb[k] = b;
-          so[k] = tot;
-          sdd[k++] = d;
-          tot += n;
-        }
-        b += n;
-      }
+    const uint32_t tot = __shfl(incl, 7, 8);
+    const bool valid = d == 0 ? (c == 0 && tot > 0) : ((c & d) == d && nc > 0);
+    const uint32_t n = d == 0 ? tot : nc;
+    const unsigned long long vm = __ballot(valid);
+    const int pos = __popcll(vm & ((1ull << lane) - 1ull));
+    uint32_t x = valid ? n : 0u;   // inclusive scan of the segment lengths over the wave
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(x, o, 64);
+      if (lane >= o) x += t;
     }
-    so[k] = tot;
-    nseg = k;
+    if (valid) {
+      sb[pos] = d == 0 ? st0 : st0 + incl - nc;
+      so[pos] = x - n;
+      sdd[pos] = d;
+    }
+    if (lane == 63) {
+      nseg = __popcll(vm);
+      so[__popcll(vm)] = x;
+    }
   }
   __syncthreads();
   const uint32_t total = so[nseg];
@@ -360,11 +360,14 @@ k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__
     }
   }
   __syncthreads();
+  // 16-byte stores: T, the row pitch and the plane stride are multiples of 4 floats
   const int ox = tx * T, oy = ty * T, oz = tz * T;
-  for (int i = threadIdx.x; i < T * T * T; i += blockDim.x) {
+  for (int i4 = threadIdx.x; i4 < T * T * T / 4; i4 += blockDim.x) {
+    const int i = 4 * i4;
     const int lx = i / (T * T), ly = (i / T) % T, lz = i % T;
-    rho[(int64_t)(ox + lx) * rplane + (int64_t)(oy + ly) * rpitch + oz + lz] =
-        (float)acc[i] * (1.f / kFix);
+    const float s = 1.f / kFix;
+    *reinterpret_cast<float4*>(rho + (int64_t)(ox + lx) * rplane + (int64_t)(oy + ly) * rpitch + oz + lz) =
+        make_float4((float)acc[i] * s, (float)acc[i + 1] * s, (float)acc[i + 2] * s, (float)acc[i + 3] * s);
   }
 }
 
