@@ -229,6 +229,39 @@ def cpu_baseline(steps=8):
                       f"{dt:.1f} s"}
 
 
+# FP64 operations of one classical Runge-Kutta step of the triangle system: four
+# right-hand sides (three mu, gamma_2^E at the triangle and at k/sqrt2, exp, ~10 state
+# terms: ~210 each) plus the update (10 x 8)
+TRIANGLE_FLOP_PER_STEP = 4 * 210 + 80
+FP64_VECTOR_PEAK_TFLOPS = 78.6
+
+
+def bench_triangles(C, torch, n=1 << 16):
+    """Exact second-order growth of n random triangles (F5, a = 1): the Fig. 1 check of
+    the approximate D2, timed with HIP events on the launch stream."""
+    import math
+    import numpy as np
+    p = C.Params(model=C.FR_HS1, fr0_abs=1e-5, z_init=19.0)
+    rng = np.random.default_rng(7)
+    k1, k2 = rng.uniform(0.005, 5.0, n), rng.uniform(0.005, 5.0, n)
+    c = rng.uniform(-1.0, 1.0, n)
+    k = np.sqrt(k1 * k1 + k2 * k2 + 2 * k1 * k2 * c)
+    tri = torch.from_numpy(np.stack([k, k1, k2], axis=1)).cuda()
+    out = torch.empty(n, 2, dtype=torch.float64, device="cuda")
+    C.cola_growth_triangles(p, tri, 1.0, out)      # warm-up
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    C.cola_growth_triangles(p, tri, 1.0, out)
+    e1.record()
+    e1.synchronize()
+    ms = e0.elapsed_time(e1)
+    steps = math.ceil(math.log(1.0 / (1.0 / (1.0 + p.z_init))) / 1e-3)
+    tflops = n * steps * TRIANGLE_FLOP_PER_STEP / (ms / 1e3) / 1e12
+    return {"triangles": n, "ms": ms, "triangles_per_s": n / (ms / 1e3),
+            "roofline": {"bound": "alu", "achieved": tflops, "peak": FP64_VECTOR_PEAK_TFLOPS,
+                         "unit": "TFLOP/s", "frac": tflops / FP64_VECTOR_PEAK_TFLOPS}}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -336,6 +369,7 @@ def main():
         "ic_ms": ic_ms, "pk_ms": pk_ms, "finite": ok,
         "kernels": kernels,
     }
+    out["growth_triangles"] = bench_triangles(C, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -161,6 +161,19 @@ cola_status cola_growth_table(const cola_params* p, const cola_state* st, int32_
 cola_status cola_white_noise(const cola_params* p, int32_t grid, float* dst,
                              hipStream_t stream);
 
+/* Second-order growth of Fourier triangles k = k1 + k2 at scale factor a, exact and as
+ * the path approximates it, for checking the approximation (Sec. 4.2, Fig. 1).  The
+ * exact D2(k, k1, k2, a) solves the triangle's own second-order equation with
+ * D1(k1) D1(k2), the cos^2 theta term and gamma_2 of the model (Sec. 4); the
+ * approximation is D2_hat(k, a)(1 - cos^2 theta), D2_hat being what the growth tables
+ * hold.  Cosmology and model come from p; growth_mode 1 gives LCDM growth.
+ * tri: device double [n][3] = (|k|, |k1|, |k2|) in h/Mpc.  out: device double [n][2] =
+ * (exact, approximation).  A set that is not a triangle (k1, k2 > 0 and
+ * |k1 - k2| <= k <= k1 + k2, to 1e-12 relative) gets NaN in both outputs.
+ * a_ini <= a <= 10.  Needs no state; n = 0 does nothing. */
+cola_status cola_growth_triangles(const cola_params* p, int32_t n, const double* tri, double a,
+                                  double* out, hipStream_t stream);
+
 /* Kernel timing by HIP events on the launch stream: enable (1) / disable (0)
  * recording; read accumulated milliseconds and launch counts per kernel name
  * (synchronises the last recorded stream).  names/ms/counts are host arrays of

@@ -21,7 +21,8 @@ SMOOTH_GAUSS, SMOOTH_TOPHAT, SMOOTH_SHARPK = 0, 1, 2
 
 EXPORTED = ["cola_query_sizes", "cola_validate", "cola_prepare", "cola_make_ic", "cola_pm_force",
             "cola_step", "cola_power_spectrum", "cola_positions", "cola_growth_table",
-            "cola_white_noise", "cola_profile_enable", "cola_profile_read", "cola_profile_reset",
+            "cola_white_noise", "cola_growth_triangles", "cola_profile_enable", "cola_profile_read",
+            "cola_profile_reset",
             "cola_status_string", "cola_last_error"]
 
 
@@ -105,7 +106,8 @@ def load_library(path=LIB_PATH):
         "cola_power_spectrum": [P, St, i32, vp, vp, vp, vp],
         "cola_positions": [P, St, vp, vp],
         "cola_growth_table": [P, St, i32, vp, i64, vp, vp],
-        "cola_white_noise": [P, i32, vp, vp], "cola_profile_enable": [i32],
+        "cola_white_noise": [P, i32, vp, vp], "cola_growth_triangles": [P, i32, vp, d, vp, vp],
+        "cola_profile_enable": [i32],
         "cola_profile_read": [vp, vp, vp, i32, vp], "cola_profile_reset": [],
     }
     for name, args in sig.items():
@@ -225,6 +227,13 @@ def cola_growth_table(p, state, i, stream=None):
 def cola_white_noise(p, dst, grid=0, stream=None):
     _check(load_library().cola_white_noise(ctypes.byref(p._c()), int(grid), _ptr(dst),
                                            _stream(stream)))
+
+
+def cola_growth_triangles(p, tri, a, out, stream=None):
+    """tri: device float64 (n, 3) of (|k|, |k1|, |k2|) [h/Mpc]; out: device float64 (n, 2)."""
+    n = int(tri.shape[0])
+    _check(load_library().cola_growth_triangles(ctypes.byref(p._c()), n, _ptr(tri), float(a),
+                                                _ptr(out), _stream(stream)))
 
 
 def cola_profile_enable(on=True):

@@ -506,6 +506,20 @@ cola_status cola_white_noise(const cola_params* p, int32_t grid, float* dst, hip
   });
 }
 
+cola_status cola_growth_triangles(const cola_params* p, int32_t n, const double* tri, double a,
+                                  double* out, hipStream_t s) {
+  return guarded([&] {
+    if (!p) throw Error{COLA_E_ARG, "params is NULL"};
+    validate(*p);
+    if (n < 0) throw Error{COLA_E_ARG, "n must be >= 0"};
+    const double a_ini = 1.0 / (1.0 + p->z_init);
+    if (!(a >= a_ini && a <= 10.0)) throw Error{COLA_E_ARG, "a must be in [a_ini, 10]"};
+    if (n == 0) return;
+    if (!tri || !out) throw Error{COLA_E_ARG, "NULL argument"};
+    launch_growth_triangles(*p, n, tri, a, out, s);
+  });
+}
+
 cola_status cola_profile_enable(int32_t on) {
   return guarded([&] {
     ProfState& P = prof();

@@ -154,6 +154,140 @@ void launch_growth_ode(const cola_params& p, const Layout& L, double* table, dou
   COLA_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------------------------ triangle growth
+// Exact second-order growth of a Fourier triangle k = k1 + k2 (Sec. 4.2) beside the
+// approximation the path uses, D2_hat(k)(1 - cos^2 theta), for checking it (Fig. 1):
+//   D2'' = kappa mu(k) D2 - kappa mu(k) D1(k1) D1(k2)
+//          [1 - (2 mu(k1) - mu(k))/mu(k) cos^2 theta + 2 a^4 H^2 gamma_2/(kappa mu(k))],
+//   gamma_2 = gamma_2^E(k, k1, k2) + (3/2) Omega_m(a) [mu(k) - mu(k1)] k1.k2/k2^2  (Sec. 4),
+// with D2 = -(3/7)(1 - cos^2 theta), D2' = -(6/7)(1 - cos^2 theta) a^2 E at a_ini; the
+// terms that single out k1 are taken as printed.  Same integrator as k_growth_ode.
+
+__device__ __forceinline__ double growth_mu(const GrowthDev& g, double k, double a) {
+  if (g.model == COLA_FR_HS1) {
+    const double ol = 1.0 - g.om;
+    const double X = g.om / (a * a * a) + 4.0 * ol, Y = g.om + 4.0 * ol;
+    const double r = X / Y;
+    const double a2m2 = a * a * kH0c * kH0c * Y * r * r * r / (2.0 * g.fr0);
+    return 1.0 + k * k / (3.0 * (k * k + a2m2));
+  }
+  if (g.model == COLA_NDGP) {
+    const double E = dE(a, g.om);
+    const double oma = g.om / (a * a * a) / (E * E);
+    return 1.0 + 1.0 / (3.0 * (1.0 + 2.0 * g.rc * E * (1.0 - 0.5 * oma)));
+  }
+  return 1.0;
+}
+
+// 2 a^4 H^2 gamma_2^E(k, k1, k2, a) (Secs. 5.1, 5.2); c2 = cos^2 theta
+__device__ __forceinline__ double gamma2E_term(const GrowthDev& g, double k, double k1, double k2,
+                                               double c2, double a) {
+  const double E = dE(a, g.om);
+  const double a6 = (a * a * a) * (a * a * a);
+  double g2 = 0.0;
+  if (g.model == COLA_FR_HS1) {
+    const double ol = 1.0 - g.om;
+    const double X = g.om / (a * a * a) + 4.0 * ol, Y = g.om + 4.0 * ol;
+    const double c0 = X * X * X / (2.0 * g.fr0 * Y * Y);
+    const double ah = a * kH0c;
+    const double P = k * k / (ah * ah) + c0, P1 = k1 * k1 / (ah * ah) + c0, P2 = k2 * k2 / (ah * ah) + c0;
+    const double kah = k / (ah * E);
+    g2 = -9.0 * g.om * g.om / (48.0 * a6 * g.fr0 * g.fr0) * kah * kah * (X * X * X * X * X) / (Y * Y * Y * Y)
+         / (P * P1 * P2);
+  } else if (g.model == COLA_NDGP) {
+    const double oma = g.om / (a * a * a) / (E * E);
+    const double beta = 1.0 + 2.0 * g.rc * E * (1.0 - 0.5 * oma);
+    g2 = -(g.rc * g.rc * g.om * g.om) / (6.0 * E * E * beta * beta * beta * a6) * (1.0 - c2);
+  }
+  return 2.0 * a * a * a * a * E * E * g2;
+}
+
+// y = (D1(k1), D1'(k1), D1(k2), D1'(k2), D1(k), D1'(k), D2, D2', D2_hat, D2_hat')
+struct Triangle {
+  double k, k1, k2, c, c2;
+};
+
+__device__ __forceinline__ void triangle_rhs(const GrowthDev& g, const Triangle& t, double lna,
+                                             const double y[10], double dy[10]) {
+  const double a = exp(lna);
+  const double E = dE(a, g.om);
+  const double kap = 1.5 * g.om * a;
+  const double f = 1.0 / (a * a * E);
+  const double mu = growth_mu(g, t.k, a), mu1 = growth_mu(g, t.k1, a), mu2 = growth_mu(g, t.k2, a);
+  const double oma = g.om / (a * a * a) / (E * E);
+  const double g2t = gamma2E_term(g, t.k, t.k1, t.k2, t.c2, a)
+                     + 2.0 * a * a * a * a * E * E * 1.5 * oma * (mu - mu1) * (t.k1 / t.k2) * t.c;
+  const double src = 1.0 - (2.0 * mu1 - mu) / mu * t.c2 + g2t / (kap * mu);
+  double muh, g2h;
+  growth_model(g, t.k, a, muh, g2h);   // the approximate equation at k
+  dy[0] = y[1] * f;
+  dy[1] = kap * mu1 * y[0] * f;
+  dy[2] = y[3] * f;
+  dy[3] = kap * mu2 * y[2] * f;
+  dy[4] = y[5] * f;
+  dy[5] = kap * mu * y[4] * f;
+  dy[6] = y[7] * f;
+  dy[7] = (kap * mu * y[6] - kap * mu * y[0] * y[2] * src) * f;
+  dy[8] = y[9] * f;
+  dy[9] = (kap * muh * y[8] - kap * muh * y[4] * y[4] - g2h * y[4] * y[4]) * f;
+}
+
+__global__ void k_growth_triangle(GrowthDev g, int n, const double* __restrict__ tri, double a_end,
+                                  double* __restrict__ out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  Triangle t;
+  t.k = tri[3 * i];
+  t.k1 = tri[3 * i + 1];
+  t.k2 = tri[3 * i + 2];
+  const double tol = 1e-12 * (t.k1 + t.k2);
+  if (!(t.k1 > 0.0 && t.k2 > 0.0 && t.k >= fabs(t.k1 - t.k2) - tol && t.k <= t.k1 + t.k2 + tol)) {
+    out[2 * i] = out[2 * i + 1] = __builtin_nan("");
+    return;
+  }
+  t.c = fmin(1.0, fmax(-1.0, (t.k * t.k - t.k1 * t.k1 - t.k2 * t.k2) / (2.0 * t.k1 * t.k2)));
+  t.c2 = t.c * t.c;
+  const double ai = g.a_ini;
+  const double g0 = ai * ai * dE(ai, g.om);
+  const double s2 = 1.0 - t.c2;
+  double y[10] = {1.0, g0, 1.0, g0, 1.0, g0, -3.0 / 7.0 * s2, -6.0 / 7.0 * s2 * g0, -3.0 / 7.0,
+                  -6.0 / 7.0 * g0};
+  double lna = log(ai);
+  const double l1 = log(a_end);
+  const int nsub = (int)ceil((l1 - lna) / 1e-3);
+  if (nsub > 0) {
+    const double h = (l1 - lna) / nsub;
+    for (int s = 0; s < nsub; ++s) {
+      double k1[10], k2[10], k3[10], k4[10], yt[10];
+      triangle_rhs(g, t, lna, y, k1);
+      for (int c = 0; c < 10; ++c) yt[c] = y[c] + 0.5 * h * k1[c];
+      triangle_rhs(g, t, lna + 0.5 * h, yt, k2);
+      for (int c = 0; c < 10; ++c) yt[c] = y[c] + 0.5 * h * k2[c];
+      triangle_rhs(g, t, lna + 0.5 * h, yt, k3);
+      for (int c = 0; c < 10; ++c) yt[c] = y[c] + h * k3[c];
+      triangle_rhs(g, t, lna + h, yt, k4);
+      for (int c = 0; c < 10; ++c) y[c] += h / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+      lna = (s + 1 == nsub) ? l1 : lna + h;
+    }
+  }
+  out[2 * i] = y[6];
+  out[2 * i + 1] = y[8] * s2;
+}
+
+void launch_growth_triangles(const cola_params& p, int n, const double* tri, double a, double* out,
+                             hipStream_t s) {
+  ProfScope ps("growth_triangles", s);
+  GrowthDev g{};
+  g.om = p.omega_m;
+  g.fr0 = p.fr0_abs;
+  g.rc = p.rc_h0;
+  g.a_ini = 1.0 / (1.0 + p.z_init);
+  g.model = (p.growth_mode == 1) ? COLA_LCDM : p.model;
+  hipLaunchKernelGGL(k_growth_triangle, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, g, n, tri, a,
+                     out);
+  COLA_LAUNCH_CHECK();
+}
+
 // ------------------------------------------------------------------ white noise
 __device__ __forceinline__ uint64_t splitmix64(uint64_t seed, uint64_t k) {
   uint64_t z = seed + (k + 1) * 0x9E3779B97F4A7C15ull;

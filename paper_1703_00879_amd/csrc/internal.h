@@ -174,6 +174,10 @@ void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* dk, float2* 
 void launch_fill(float* p, size_t n, float v, hipStream_t s);
 void launch_growth_ode(const cola_params& p, const Layout& L, double* table, double* ref,
                        hipStream_t s);
+// exact D2 of triangles tri[i] = (k, k1, k2) and D2_hat(k)(1 - cos^2 theta) at a into
+// out[i] = (exact, approximation); NaN for sets that are no triangle
+void launch_growth_triangles(const cola_params& p, int n, const double* tri, double a, double* out,
+                             hipStream_t s);
 void launch_noise(const cola_params& p, int n, int pitch, int64_t plane, float* dst_padded,
                   float* dst_flat, hipStream_t s);
 void launch_ic_phi1(const cola_params& p, const Layout& L, const float2* wk, float2* phi1,

@@ -230,3 +230,55 @@ def test_step_order_and_state_errors():
         C.cola_step(p, st, 3)
     sync()
     assert np.isfinite(st.disp_f.cpu().numpy()).all()
+
+
+# ----------------------------------------------------------------------------- triangles
+TRI_CASES = {"f5": dict(model=C.FR_HS1, fr0_abs=1e-5), "f6": dict(model=C.FR_HS1, fr0_abs=1e-6),
+             "f5_lcdm_growth": dict(model=C.FR_HS1, fr0_abs=1e-5, growth_mode=1),
+             "ndgp": dict(model=C.NDGP, rc_h0=0.5), "lcdm": dict(model=C.LCDM)}
+
+
+@pytest.mark.parametrize("name", list(TRI_CASES))
+def test_growth_triangles_match_oracle(name):
+    """Exact triangle D2 and the approximation D2_hat (1 - cos^2 theta) (Sec. 4.2) for
+    random triangles and the Fig. 1 configurations, against the FP64 oracle."""
+    from oracle.triangle import approx_d2_triangle, fig1_triangles, solve_d2_triangle
+    p = C.Params(**TRI_CASES[name])
+    rng = np.random.default_rng(sorted(TRI_CASES).index(name))
+    k1 = rng.uniform(0.005, 4.0, 200)
+    k2 = rng.uniform(0.005, 4.0, 200)
+    c = rng.uniform(-0.999, 0.999, 200)
+    k = np.sqrt(k1 * k1 + k2 * k2 + 2 * k1 * k2 * c)
+    ks = np.geomspace(0.01, 5.0, 25)
+    for cfg in ("equilateral", "orthogonal", "squeezed"):
+        a_, b_, c_ = fig1_triangles(ks, cfg)
+        k, k1, k2 = np.concatenate([k, a_]), np.concatenate([k1, b_]), np.concatenate([k2, c_])
+    tri = torch.from_numpy(np.stack([k, k1, k2], axis=1)).cuda()
+    po = to_oracle(p)
+    worst = 0.0
+    for a in (0.4, 1.0):
+        out = torch.empty(k.size, 2, dtype=torch.float64, device="cuda")
+        C.cola_growth_triangles(p, tri, a, out)
+        sync()
+        got = out.cpu().numpy()
+        ex = solve_d2_triangle(k, k1, k2, [a], po)[0]
+        ap = approx_d2_triangle(k, k1, k2, [a], po)[0]
+        worst = max(worst, float(np.max(np.abs(got[:, 0] / ex - 1))),
+                    float(np.max(np.abs(got[:, 1] / ap - 1))))
+    record(f"growth_triangles_{name}", max_rel=worst)
+    assert worst < 1e-10
+
+
+def test_growth_triangles_rejects_non_triangles():
+    p = C.Params(model=C.FR_HS1)
+    tri = torch.tensor([[3.0, 1.0, 1.0], [0.5, 0.0, 0.5], [1.0, 0.5, 0.5], [0.2, 1.0, 0.5]],
+                       dtype=torch.float64, device="cuda")
+    out = torch.zeros(4, 2, dtype=torch.float64, device="cuda")
+    C.cola_growth_triangles(p, tri, 1.0, out)
+    sync()
+    o = out.cpu().numpy()
+    assert np.isnan(o[0]).all() and np.isnan(o[1]).all() and np.isnan(o[3]).all()
+    assert np.isfinite(o[2]).all()            # degenerate but valid: k1, k2 collinear
+    with pytest.raises(C.ColaError):
+        C.cola_growth_triangles(p, tri, 0.01, out)   # before a_ini
+    C.cola_growth_triangles(p, tri[:0], 1.0, out[:0])

@@ -236,3 +236,53 @@ def test_screening_factor_limits():
     assert np.all(eps_chameleon(np.array([1e-9, -1e-8, 0.0]), fR) == 1.0)
     deep = np.array([-1e-4, 3e-4])
     assert np.allclose(eps_chameleon(deep, fR), np.abs(1.5 * fR / deep), rtol=1e-15)
+
+
+# ----------------------------------------------------------------------------- triangles
+from oracle import MODEL_LCDM, MODEL_NDGP  # noqa: E402
+from oracle.triangle import (approx_d2_triangle, cos_theta, fig1_triangles,  # noqa: E402
+                             solve_d2_triangle)
+
+
+def _random_triangles(n, seed):
+    rng = np.random.default_rng(seed)
+    k1 = rng.uniform(0.01, 3.0, n)
+    k2 = rng.uniform(0.01, 3.0, n)
+    c = rng.uniform(-0.99, 0.99, n)
+    return np.sqrt(k1 * k1 + k2 * k2 + 2 * k1 * k2 * c), k1, k2
+
+
+@pytest.mark.parametrize("model", [MODEL_LCDM, MODEL_NDGP])
+def test_triangle_growth_exact_where_the_approximation_is(model):
+    """LCDM and nDGP: mu does not depend on k and gamma_2 is proportional to
+    (1 - cos^2 theta), so the exact triangle D2 equals D2_hat (1 - cos^2 theta) (Sec. 4.2)."""
+    p = Params(model=model, rc_h0=0.5)
+    k, k1, k2 = _random_triangles(40, seed=model)
+    a = [p.a_ini, 0.3, 1.0]
+    ex = solve_d2_triangle(k, k1, k2, a, p)
+    ap = approx_d2_triangle(k, k1, k2, a, p)
+    assert np.max(np.abs(ex / ap - 1.0)) < 1e-9
+    c = cos_theta(k, k1, k2)
+    assert np.allclose(ex[0], -3.0 / 7.0 * (1.0 - c * c), rtol=1e-14, atol=0)
+
+
+@pytest.mark.parametrize("fr0", [1e-5, 1e-6])
+def test_fig1_ratios_of_exact_to_approximate_d2(fr0):
+    """Fig. 1 and its discussion (Sec. 4.2): for F5 and F6 at a = 1 the approximation
+    agrees with the exact D2 to a few per cent up to k = 5 h/Mpc for equilateral and
+    orthogonal triangles; for squeezed triangles it departs by up to ~10 % at
+    k >~ 1 h/Mpc; all configurations agree on large scales."""
+    p = Params(model=MODEL_FR, fr0_abs=fr0)
+    ks = np.geomspace(0.01, 5.0, 25)
+    r = {}
+    for cfg in ("equilateral", "orthogonal", "squeezed"):
+        k, k1, k2 = fig1_triangles(ks, cfg)
+        r[cfg] = solve_d2_triangle(k, k1, k2, [1.0], p)[0] / approx_d2_triangle(k, k1, k2, [1.0], p)[0]
+    for cfg in r:
+        assert np.all(np.abs(r[cfg][ks <= 0.05] - 1.0) < 5e-3), cfg
+    assert np.max(np.abs(r["equilateral"] - 1.0)) < 0.02
+    assert np.max(np.abs(r["orthogonal"] - 1.0)) < 0.03
+    sq = np.abs(r["squeezed"][ks >= 1.0] - 1.0)
+    assert 0.03 < sq.max() < 0.13
+    # the squeezed departure grows with k: the long mode k2 has LCDM-like growth
+    assert np.all(np.diff(r["squeezed"][ks >= 0.5]) < 0)
