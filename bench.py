@@ -262,12 +262,39 @@ def bench_triangles(C, torch, n=1 << 16):
                          "unit": "TFLOP/s", "frac": tflops / FP64_VECTOR_PEAK_TFLOPS}}
 
 
+def bench_models(C, torch, steps=3):
+    """ms per step of the other gravity models at the same 512^3 / 1024^3 size, from a
+    mid-run step: LCDM, f(R) F5 with LCDM growth factors (no per-step LPT transforms),
+    f(R) F5 with its own scale-dependent growth (six particle-grid inverse FFTs per step
+    rebuild the LPT terms, App. A)."""
+    base = dict(np1d=512, nmesh1d=1024, box=1024.0, z_init=19.0, n_steps=30, seed=1)
+    cases = {"lcdm": dict(model=C.LCDM), "fr5_lcdm_growth": dict(model=C.FR_HS1, fr0_abs=1e-5, growth_mode=1),
+             "fr5_scale_dependent": dict(model=C.FR_HS1, fr0_abs=1e-5, growth_mode=0)}
+    out = {}
+    for name, kw in cases.items():
+        p = C.Params(**base, **kw)
+        st = C.State(p, device="cuda:0")
+        C.cola_make_ic(p, st)
+        C.cola_step(p, st, 0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i in range(1, 1 + steps):
+            C.cola_step(p, st, i)
+        torch.cuda.synchronize()
+        out[name] = (time.perf_counter() - t0) * 1e3 / steps
+        del st
+        torch.cuda.empty_cache()
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=28)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-models", action="store_true",
+                    help="skip the per-step times of the other gravity models")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not record per-kernel HIP events in the timed region")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
@@ -370,6 +397,8 @@ def main():
         "kernels": kernels,
     }
     out["growth_triangles"] = bench_triangles(C, torch)
+    if not args.no_models:
+        out["other_models_ms_per_step"] = bench_models(C, torch)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()

@@ -178,12 +178,14 @@ def _min_image_rms_cells(x_gpu, x_or, p):
     return float(np.sqrt(np.mean(np.sum(d * d, axis=0)) / 3.0) / (p.box / p.nmesh1d))
 
 
-@pytest.mark.parametrize("model", [C.FR_HS1, C.NDGP, C.LCDM])
-def test_full_run_config1_positions_and_pk(model):
+@pytest.mark.parametrize("model,growth_mode", [(C.FR_HS1, 0), (C.NDGP, 0), (C.LCDM, 0),
+                                               (C.FR_HS1, 1)])
+def test_full_run_config1_positions_and_pk(model, growth_mode):
     # f(R) |fR0| = 1e-5 with screening, 32^3 particles, 64^3 mesh, L = 200 Mpc/h, 2LPT at
-    # z = 19, 10 steps to z = 0 (and the same run for nDGP r_c H0 = 1 and LCDM)
+    # z = 19, 10 steps to z = 0 (and the same run for nDGP r_c H0 = 1, LCDM, and f(R)
+    # with LCDM growth factors, the paper's production mode of Sec. 7.1)
     p = C.Params(model=model, fr0_abs=1e-5, rc_h0=1.0, np1d=32, nmesh1d=64, box=200.0,
-                 z_init=19.0, n_steps=10, seed=1)
+                 z_init=19.0, n_steps=10, seed=1, growth_mode=growth_mode)
     st = _ic_state(p)
     for i in range(p.n_steps):
         C.cola_step(p, st, i)
@@ -194,7 +196,7 @@ def test_full_run_config1_positions_and_pk(model):
     err = _min_image_rms_cells(xyz.cpu().numpy(), r.positions(), p)
     ko, Po, nmo = power_spectrum(r.u, to_oracle(p))
     half = p.nmesh1d // 4     # k <= k_Nyq / 2
-    record(f"run_config1_model{model}", pos_cells=err,
+    record(f"run_config1_model{model}_growth{growth_mode}", pos_cells=err,
            pk=np.max(np.abs(P[1:half] / Po[1:half] - 1)))
     assert err < 1e-3, err
     assert np.array_equal(nm[1:half], nmo[1:half].astype(np.int64))
