@@ -31,5 +31,5 @@ closed forms, limits, invariants or brute force, except where its docstring
 says "parity unpinned".
 """
 
-from .params import Params, MODEL_LCDM, MODEL_FR, MODEL_NDGP  # noqa: F401
+from .params import Params, MODEL_LCDM, MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON  # noqa: F401
 from .params import FILTER_GAUSS, FILTER_TOPHAT, FILTER_SHARPK  # noqa: F401

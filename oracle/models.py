@@ -17,8 +17,8 @@ Each model supplies, as functions of wavenumber k [h/Mpc] and scale factor a:
 import numpy as np
 
 from .background import E, omega_m_of_a
-from .params import (MODEL_LCDM, MODEL_FR, MODEL_NDGP, FILTER_GAUSS, FILTER_TOPHAT,
-                     FILTER_SHARPK, H0_OVER_C)
+from .params import (MODEL_LCDM, MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, FILTER_GAUSS,
+                     FILTER_TOPHAT, FILTER_SHARPK, H0_OVER_C)
 
 
 # ----------------------------------------------------------------------------- f(R)
@@ -84,6 +84,64 @@ def dgp_gamma2E_orth(a, om, rc):
     return -(rc * rc * om * om) / (6.0 * E(a, om) ** 2 * b ** 3 * a ** 6)
 
 
+# ----------------------------------------------------------------------------- symmetron
+# A {m(a), beta(a)} model (App. C): mu = 1 + 2 beta^2 k^2/(k^2 + a^2 m^2),
+# gamma_2^E = m^2 (dm^2/da) beta^2 Om / (2 H0^4 Pi(k) Pi(k1) Pi(k2)) k^2/(a^4 H^2) with
+# Pi(q) = (q/(a H0))^2 + m^2/H0^2, field equation nabla^2 phi = a^2 m^2 phi + 2 beta^2
+# kappa delta eps_screen, eps_screen = min(1, |Phi_crit/Phi_N|).  For the symmetron
+# beta = beta_* sqrt(s), m^2 = m_*^2 s, s = 1 - (a_*/a)^3 after a_* and beta = m = 0 before.
+def sym_s(a, astar):
+    a = np.asarray(a, dtype=np.float64)
+    return np.where(a > astar, 1.0 - (astar / np.maximum(a, 1e-300)) ** 3, 0.0)
+
+
+def sym_beta2(a, p):
+    return p.sym_beta ** 2 * sym_s(a, p.sym_astar)
+
+
+def sym_m2(a, p):
+    """m^2(a)/H0^2."""
+    return p.sym_mass ** 2 * sym_s(a, p.sym_astar)
+
+
+def sym_dm2_da(a, p):
+    """d(m^2/H0^2)/da = m_*^2/H0^2 * 3 a_*^3 / a^4 after a_*, else 0."""
+    a = np.asarray(a, dtype=np.float64)
+    return np.where(a > p.sym_astar, p.sym_mass ** 2 * 3.0 * p.sym_astar ** 3 / a ** 4, 0.0)
+
+
+def sym_a2m2(a, p):
+    """a^2 m^2(a) in (h/Mpc)^2 (H0 -> H0/c)."""
+    return a * a * H0_OVER_C ** 2 * sym_m2(a, p)
+
+
+def sym_mu(k, a, p):
+    k2 = np.asarray(k, dtype=np.float64) ** 2
+    b2 = sym_beta2(a, p)
+    if not np.any(b2 > 0):
+        return np.ones_like(k2)
+    return 1.0 + 2.0 * b2 * k2 / (k2 + sym_a2m2(a, p))
+
+
+def sym_gamma2E(k, k1, k2, a, p):
+    k = np.asarray(k, dtype=np.float64)
+    if not np.any(sym_s(a, p.sym_astar) > 0):
+        return np.zeros_like(k)
+    m2 = sym_m2(a, p)
+    Pi = lambda q: (np.asarray(q, dtype=np.float64) / (a * H0_OVER_C)) ** 2 + m2  # noqa: E731
+    H = E(a, p.omega_m) * H0_OVER_C
+    return (m2 * sym_dm2_da(a, p) * sym_beta2(a, p) * p.omega_m / (2.0 * Pi(k) * Pi(k1) * Pi(k2))
+            * k * k / (a ** 4 * H * H))
+
+
+def sym_phi_crit(p):
+    """Phi_crit of the symmetron from the App. C integral with Phi_crit(a_*) = 0:
+    (9 Om/(2 beta(a))) int_{a_*}^a beta/((m^2/H0^2) a'^4) da' = 3 Om/(a_*^3 m_*^2/H0^2),
+    the same at every a > a_*.  (The printed closed form is half of this; the integral,
+    which reproduces the f(R) value (3/2)|f_R(a)| exactly, is taken as the definition.)"""
+    return 3.0 * p.omega_m / (p.sym_astar ** 3 * p.sym_mass ** 2)
+
+
 # ----------------------------------------------------------------------------- dispatch
 class Model:
     """Model functions of a run (bound to its cosmology and model parameters)."""
@@ -103,6 +161,8 @@ class Model:
             return fr_mu(k, a, self.om, self.p.fr0_abs)
         if self.kind == MODEL_NDGP:
             return np.full_like(k, dgp_mu(a, self.om, self.p.rc_h0))
+        if self.kind == MODEL_SYMMETRON:
+            return sym_mu(k, a, self.p)
         raise ValueError(self.kind)
 
     def gamma2_orth(self, k, a):
@@ -114,24 +174,32 @@ class Model:
             return fr_gamma2E(k, kk, kk, a, self.om, self.p.fr0_abs)
         if self.kind == MODEL_NDGP:
             return np.full_like(k, dgp_gamma2E_orth(a, self.om, self.p.rc_h0))
+        if self.kind == MODEL_SYMMETRON:
+            kk = k / np.sqrt(2.0)
+            return sym_gamma2E(k, kk, kk, a, self.p)
         raise ValueError(self.kind)
 
     # --- N-body field equation (Sec. 6, App. B)
     @property
     def has_fifth_force(self):
-        return self.kind in (MODEL_FR, MODEL_NDGP)
+        return self.kind in (MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON)
 
     def a2m2(self, a):
         if self.kind == MODEL_FR:
             return float(fr_a2m2(a, self.om, self.p.fr0_abs))
+        if self.kind == MODEL_SYMMETRON:
+            return float(sym_a2m2(a, self.p))
         return 0.0
 
     def coupling(self, a):
-        """C(a): 1/3 for f(R) (Sec. 6.1), 1/(3 beta_DGP) for nDGP (Sec. 6.2)."""
+        """C(a): 1/3 for f(R) (Sec. 6.1), 1/(3 beta_DGP) for nDGP (Sec. 6.2), 2 beta^2(a)
+        for the symmetron (App. C)."""
         if self.kind == MODEL_FR:
             return 1.0 / 3.0
         if self.kind == MODEL_NDGP:
             return float(1.0 / (3.0 * dgp_beta(a, self.om, self.p.rc_h0)))
+        if self.kind == MODEL_SYMMETRON:
+            return float(2.0 * sym_beta2(a, self.p))   # C = 2 beta^2 (App. B, C)
         return 0.0
 
 
@@ -143,6 +211,15 @@ def eps_chameleon(phi_n, fR_abs):
     out = np.ones_like(phi_n)
     nz = phi_n != 0.0
     out[nz] = np.minimum(1.0, np.abs(1.5 * fR_abs / phi_n[nz]))
+    return out
+
+
+def eps_potential(phi_n, phi_crit):
+    """eps = min(1, |Phi_crit/Phi_N|) (App. C); eps = 1 where Phi_N = 0."""
+    phi_n = np.asarray(phi_n, dtype=np.float64)
+    out = np.ones_like(phi_n)
+    nz = phi_n != 0.0
+    out[nz] = np.minimum(1.0, np.abs(phi_crit / phi_n[nz]))
     return out
 
 

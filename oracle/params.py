@@ -14,6 +14,7 @@ from dataclasses import dataclass, replace
 MODEL_LCDM = 0
 MODEL_FR = 1      # Hu-Sawicki f(R), n = 1 (Sec. 5.1)
 MODEL_NDGP = 2    # normal-branch DGP (Sec. 5.2)
+MODEL_SYMMETRON = 3   # symmetron, a {m(a), beta(a)} model with potential screening (App. C)
 
 FILTER_GAUSS = 0
 FILTER_TOPHAT = 1
@@ -33,6 +34,9 @@ class Params:
     model: int = MODEL_LCDM
     fr0_abs: float = 1e-5
     rc_h0: float = 1.0
+    sym_beta: float = 1.0         # beta_* of the symmetron (App. C)
+    sym_mass: float = 2997.92458  # m_*/H0 (m_* = 1 h/Mpc: a 1 Mpc/h range)
+    sym_astar: float = 0.5        # a_*: beta = m = 0 before it
     screening: int = 1
     filter: int = FILTER_GAUSS
     r_smooth: float = 1.0
@@ -62,10 +66,11 @@ class Params:
 
     @property
     def scale_dependent(self):
-        """True when the LPT growth factors depend on k (Sec. 4): only f(R) run
-        with its own growth factors.  LCDM and nDGP have k-independent D1, D2
-        (Sec. 5.2), and growth_mode 1 forces the LCDM factors (Sec. 7.1)."""
-        return self.model == MODEL_FR and self.growth_mode == 0
+        """True when the LPT growth factors depend on k (Sec. 4): f(R) and the
+        symmetron run with their own growth factors.  LCDM and nDGP have
+        k-independent D1, D2 (Sec. 5.2), and growth_mode 1 forces the LCDM factors
+        (Sec. 7.1)."""
+        return self.model in (MODEL_FR, MODEL_SYMMETRON) and self.growth_mode == 0
 
     def with_(self, **kw):
         return replace(self, **kw)

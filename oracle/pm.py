@@ -23,9 +23,9 @@ import numpy as np
 
 from .background import kappa
 from .lpt import grad_factor, inv_laplacian, kvec
-from .models import (Model, eps_chameleon, eps_vainshtein, vainshtein_x, window,
-                     fr_fR_abs, dgp_beta)
-from .params import MODEL_FR, MODEL_NDGP, H0_OVER_C
+from .models import (Model, eps_chameleon, eps_potential, eps_vainshtein, vainshtein_x, window,
+                     fr_fR_abs, dgp_beta, sym_phi_crit)
+from .params import MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, H0_OVER_C
 
 
 def lagrangian_index(n_p):
@@ -95,10 +95,13 @@ def screened_source(delta, delta_k, p, a, model):
     n, L = p.nmesh1d, p.box
     if not p.screening or not model.has_fifth_force:
         return delta.copy()
-    if p.model == MODEL_FR:
+    if p.model in (MODEL_FR, MODEL_SYMMETRON):
         Phi = np.fft.irfftn(-kappa(a, p.omega_m) * delta_k * inv_laplacian(n, L), s=(n, n, n), axes=(0, 1, 2))
         phi_n = Phi * H0_OVER_C ** 2 / (a * a)
-        eps = eps_chameleon(phi_n, fr_fR_abs(a, p.omega_m, p.fr0_abs))
+        if p.model == MODEL_FR:
+            eps = eps_chameleon(phi_n, fr_fR_abs(a, p.omega_m, p.fr0_abs))
+        else:
+            eps = eps_potential(phi_n, sym_phi_crit(p))
     elif p.model == MODEL_NDGP:
         (kx, ky, kz), _ = kvec(n, L)
         k = np.sqrt(kx * kx + ky * ky + kz * kz)

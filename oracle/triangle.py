@@ -29,8 +29,8 @@ from scipy import integrate
 
 from .background import E, kappa, dlna_dtau, omega_m_of_a
 from .growth import solve_growth
-from .models import Model, fr_gamma2E, dgp_gamma2E_orth
-from .params import MODEL_FR, MODEL_NDGP
+from .models import Model, fr_gamma2E, dgp_gamma2E_orth, sym_gamma2E
+from .params import MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON
 
 
 def cos_theta(k, k1, k2):
@@ -38,13 +38,15 @@ def cos_theta(k, k1, k2):
 
 
 def gamma2E(model, k, k1, k2, a):
-    """gamma_2^E of the model at the triangle (Secs. 5.1-5.2); zero for LCDM and for
-    runs with LCDM growth factors."""
+    """gamma_2^E of the model at the triangle (Secs. 5.1-5.2, App. C); zero for LCDM and
+    for runs with LCDM growth factors."""
     k, k1, k2 = (np.asarray(x, dtype=np.float64) for x in (k, k1, k2))
-    if model.lcdm_growth or model.kind not in (MODEL_FR, MODEL_NDGP):
+    if model.lcdm_growth or model.kind not in (MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON):
         return np.zeros_like(k)
     if model.kind == MODEL_FR:
         return fr_gamma2E(k, k1, k2, a, model.om, model.p.fr0_abs)
+    if model.kind == MODEL_SYMMETRON:
+        return sym_gamma2E(k, k1, k2, a, model.p)
     c = cos_theta(k, k1, k2)
     return dgp_gamma2E_orth(a, model.om, model.p.rc_h0) * (1.0 - c * c)
 

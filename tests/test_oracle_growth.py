@@ -286,3 +286,75 @@ def test_fig1_ratios_of_exact_to_approximate_d2(fr0):
     assert 0.03 < sq.max() < 0.13
     # the squeezed departure grows with k: the long mode k2 has LCDM-like growth
     assert np.all(np.diff(r["squeezed"][ks >= 0.5]) < 0)
+
+
+# ----------------------------------------------------------------------------- symmetron
+from oracle import MODEL_SYMMETRON  # noqa: E402
+from oracle.models import (eps_potential, sym_a2m2, sym_beta2, sym_dm2_da, sym_gamma2E,  # noqa: E402
+                           sym_m2, sym_mu, sym_phi_crit)
+
+SYM = Params(model=MODEL_SYMMETRON, sym_beta=1.0, sym_mass=2997.92458, sym_astar=0.5)
+
+
+def test_symmetron_phi_crit_is_the_app_c_integral():
+    """Phi_crit(a) = (9 Om/(2 beta(a))) int_{a_*}^a beta/((m^2/H0^2) a'^4) da' (App. C),
+    evaluated by quadrature with the (a' - a_*)^(-1/2) endpoint singularity as a weight."""
+    p, ast = SYM, SYM.sym_astar
+    for a in (0.55, 0.8, 1.0):
+        def f(x):   # beta/(m^2 a^4) with (x - a_*)^(-1/2) taken out
+            return (p.sym_beta * x ** 1.5
+                    / (p.sym_mass ** 2 * x ** 4 * np.sqrt(x * x + x * ast + ast * ast)))
+        I, _ = integrate.quad(f, ast, a, weight="alg", wvar=(-0.5, 0.0), epsabs=0, epsrel=1e-13)
+        phi = 4.5 * p.omega_m / np.sqrt(sym_beta2(a, p)) * I
+        assert phi == pytest.approx(sym_phi_crit(p), rel=1e-11)
+
+
+def test_symmetron_mu_limits_and_switch_on():
+    p = SYM
+    for a in (0.2, 0.5):            # beta = m = 0 up to a_*
+        assert sym_mu(np.array([0.01, 1.0, 100.0]), a, p) == pytest.approx(1.0, abs=0)
+        assert sym_gamma2E(np.array([1.0]), 0.7, 0.7, a, p)[0] == 0.0
+        assert Model(p).coupling(a) == 0.0
+    a = 0.8
+    s = 1 - (0.5 / a) ** 3
+    assert sym_mu(1e-9, a, p) == pytest.approx(1.0, abs=1e-12)
+    assert sym_mu(1e9, a, p) == pytest.approx(1 + 2 * s, rel=1e-12)
+    am = np.sqrt(sym_a2m2(a, p))
+    assert sym_mu(am, a, p) == pytest.approx(1 + s, rel=1e-14)   # k = a m
+    assert Model(p).coupling(a) == pytest.approx(2 * s, rel=1e-14)
+
+
+def test_symmetron_gamma2_matches_general_m_beta_form():
+    # App. C: gamma_2^E = m^2 (dm^2/da) beta^2 Om / (2 H0^4 Pi Pi Pi) k^2/(a^4 H^2), with
+    # dm^2/da taken here by finite differences of m^2(a)
+    p = SYM
+    for a in (0.6, 1.0):
+        h = 1e-6 * a
+        dm2 = (sym_m2(a + h, p) - sym_m2(a - h, p)) / (2 * h)
+        assert dm2 == pytest.approx(sym_dm2_da(a, p), rel=1e-8)
+        for k, k1, k2 in [(0.1, 0.2, 0.15), (1.0, 0.7071, 0.7071), (3.0, 1.0, 2.5)]:
+            Pi = lambda q: (q / (a * H0_OVER_C)) ** 2 + sym_m2(a, p)     # noqa: E731
+            H = E(a, p.omega_m) * H0_OVER_C
+            gen = sym_m2(a, p) * dm2 * sym_beta2(a, p) * p.omega_m / (2 * Pi(k) * Pi(k1) * Pi(k2)) \
+                * k * k / (a ** 4 * H * H)
+            assert float(sym_gamma2E(k, k1, k2, a, p)) == pytest.approx(gen, rel=1e-7)
+
+
+def test_symmetron_growth_lcdm_until_astar_then_scale_dependent():
+    p = SYM
+    model = Model(p)
+    k = np.array([1e-4, 0.1, 1.0, 5.0])
+    a = np.array([p.a_ini, 0.3, 0.5, 0.75, 1.0])
+    G = solve_growth(k, a, p.omega_m, model.mu, model.gamma2_orth, p.a_ini)
+    L = solve_growth(k, a, p.omega_m, ONE, ZERO, p.a_ini)
+    assert np.max(np.abs(G[:3] / L[:3] - 1)) < 1e-10          # a <= a_*: LCDM (solver tol.)
+    assert np.all(np.diff(G[-1, :, 0]) > 0)                  # enhanced growth on small scales
+    assert G[-1, 0, 0] == pytest.approx(L[-1, 0, 0], rel=1e-6)   # k << a m: LCDM
+
+
+def test_potential_screening_limits():
+    pc = sym_phi_crit(SYM)
+    assert np.all(eps_potential(np.array([1e-3, -1e-3]) * pc, pc) == 1.0)
+    deep = np.array([1e3, -3e4]) * pc
+    assert eps_potential(deep, pc) == pytest.approx(np.abs(pc / deep), rel=1e-15)
+    assert eps_potential(np.array([0.0]), pc)[0] == 1.0

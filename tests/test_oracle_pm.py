@@ -275,6 +275,8 @@ PLANAR_CASES = {
     "fr_screened_r1": dict(model=MODEL_FR, fr0_abs=1e-7, np1d=24, nmesh1d=24, box=60.0),
     "fr_unscreened_r2": dict(model=MODEL_FR, fr0_abs=1e-5, screening=0, np1d=12, nmesh1d=24,
                              box=48.0),
+    "symmetron_r2": dict(model=3, sym_beta=1.0, sym_mass=2997.92458, sym_astar=0.5, np1d=16,
+                         nmesh1d=32, box=32.0),
 }
 
 
