@@ -40,10 +40,12 @@ typedef int32_t cola_status;
 #define COLA_E_HIP (-4)          /* a HIP runtime call failed */
 #define COLA_E_UNSUPPORTED (-5)  /* valid request this build does not implement */
 
-/* Gravity models (Sec. 5): LCDM, Hu-Sawicki f(R) with n = 1, normal-branch DGP. */
+/* Gravity models (Sec. 5, App. C): LCDM, Hu-Sawicki f(R) with n = 1, normal-branch DGP,
+ * and the symmetron, a {m(a), beta(a)} model with potential screening. */
 #define COLA_LCDM 0
 #define COLA_FR_HS1 1
 #define COLA_NDGP 2
+#define COLA_SYMMETRON 3
 
 /* Fourier-space smoothing windows for density (Vainshtein) screening (App. B). */
 #define COLA_SMOOTH_GAUSS 0
@@ -59,8 +61,9 @@ typedef int32_t cola_status;
  * sigma8 > 0, t_cmb > 0, np1d and nmesh1d of the form 2^a 3^b with b <= 1,
  * 8 <= np1d <= 1024, np1d <= nmesh1d <= min(2048, 4 np1d), nmesh1d a multiple of np1d,
  * box > 0, z_init > 0,
- * 1 <= n_steps <= 4096, fr0_abs > 0 for f(R), rc_h0 > 0 for nDGP, r_smooth >= 0,
- * filter in 0..2, model in 0..2, growth_mode in 0..1, screening in 0..1. */
+ * 1 <= n_steps <= 4096, fr0_abs > 0 for f(R), rc_h0 > 0 for nDGP, sym_beta >= 0,
+ * sym_mass > 0 and 0 < sym_astar < 1 for the symmetron, r_smooth >= 0, filter in 0..2,
+ * model in 0..3, growth_mode in 0..1, screening in 0..1. */
 typedef struct cola_params {
   double omega_m, omega_b, h, n_s, sigma8, t_cmb;
   double fr0_abs;     /* |f_R0| of Hu-Sawicki f(R) (Sec. 5.1) */
@@ -71,6 +74,13 @@ typedef struct cola_params {
   uint64_t seed;      /* seed of the counter-based white noise */
   int32_t model, screening, filter, growth_mode;
   int32_t np1d, nmesh1d, n_steps, reserved;
+  /* symmetron (App. C): beta(a) = sym_beta sqrt(s), m^2(a) = (sym_mass H0)^2 s with
+   * s = 1 - (sym_astar / a)^3 after a = sym_astar, beta = m = 0 before; the field equation
+   * couples with C = 2 beta^2 and screens with eps = min(1, |Phi_crit/Phi_N|), Phi_crit the
+   * App. C integral 3 Omega_m / (sym_astar^3 sym_mass^2) */
+  double sym_beta;    /* beta_star */
+  double sym_mass;    /* m_star / H0 (dimensionless; 2997.92458 is a 1 Mpc/h range) */
+  double sym_astar;   /* a_star */
 } cola_params;
 
 /* Byte sizes of the caller-owned device buffers of one state. */

@@ -15,14 +15,18 @@ import numpy as np
 from scipy import integrate
 
 from .background import E, kappa, dlna_dtau
+from .params import MODEL_SYMMETRON
 
 
-def solve_growth(k, a_out, om, mu_fn, g2_fn, a_ini, rtol=1e-12, atol=1e-14):
+def solve_growth(k, a_out, om, mu_fn, g2_fn, a_ini, rtol=1e-12, atol=1e-14, breaks=()):
     """Return an array G[len(a_out), len(k), 6] of (D1, D1', D1'', D2, D2', D2'')
     at the requested scale factors (a_out sorted ascending, a_out[0] >= a_ini).
 
     mu_fn(k, a) and g2_fn(k, a) give mu and gamma_2 at the orthogonal triangle.
     D'' is taken from the right-hand side of the ODE at each output time.
+    breaks: scale factors where the right-hand side is not smooth (the symmetron's
+    switch-on at a_*, App. C); the integration restarts there with a tiny first step, so
+    that the narrow feature that follows is resolved rather than stepped over.
     """
     k = np.atleast_1d(np.asarray(k, dtype=np.float64))
     a_out = np.asarray(a_out, dtype=np.float64)
@@ -49,11 +53,7 @@ def solve_growth(k, a_out, om, mu_fn, g2_fn, a_ini, rtol=1e-12, atol=1e-14):
     out = np.empty((a_out.size, K, 6))
     need = a_out > a_ini
     if np.any(need):
-        sol = integrate.solve_ivp(rhs, (a_ini, float(a_out[-1])), y0, method="DOP853",
-                                  t_eval=a_out[need], rtol=rtol, atol=atol)
-        if not sol.success:
-            raise RuntimeError(sol.message)
-        Ys = iter(sol.y.T)
+        Ys = iter(_integrate_pieces(rhs, y0, a_ini, a_out[need], breaks, rtol, atol))
     for i, a in enumerate(a_out):
         y = next(Ys) if need[i] else y0
         dD1, dd1, dD2, dd2 = rhs_tau(a, y)
@@ -64,6 +64,28 @@ def solve_growth(k, a_out, om, mu_fn, g2_fn, a_ini, rtol=1e-12, atol=1e-14):
         out[i, :, 4] = dD2
         out[i, :, 5] = dd2
     return out
+
+
+def _integrate_pieces(rhs, y0, a0, a_eval, breaks, rtol, atol):
+    """DOP853 from a0 through the sorted a_eval, restarted at every break point inside;
+    returns the states at a_eval."""
+    a_end = float(a_eval[-1])
+    cuts = [a0] + sorted(b for b in breaks if a0 < b < a_end) + [a_end]
+    ys, y = [], y0
+    for j in range(len(cuts) - 1):
+        lo, hi = cuts[j], cuts[j + 1]
+        sel = a_eval[(a_eval > lo) & (a_eval <= hi)]
+        t_eval = np.unique(np.concatenate([sel, [hi]]))
+        kw = dict(first_step=1e-12 * hi) if j > 0 else {}
+        sol = integrate.solve_ivp(rhs, (lo, hi), y, method="DOP853", t_eval=t_eval, rtol=rtol,
+                                  atol=atol, **kw)
+        if not sol.success:
+            raise RuntimeError(sol.message)
+        for t, col in zip(sol.t, sol.y.T):
+            if np.any(sel == t):
+                ys.append(col)
+        y = sol.y[:, -1]
+    return ys
 
 
 def distinct_n2(n):
@@ -80,11 +102,18 @@ def growth_table(p, model, a_out):
     k = 2 pi sqrt(|nu|^2) / L, so no interpolation in k is ever needed.
     Returns G[len(a_out), n_k, 6] and a flag saying whether it is k-dependent.
     """
+    breaks = growth_breaks(p, model)
     if not p.scale_dependent:
         G = solve_growth(np.array([0.0]), a_out, p.omega_m, model.mu, model.gamma2_orth,
-                         p.a_ini)
+                         p.a_ini, breaks=breaks)
         return G, False
     n2 = distinct_n2(p.np1d)
     k = 2.0 * np.pi * np.sqrt(n2.astype(np.float64)) / p.box
-    G = solve_growth(k, a_out, p.omega_m, model.mu, model.gamma2_orth, p.a_ini)
+    G = solve_growth(k, a_out, p.omega_m, model.mu, model.gamma2_orth, p.a_ini, breaks=breaks)
     return G, True
+
+
+def growth_breaks(p, model):
+    """Scale factors where the growth equations' right-hand side is not smooth: a_* of the
+    symmetron run with its own growth factors (App. C)."""
+    return (p.sym_astar,) if (model.kind == MODEL_SYMMETRON and not model.lcdm_growth) else ()

@@ -25,10 +25,9 @@ k and gamma_2 is proportional to (1 - cos^2 theta) (Sec. 4.2).
 """
 
 import numpy as np
-from scipy import integrate
 
 from .background import E, kappa, dlna_dtau, omega_m_of_a
-from .growth import solve_growth
+from .growth import _integrate_pieces, growth_breaks, solve_growth
 from .models import Model, fr_gamma2E, dgp_gamma2E_orth, sym_gamma2E
 from .params import MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON
 
@@ -81,11 +80,8 @@ def solve_d2_triangle(k, k1, k2, a_out, p, rtol=1e-12, atol=1e-14):
     out = np.empty((a_out.size, n))
     need = a_out > p.a_ini
     if np.any(need):
-        sol = integrate.solve_ivp(rhs, (p.a_ini, float(a_out[-1])), y0, method="DOP853",
-                                  t_eval=a_out[need], rtol=rtol, atol=atol)
-        if not sol.success:
-            raise RuntimeError(sol.message)
-        ys = iter(sol.y.T)
+        ys = iter(_integrate_pieces(rhs, y0, p.a_ini, a_out[need], growth_breaks(p, model), rtol,
+                                    atol))
     for i in range(a_out.size):
         y = next(ys) if need[i] else y0
         out[i] = y[4 * n:5 * n]
@@ -97,7 +93,8 @@ def approx_d2_triangle(k, k1, k2, a_out, p):
     model = Model(p)
     k, k1, k2 = (np.atleast_1d(np.asarray(x, dtype=np.float64)) for x in (k, k1, k2))
     c = cos_theta(k, k1, k2)
-    G = solve_growth(k, np.atleast_1d(a_out), p.omega_m, model.mu, model.gamma2_orth, p.a_ini)
+    G = solve_growth(k, np.atleast_1d(a_out), p.omega_m, model.mu, model.gamma2_orth, p.a_ini,
+                     breaks=growth_breaks(p, model))
     return G[:, :, 3] * (1.0 - c * c)
 
 

@@ -16,7 +16,7 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("COLA_LIBRARY") or os.path.join(_PKG, "_lib", "libcola.so")
 
 COLA_OK = 0
-LCDM, FR_HS1, NDGP = 0, 1, 2
+LCDM, FR_HS1, NDGP, SYMMETRON = 0, 1, 2, 3
 SMOOTH_GAUSS, SMOOTH_TOPHAT, SMOOTH_SHARPK = 0, 1, 2
 
 EXPORTED = ["cola_query_sizes", "cola_validate", "cola_prepare", "cola_make_ic", "cola_pm_force",
@@ -41,7 +41,9 @@ class _Params(ctypes.Structure):
                 ("model", ctypes.c_int32), ("screening", ctypes.c_int32),
                 ("filter", ctypes.c_int32), ("growth_mode", ctypes.c_int32),
                 ("np1d", ctypes.c_int32), ("nmesh1d", ctypes.c_int32),
-                ("n_steps", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("n_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("sym_beta", ctypes.c_double), ("sym_mass", ctypes.c_double),
+                ("sym_astar", ctypes.c_double)]
 
 
 class _Sizes(ctypes.Structure):
@@ -67,6 +69,9 @@ class Params:
     t_cmb: float = 2.7255
     fr0_abs: float = 1e-5
     rc_h0: float = 1.0
+    sym_beta: float = 1.0
+    sym_mass: float = 2997.92458
+    sym_astar: float = 0.5
     r_smooth: float = 1.0
     box: float = 200.0
     z_init: float = 19.0

@@ -217,7 +217,7 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
     KOp op = base;
     op.scale = invM;
     int kind = K_SMOOTH;
-    if (p.model == COLA_FR_HS1) {
+    if (p.model == COLA_FR_HS1 || p.model == COLA_SYMMETRON) {   // potential screening
       op.g_n = -sc.kappa;
       kind = K_POT;
     } else {

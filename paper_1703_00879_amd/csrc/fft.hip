@@ -917,7 +917,7 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
     ProfScope ps("fft_z_screen", s);
     constexpr int BR = RowCfg<N / 2>::B;
     const dim3 g((unsigned)((rows + BR - 1) / BR)), b(RowCfg<N / 2>::T);
-    if (model == COLA_FR_HS1)
+    if (model == COLA_FR_HS1 || model == COLA_SYMMETRON)   // eps = min(1, thr/|Phi|)
       hipLaunchKernelGGL((k_fft_screen_row<N / 2, COLA_FR_HS1>), g, b, 0, s, data, rho, s_out, rows, n,
                          P, pl.plane, pl.tw, thr, vx);
     else

@@ -120,7 +120,7 @@ StepScalars step_scalars(const cola_params& p, double a) {
   const double E = std::sqrt(om / (a * a * a) + ol);
   s.a = a;
   s.kappa = (float)(1.5 * om * a);
-  s.fifth = (p.model == COLA_FR_HS1 || p.model == COLA_NDGP) ? 1 : 0;
+  s.fifth = (p.model == COLA_FR_HS1 || p.model == COLA_NDGP || p.model == COLA_SYMMETRON) ? 1 : 0;
   s.screen = s.fifth && p.screening;
   if (p.model == COLA_FR_HS1) {
     const double X = om / (a * a * a) + 4.0 * ol, Y = om + 4.0 * ol;
@@ -129,6 +129,15 @@ StepScalars step_scalars(const cola_params& p, double a) {
     s.coupling = (float)(1.0 / 3.0);
     const double fR = p.fr0_abs * (Y / X) * (Y / X);
     s.cham_thr = (float)(1.5 * fR * a * a / (kH0c * kH0c));
+  } else if (p.model == COLA_SYMMETRON) {
+    // App. C: C = 2 beta^2, a^2 m^2, and the potential threshold Phi_crit a^2/(H0/c)^2 on
+    // the code potential; before a_* the coupling is zero and the force Newtonian
+    const double as = p.sym_astar / a;
+    const double sv = a > p.sym_astar ? 1.0 - as * as * as : 0.0;
+    s.a2m2 = (float)(a * a * kH0c * kH0c * p.sym_mass * p.sym_mass * sv);
+    s.coupling = (float)(2.0 * p.sym_beta * p.sym_beta * sv);
+    const double phi_crit = 3.0 * om / (p.sym_astar * p.sym_astar * p.sym_astar * p.sym_mass * p.sym_mass);
+    s.cham_thr = (float)(phi_crit * a * a / (kH0c * kH0c));
   } else if (p.model == COLA_NDGP) {
     const double oma = om / (a * a * a) / (E * E);
     const double beta = 1.0 + 2.0 * p.rc_h0 * E * (1.0 - 0.5 * oma);
@@ -153,7 +162,10 @@ void validate(const cola_params& p) {
   if (!(p.omega_b >= 0 && p.omega_b < p.omega_m)) bad("omega_b must be in [0, omega_m)");
   if (!(p.h > 0) || !(p.sigma8 > 0) || !(p.t_cmb > 0)) bad("h, sigma8 and t_cmb must be > 0");
   if (!std::isfinite(p.n_s)) bad("n_s must be finite");
-  if (p.model < 0 || p.model > 2) bad("model must be 0 (LCDM), 1 (f(R)) or 2 (nDGP)");
+  if (p.model < 0 || p.model > 3) bad("model must be 0 (LCDM), 1 (f(R)), 2 (nDGP) or 3 (symmetron)");
+  if (p.model == COLA_SYMMETRON &&
+      !(p.sym_beta >= 0 && p.sym_mass > 0 && p.sym_astar > 0 && p.sym_astar < 1))
+    bad("symmetron needs sym_beta >= 0, sym_mass > 0, 0 < sym_astar < 1");
   if (p.model == COLA_FR_HS1 && !(p.fr0_abs > 0)) bad("fr0_abs must be > 0 for f(R)");
   if (p.model == COLA_NDGP && !(p.rc_h0 > 0)) bad("rc_h0 must be > 0 for nDGP");
   if (p.screening < 0 || p.screening > 1) bad("screening must be 0 or 1");
@@ -185,7 +197,7 @@ Layout make_layout(const cola_params& p) {
   L.plane_m = plane_stride(L.nm);
   L.pgrid_elems = (size_t)L.np * L.plane_p;
   L.mesh_elems = (size_t)L.nm * L.plane_m;
-  L.kdep = (p.model == COLA_FR_HS1 && p.growth_mode == 0);
+  L.kdep = ((p.model == COLA_FR_HS1 || p.model == COLA_SYMMETRON) && p.growth_mode == 0);
   L.n_k = L.kdep ? 3 * (int64_t)(L.np / 2) * (L.np / 2) + 1 : 1;
   L.n_steps = p.n_steps;
   size_t o = 0;

@@ -25,6 +25,7 @@ constexpr double kH0c = 1.0 / 2997.92458;   // H0/c in h/Mpc
 
 struct GrowthDev {
   double om, fr0, rc, a_ini, kf;
+  double sb, sm, sa;  // symmetron beta_*, m_*/H0, a_*
   int model;          // effective model for the growth (LCDM when growth_mode = 1)
   int kdep;           // table indexed by |nu|^2
   int n_steps;
@@ -32,6 +33,115 @@ struct GrowthDev {
 };
 
 __device__ __forceinline__ double dE(double a, double om) { return sqrt(om / (a * a * a) + 1.0 - om); }
+
+// One classical fourth-order Runge-Kutta step of length h in ln a.
+template <int NV, class Rhs>
+__device__ __forceinline__ void rk4_step(double* y, double lna, double h, const Rhs& rhs) {
+  double k1[NV], k2[NV], k3[NV], k4[NV], yt[NV];
+  rhs(lna, y, k1);
+  for (int c = 0; c < NV; ++c) yt[c] = y[c] + 0.5 * h * k1[c];
+  rhs(lna + 0.5 * h, yt, k2);
+  for (int c = 0; c < NV; ++c) yt[c] = y[c] + 0.5 * h * k2[c];
+  rhs(lna + 0.5 * h, yt, k3);
+  for (int c = 0; c < NV; ++c) yt[c] = y[c] + h * k3[c];
+  rhs(lna + h, yt, k4);
+  for (int c = 0; c < NV; ++c) y[c] += h / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
+}
+
+// RK4 in ln a from lna to le in equal steps <= 1e-3.
+template <int NV, class Rhs>
+__device__ __forceinline__ void rk4_segment(double* y, double& lna, double le, const Rhs& rhs) {
+  const int nsub = (int)ceil((le - lna) / 1e-3);
+  if (nsub <= 0) return;
+  const double h = (le - lna) / nsub;
+  for (int s = 0; s < nsub; ++s) {
+    rk4_step<NV>(y, lna, h, rhs);
+    lna = (s + 1 == nsub) ? le : lna + h;
+  }
+}
+
+// RK4 from lna to l1 for a right-hand side that switches on at l_kink (the symmetron at
+// a_*; -1e300 for the other models).  A step boundary falls exactly on l_kink.  Just after
+// it the symmetron's gamma_2 term has a peak whose width in ln a scales as
+// (k / (a_* m_*))^2, far below 1e-3 for the fundamental mode of a large box; the steps
+// there start at 1e-10 and grow geometrically (h = 1e-10 + 0.02 (ln a - l_kink)) until
+// they reach the 1e-3 of the rest of the integration.
+template <int NV, class Rhs>
+__device__ __forceinline__ void rk4_to(double* y, double& lna, double l1, double l_kink, const Rhs& rhs) {
+  if (lna < l_kink && l_kink < l1) rk4_segment<NV>(y, lna, l_kink, rhs);
+  if (lna >= l_kink) {
+    while (lna < l1) {
+      const double h = 1e-10 + 0.02 * (lna - l_kink);
+      if (h >= 1e-3) break;
+      if (h >= l1 - lna) {
+        rk4_step<NV>(y, lna, l1 - lna, rhs);
+        lna = l1;
+      } else {
+        rk4_step<NV>(y, lna, h, rhs);
+        lna += h;
+      }
+    }
+  }
+  rk4_segment<NV>(y, lna, l1, rhs);
+}
+
+__device__ __forceinline__ double growth_kink(const GrowthDev& g) {
+  return g.model == COLA_SYMMETRON ? log(g.sa) : -1e300;
+}
+
+// mu(k, a) of the model (Secs. 5.1, 5.2, App. C)
+__device__ __forceinline__ double growth_mu(const GrowthDev& g, double k, double a) {
+  if (g.model == COLA_FR_HS1) {
+    const double ol = 1.0 - g.om;
+    const double X = g.om / (a * a * a) + 4.0 * ol, Y = g.om + 4.0 * ol;
+    const double r = X / Y;
+    const double a2m2 = a * a * kH0c * kH0c * Y * r * r * r / (2.0 * g.fr0);
+    return 1.0 + k * k / (3.0 * (k * k + a2m2));
+  }
+  if (g.model == COLA_NDGP) {
+    const double E = dE(a, g.om);
+    const double oma = g.om / (a * a * a) / (E * E);
+    return 1.0 + 1.0 / (3.0 * (1.0 + 2.0 * g.rc * E * (1.0 - 0.5 * oma)));
+  }
+  if (g.model == COLA_SYMMETRON) {   // App. C: 1 + 2 beta^2 k^2/(k^2 + a^2 m^2)
+    if (a <= g.sa) return 1.0;
+    const double r = g.sa / a, s = 1.0 - r * r * r;
+    const double a2m2 = a * a * kH0c * kH0c * g.sm * g.sm * s;
+    return 1.0 + 2.0 * g.sb * g.sb * s * k * k / (k * k + a2m2);
+  }
+  return 1.0;
+}
+
+// 2 a^4 H^2 gamma_2^E(k, k1, k2, a) (Secs. 5.1, 5.2); c2 = cos^2 theta
+__device__ __forceinline__ double gamma2E_term(const GrowthDev& g, double k, double k1, double k2,
+                                               double c2, double a) {
+  const double E = dE(a, g.om);
+  const double a6 = (a * a * a) * (a * a * a);
+  double g2 = 0.0;
+  if (g.model == COLA_FR_HS1) {
+    const double ol = 1.0 - g.om;
+    const double X = g.om / (a * a * a) + 4.0 * ol, Y = g.om + 4.0 * ol;
+    const double c0 = X * X * X / (2.0 * g.fr0 * Y * Y);
+    const double ah = a * kH0c;
+    const double P = k * k / (ah * ah) + c0, P1 = k1 * k1 / (ah * ah) + c0, P2 = k2 * k2 / (ah * ah) + c0;
+    const double kah = k / (ah * E);
+    g2 = -9.0 * g.om * g.om / (48.0 * a6 * g.fr0 * g.fr0) * kah * kah * (X * X * X * X * X) / (Y * Y * Y * Y)
+         / (P * P1 * P2);
+  } else if (g.model == COLA_NDGP) {
+    const double oma = g.om / (a * a * a) / (E * E);
+    const double beta = 1.0 + 2.0 * g.rc * E * (1.0 - 0.5 * oma);
+    g2 = -(g.rc * g.rc * g.om * g.om) / (6.0 * E * E * beta * beta * beta * a6) * (1.0 - c2);
+  } else if (g.model == COLA_SYMMETRON && a > g.sa) {
+    // App. C: m^2 (dm^2/da) beta^2 Om / (2 H0^4 Pi Pi Pi) k^2/(a^4 H^2), Pi(q) = (q/(aH0))^2 + m^2/H0^2
+    const double r = g.sa / a, s = 1.0 - r * r * r;
+    const double m2 = g.sm * g.sm * s, dm2 = g.sm * g.sm * 3.0 * g.sa * g.sa * g.sa / (a * a * a * a);
+    const double ah = a * kH0c;
+    const double P = k * k / (ah * ah) + m2, P1 = k1 * k1 / (ah * ah) + m2, P2 = k2 * k2 / (ah * ah) + m2;
+    const double H = E * kH0c;
+    g2 = m2 * dm2 * g.sb * g.sb * s * g.om / (2.0 * P * P1 * P2) * k * k / (a * a * a * a * H * H);
+  }
+  return 2.0 * a * a * a * a * E * E * g2;
+}
 
 // mu(k, a) and 2 a^4 H^2 gamma_2(k, k/sqrt2, k/sqrt2, a) for the growth equations
 __device__ __forceinline__ void growth_model(const GrowthDev& g, double k, double a, double& mu,
@@ -60,6 +170,9 @@ __device__ __forceinline__ void growth_model(const GrowthDev& g, double k, doubl
     mu = 1.0 + 1.0 / (3.0 * beta);
     const double g2 = -(g.rc * g.rc * g.om * g.om) / (6.0 * E * E * beta * beta * beta * ((a * a * a) * (a * a * a)));
     g2term = 2.0 * a * a * a * a * E * E * g2;
+  } else if (g.model == COLA_SYMMETRON) {
+    mu = growth_mu(g, k, a);
+    g2term = gamma2E_term(g, k, k * M_SQRT1_2, k * M_SQRT1_2, 0.0, a);
   } else {
     mu = 1.0;
     g2term = 0.0;
@@ -67,8 +180,8 @@ __device__ __forceinline__ void growth_model(const GrowthDev& g, double k, doubl
 }
 
 // d y / d ln a for y = (D1, D1', D2, D2'), ' = d/dtau; d/dln a = (a^2 E)^-1 d/dtau
-__device__ __forceinline__ void growth_rhs(const GrowthDev& g, double k, double lna, const double y[4],
-                                           double dy[4]) {
+__device__ __forceinline__ void growth_rhs(const GrowthDev& g, double k, double lna, const double* y,
+                                           double* dy) {
   const double a = exp(lna);
   double mu, g2t;
   growth_model(g, k, a, mu, g2t);
@@ -93,7 +206,7 @@ __device__ __forceinline__ void store_slice(const GrowthDev& g, double k, double
   out[5] = kap * mu * y[2] - kap * mu * y[0] * y[0] - g2t * y[0] * y[0];
 }
 
-__global__ void k_growth_ode(GrowthDev g, double* __restrict__ table, double* __restrict__ ref) {
+__global__ void __launch_bounds__(64) k_growth_ode(GrowthDev g, double* __restrict__ table, double* __restrict__ ref) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t > g.n_k) return;
   GrowthDev gg = g;
@@ -112,22 +225,8 @@ __global__ void k_growth_ode(GrowthDev g, double* __restrict__ table, double* __
   for (int i = 0; i < nsl; ++i) {
     const double a_target = (t == g.n_k) ? 1.0 : ai + i * (1.0 - ai) / g.n_steps;
     const double l1 = log(a_target);
-    const int nsub = (int)ceil((l1 - lna) / 1e-3);
-    if (nsub > 0) {
-      const double h = (l1 - lna) / nsub;
-      for (int s = 0; s < nsub; ++s) {
-        double k1[4], k2[4], k3[4], k4[4], yt[4];
-        growth_rhs(gg, k, lna, y, k1);
-        for (int c = 0; c < 4; ++c) yt[c] = y[c] + 0.5 * h * k1[c];
-        growth_rhs(gg, k, lna + 0.5 * h, yt, k2);
-        for (int c = 0; c < 4; ++c) yt[c] = y[c] + 0.5 * h * k2[c];
-        growth_rhs(gg, k, lna + 0.5 * h, yt, k3);
-        for (int c = 0; c < 4; ++c) yt[c] = y[c] + h * k3[c];
-        growth_rhs(gg, k, lna + h, yt, k4);
-        for (int c = 0; c < 4; ++c) y[c] += h / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
-        lna = (s + 1 == nsub) ? l1 : lna + h;
-      }
-    }
+    rk4_to<4>(y, lna, l1, growth_kink(gg),
+              [&](double l, const double* yy, double* dy) { growth_rhs(gg, k, l, yy, dy); });
     if (t == g.n_k)
       store_slice(gg, k, a_target, y, ref);
     else
@@ -145,6 +244,9 @@ void launch_growth_ode(const cola_params& p, const Layout& L, double* table, dou
   g.a_ini = 1.0 / (1.0 + p.z_init);
   g.kf = 2.0 * M_PI / p.box;
   g.model = (p.growth_mode == 1) ? COLA_LCDM : p.model;
+  g.sb = p.sym_beta;
+  g.sm = p.sym_mass;
+  g.sa = p.sym_astar;
   g.kdep = L.kdep ? 1 : 0;
   g.n_steps = p.n_steps;
   g.n_k = L.n_k;
@@ -163,52 +265,13 @@ void launch_growth_ode(const cola_params& p, const Layout& L, double* table, dou
 // with D2 = -(3/7)(1 - cos^2 theta), D2' = -(6/7)(1 - cos^2 theta) a^2 E at a_ini; the
 // terms that single out k1 are taken as printed.  Same integrator as k_growth_ode.
 
-__device__ __forceinline__ double growth_mu(const GrowthDev& g, double k, double a) {
-  if (g.model == COLA_FR_HS1) {
-    const double ol = 1.0 - g.om;
-    const double X = g.om / (a * a * a) + 4.0 * ol, Y = g.om + 4.0 * ol;
-    const double r = X / Y;
-    const double a2m2 = a * a * kH0c * kH0c * Y * r * r * r / (2.0 * g.fr0);
-    return 1.0 + k * k / (3.0 * (k * k + a2m2));
-  }
-  if (g.model == COLA_NDGP) {
-    const double E = dE(a, g.om);
-    const double oma = g.om / (a * a * a) / (E * E);
-    return 1.0 + 1.0 / (3.0 * (1.0 + 2.0 * g.rc * E * (1.0 - 0.5 * oma)));
-  }
-  return 1.0;
-}
-
-// 2 a^4 H^2 gamma_2^E(k, k1, k2, a) (Secs. 5.1, 5.2); c2 = cos^2 theta
-__device__ __forceinline__ double gamma2E_term(const GrowthDev& g, double k, double k1, double k2,
-                                               double c2, double a) {
-  const double E = dE(a, g.om);
-  const double a6 = (a * a * a) * (a * a * a);
-  double g2 = 0.0;
-  if (g.model == COLA_FR_HS1) {
-    const double ol = 1.0 - g.om;
-    const double X = g.om / (a * a * a) + 4.0 * ol, Y = g.om + 4.0 * ol;
-    const double c0 = X * X * X / (2.0 * g.fr0 * Y * Y);
-    const double ah = a * kH0c;
-    const double P = k * k / (ah * ah) + c0, P1 = k1 * k1 / (ah * ah) + c0, P2 = k2 * k2 / (ah * ah) + c0;
-    const double kah = k / (ah * E);
-    g2 = -9.0 * g.om * g.om / (48.0 * a6 * g.fr0 * g.fr0) * kah * kah * (X * X * X * X * X) / (Y * Y * Y * Y)
-         / (P * P1 * P2);
-  } else if (g.model == COLA_NDGP) {
-    const double oma = g.om / (a * a * a) / (E * E);
-    const double beta = 1.0 + 2.0 * g.rc * E * (1.0 - 0.5 * oma);
-    g2 = -(g.rc * g.rc * g.om * g.om) / (6.0 * E * E * beta * beta * beta * a6) * (1.0 - c2);
-  }
-  return 2.0 * a * a * a * a * E * E * g2;
-}
-
 // y = (D1(k1), D1'(k1), D1(k2), D1'(k2), D1(k), D1'(k), D2, D2', D2_hat, D2_hat')
 struct Triangle {
   double k, k1, k2, c, c2;
 };
 
 __device__ __forceinline__ void triangle_rhs(const GrowthDev& g, const Triangle& t, double lna,
-                                             const double y[10], double dy[10]) {
+                                             const double* y, double* dy) {
   const double a = exp(lna);
   const double E = dE(a, g.om);
   const double kap = 1.5 * g.om * a;
@@ -232,7 +295,7 @@ __device__ __forceinline__ void triangle_rhs(const GrowthDev& g, const Triangle&
   dy[9] = (kap * muh * y[8] - kap * muh * y[4] * y[4] - g2h * y[4] * y[4]) * f;
 }
 
-__global__ void k_growth_triangle(GrowthDev g, int n, const double* __restrict__ tri, double a_end,
+__global__ void __launch_bounds__(64) k_growth_triangle(GrowthDev g, int n, const double* __restrict__ tri, double a_end,
                                   double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -253,23 +316,8 @@ __global__ void k_growth_triangle(GrowthDev g, int n, const double* __restrict__
   double y[10] = {1.0, g0, 1.0, g0, 1.0, g0, -3.0 / 7.0 * s2, -6.0 / 7.0 * s2 * g0, -3.0 / 7.0,
                   -6.0 / 7.0 * g0};
   double lna = log(ai);
-  const double l1 = log(a_end);
-  const int nsub = (int)ceil((l1 - lna) / 1e-3);
-  if (nsub > 0) {
-    const double h = (l1 - lna) / nsub;
-    for (int s = 0; s < nsub; ++s) {
-      double k1[10], k2[10], k3[10], k4[10], yt[10];
-      triangle_rhs(g, t, lna, y, k1);
-      for (int c = 0; c < 10; ++c) yt[c] = y[c] + 0.5 * h * k1[c];
-      triangle_rhs(g, t, lna + 0.5 * h, yt, k2);
-      for (int c = 0; c < 10; ++c) yt[c] = y[c] + 0.5 * h * k2[c];
-      triangle_rhs(g, t, lna + 0.5 * h, yt, k3);
-      for (int c = 0; c < 10; ++c) yt[c] = y[c] + h * k3[c];
-      triangle_rhs(g, t, lna + h, yt, k4);
-      for (int c = 0; c < 10; ++c) y[c] += h / 6.0 * (k1[c] + 2.0 * k2[c] + 2.0 * k3[c] + k4[c]);
-      lna = (s + 1 == nsub) ? l1 : lna + h;
-    }
-  }
+  rk4_to<10>(y, lna, log(a_end), growth_kink(g),
+             [&](double l, const double* yy, double* dy) { triangle_rhs(g, t, l, yy, dy); });
   out[2 * i] = y[6];
   out[2 * i + 1] = y[8] * s2;
 }
@@ -283,6 +331,9 @@ void launch_growth_triangles(const cola_params& p, int n, const double* tri, dou
   g.rc = p.rc_h0;
   g.a_ini = 1.0 / (1.0 + p.z_init);
   g.model = (p.growth_mode == 1) ? COLA_LCDM : p.model;
+  g.sb = p.sym_beta;
+  g.sm = p.sym_mass;
+  g.sa = p.sym_astar;
   hipLaunchKernelGGL(k_growth_triangle, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, g, n, tri, a,
                      out);
   COLA_LAUNCH_CHECK();

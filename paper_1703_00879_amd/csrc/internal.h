@@ -97,7 +97,8 @@ double eh_transfer(const cola_params& p, double k);
 struct StepScalars {         // PM-force scalars at scale factor a
   double a;
   float kappa, a2m2, coupling;
-  float cham_thr;   // f(R): screening threshold on |Phi_code|: (3/2)|f_R(a)| a^2 / (H0/c)^2
+  float cham_thr;   // potential screening threshold on |Phi_code|: Phi_crit(a) a^2/(H0/c)^2,
+                    // Phi_crit = (3/2)|f_R(a)| for f(R), the App. C integral for the symmetron
   float vx_pref;    // nDGP: x = vx_pref (1 + delta_R), 8 (rc H0)^2 Om / (9 beta^2 a^3)
   float beta;
   int fifth, screen;  // fifth force on, screening on
@@ -195,8 +196,6 @@ void launch_combine_u0(const Layout& L, const float* psi1, const float* psi2,
 void launch_deposit(const Layout& L, const float* disp, float* rho_padded, void* bins,
                     float4* entries, hipStream_t s);
 size_t bins_bytes(int64_t ntiles);
-void launch_screen(const cola_params& p, const Layout& L, const StepScalars& sc,
-                   const float* rho, float* field_inout, hipStream_t s);
 struct GatherArgs {
   const float* F3;            // interleaved force mesh (F_x, F_y, F_z) per cell
   float* disp;

@@ -420,48 +420,6 @@ void launch_deposit(const Layout& L, const float* disp, float* rho, void* bins, 
   COLA_LAUNCH_CHECK();
 }
 
-// ------------------------------------------------------------------ real-space screening
-// S = delta * eps_screen in place over the padded real mesh (row padding left alone).
-// f(R):  eps = min(1, thr / |Phi|), thr = (3/2)|f_R(a)| a^2 / (H0/c)^2 (Sec. 6.1)
-// nDGP:  eps = 2 / (1 + sqrt(1 + x)), x = vx (1 + delta_R)_+ (Sec. 6.2)
-template <int MODEL>
-__global__ void __launch_bounds__(256)
-k_screen(const float* __restrict__ rho, float* __restrict__ field, int64_t rows, int n,
-         int rpitch, int64_t rplane, float thr, float vx) {
-  const int64_t total = rows * n;
-  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
-       e += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t r = e / n;
-    const int z = (int)(e - r * n);
-    const int64_t i = (r / n) * rplane + (r % n) * rpitch + z;
-    const float delta = rho[i] - 1.f;
-    const float g = field[i];
-    float eps;
-    if (MODEL == COLA_FR_HS1) {
-      const float ag = fabsf(g);
-      eps = (ag > thr) ? thr / ag : 1.f;
-    } else {
-      const float x = vx * fmaxf(0.f, 1.f + g);
-      eps = 2.f / (1.f + sqrtf(1.f + x));
-    }
-    field[i] = delta * eps;
-  }
-}
-
-void launch_screen(const cola_params& p, const Layout& L, const StepScalars& sc, const float* rho,
-                   float* field, hipStream_t s) {
-  ProfScope ps("screen", s);
-  const int64_t rows = (int64_t)L.nm * L.nm;
-  const unsigned g = grid_for(rows * L.nm, 256);
-  if (p.model == COLA_FR_HS1)
-    hipLaunchKernelGGL(k_screen<COLA_FR_HS1>, dim3(g), dim3(256), 0, s, rho, field, rows, L.nm,
-                       2 * L.pitch_m, 2 * L.plane_m, sc.cham_thr, 0.f);
-  else
-    hipLaunchKernelGGL(k_screen<COLA_NDGP>, dim3(g), dim3(256), 0, s, rho, field, rows, L.nm,
-                       2 * L.pitch_m, 2 * L.plane_m, 0.f, sc.vx_pref);
-  COLA_LAUNCH_CHECK();
-}
-
 // ------------------------------------------------------------------ gather + kick + drift
 struct GatherDev {
   const float* F3;   // interleaved force mesh, 3 floats per cell, unpadded rows

@@ -69,7 +69,7 @@ def test_white_noise_integer_stream_and_gaussians():
 
 
 @pytest.mark.parametrize("model,growth_mode", [(C.LCDM, 0), (C.FR_HS1, 0), (C.NDGP, 0),
-                                               (C.FR_HS1, 1)])
+                                               (C.FR_HS1, 1), (C.SYMMETRON, 0)])
 def test_growth_tables_fp64(model, growth_mode):
     p = C.Params(model=model, growth_mode=growth_mode, np1d=16, nmesh1d=32, box=100.0,
                  n_steps=5)
@@ -102,6 +102,10 @@ PM_CASES = {
     "ragged_12_24": dict(model=C.FR_HS1, fr0_abs=1e-7, np1d=12, nmesh1d=24, box=48.0, a=0.6, rms=1.0),
     "ratio1_32_32": dict(model=C.LCDM, np1d=32, nmesh1d=32, box=100.0, a=1.0, rms=1.0),
     "mesh3x_16_48": dict(model=C.FR_HS1, fr0_abs=1e-6, np1d=16, nmesh1d=48, box=48.0, a=1.0, rms=1.5),
+    "symmetron_screened": dict(model=C.SYMMETRON, np1d=32, nmesh1d=64, box=64.0, a=0.8, rms=2.0,
+                               clustered=True),
+    "symmetron_before_astar": dict(model=C.SYMMETRON, np1d=16, nmesh1d=32, box=32.0, a=0.4,
+                                   rms=1.0, clustered=True),
 }
 
 
@@ -141,7 +145,7 @@ def _ic_state(p):
     return st
 
 
-@pytest.mark.parametrize("model", [C.LCDM, C.FR_HS1, C.NDGP])
+@pytest.mark.parametrize("model", [C.LCDM, C.FR_HS1, C.NDGP, C.SYMMETRON])
 def test_initial_conditions_match_oracle(model):
     p = C.Params(model=model, np1d=32, nmesh1d=64, box=200.0, n_steps=10, seed=3)
     st = _ic_state(p)
@@ -153,7 +157,7 @@ def test_initial_conditions_match_oracle(model):
     assert float(st.vel_f.abs().max()) == 0.0
 
 
-@pytest.mark.parametrize("model", [C.FR_HS1, C.NDGP])
+@pytest.mark.parametrize("model", [C.FR_HS1, C.NDGP, C.SYMMETRON])
 def test_single_step_matches_oracle(model):
     p = C.Params(model=model, np1d=32, nmesh1d=64, box=200.0, n_steps=10, seed=5)
     st = _ic_state(p)
@@ -179,7 +183,7 @@ def _min_image_rms_cells(x_gpu, x_or, p):
 
 
 @pytest.mark.parametrize("model,growth_mode", [(C.FR_HS1, 0), (C.NDGP, 0), (C.LCDM, 0),
-                                               (C.FR_HS1, 1)])
+                                               (C.FR_HS1, 1), (C.SYMMETRON, 0)])
 def test_full_run_config1_positions_and_pk(model, growth_mode):
     # f(R) |fR0| = 1e-5 with screening, 32^3 particles, 64^3 mesh, L = 200 Mpc/h, 2LPT at
     # z = 19, 10 steps to z = 0 (and the same run for nDGP r_c H0 = 1, LCDM, and f(R)
@@ -237,7 +241,8 @@ def test_step_order_and_state_errors():
 # ----------------------------------------------------------------------------- triangles
 TRI_CASES = {"f5": dict(model=C.FR_HS1, fr0_abs=1e-5), "f6": dict(model=C.FR_HS1, fr0_abs=1e-6),
              "f5_lcdm_growth": dict(model=C.FR_HS1, fr0_abs=1e-5, growth_mode=1),
-             "ndgp": dict(model=C.NDGP, rc_h0=0.5), "lcdm": dict(model=C.LCDM)}
+             "ndgp": dict(model=C.NDGP, rc_h0=0.5), "lcdm": dict(model=C.LCDM),
+             "symmetron": dict(model=C.SYMMETRON)}
 
 
 @pytest.mark.parametrize("name", list(TRI_CASES))

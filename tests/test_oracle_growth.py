@@ -358,3 +358,43 @@ def test_potential_screening_limits():
     deep = np.array([1e3, -3e4]) * pc
     assert eps_potential(deep, pc) == pytest.approx(np.abs(pc / deep), rel=1e-15)
     assert eps_potential(np.array([0.0]), pc)[0] == 1.0
+
+
+def test_symmetron_growth_resolves_the_switch_on():
+    """Just after a_* the symmetron's gamma_2 term has a narrow peak for small k (its
+    width in s = 1 - (a_*/a)^3 scales as (k/(a_* m_*))^2).  The oracle restarts its
+    adaptive integration at a_*; a fixed-step RK4 in ln a whose steps grow geometrically
+    from 1e-10 after a_* must agree with it, for the fundamental mode of a 1024 Mpc/h box."""
+    from oracle.growth import growth_table
+    p = SYM.with_(np1d=16, nmesh1d=32, box=1024.0, n_steps=4)
+    model = Model(p)
+    a_grid = p.a_ini + np.arange(5) * (1 - p.a_ini) / 4
+    G, _ = growth_table(p, model, a_grid)
+    k = 2 * np.pi * np.sqrt(np.arange(G.shape[1], dtype=float)) / p.box
+    om = p.omega_m
+
+    def rhs(lna, y):
+        a = np.exp(lna)
+        kap, Ea = 1.5 * om * a, E(a, om)
+        mu, g2 = model.mu(k, a), model.gamma2_orth(k, a)
+        f = 1 / (a * a * Ea)
+        return np.array([y[1] * f, kap * mu * y[0] * f, y[3] * f,
+                         (kap * mu * y[2] - kap * mu * y[0] ** 2 - 2 * a ** 4 * Ea * Ea * g2 * y[0] ** 2) * f])
+
+    g0 = p.a_ini ** 2 * E(p.a_ini, om)
+    y = np.array([np.ones_like(k), g0 + 0 * k, -3 / 7 + 0 * k, -6 / 7 * g0 + 0 * k])
+    lna, lk = np.log(p.a_ini), np.log(p.sym_astar)
+    for i in range(1, 5):
+        l1 = np.log(a_grid[i])
+        while lna < l1 - 1e-15:
+            h = 1e-3 if lna < lk - 1e-15 else min(1e-3, 1e-10 + 0.02 * (lna - lk))
+            if lna < lk < lna + h:
+                h = lk - lna
+            h = min(h, l1 - lna)
+            k1 = rhs(lna, y)
+            k2 = rhs(lna + h / 2, y + h / 2 * k1)
+            k3 = rhs(lna + h / 2, y + h / 2 * k2)
+            k4 = rhs(lna + h, y + h * k3)
+            y, lna = y + h / 6 * (k1 + 2 * k2 + 2 * k3 + k4), lna + h
+        assert np.max(np.abs(y[0] / G[i, :, 0] - 1)) < 1e-10
+        assert np.max(np.abs(y[2] / G[i, :, 3] - 1)) < 1e-10
