@@ -266,19 +266,24 @@ def bench_models(C, torch, steps=3):
     """ms per step of the other gravity models at the same 512^3 / 1024^3 size, from a
     mid-run step: LCDM, f(R) F5 with LCDM growth factors (no per-step LPT transforms),
     f(R) F5 with its own scale-dependent growth (six particle-grid inverse FFTs per step
-    rebuild the LPT terms, App. A)."""
+    rebuild the LPT terms, App. A), and the symmetron of App. C (beta_* = 1, m_*/H0 = 2998,
+    a_* = 0.5) timed after a_*, where its fifth force is on."""
     base = dict(np1d=512, nmesh1d=1024, box=1024.0, z_init=19.0, n_steps=30, seed=1)
-    cases = {"lcdm": dict(model=C.LCDM), "fr5_lcdm_growth": dict(model=C.FR_HS1, fr0_abs=1e-5, growth_mode=1),
-             "fr5_scale_dependent": dict(model=C.FR_HS1, fr0_abs=1e-5, growth_mode=0)}
+    cases = {"lcdm": (dict(model=C.LCDM), 1),
+             "fr5_lcdm_growth": (dict(model=C.FR_HS1, fr0_abs=1e-5, growth_mode=1), 1),
+             "fr5_scale_dependent": (dict(model=C.FR_HS1, fr0_abs=1e-5, growth_mode=0), 1),
+             "symmetron_scale_dependent": (dict(model=C.SYMMETRON, sym_beta=1.0,
+                                                sym_mass=2997.92458, sym_astar=0.5), 16)}
     out = {}
-    for name, kw in cases.items():
+    for name, (kw, first) in cases.items():
         p = C.Params(**base, **kw)
         st = C.State(p, device="cuda:0")
         C.cola_make_ic(p, st)
-        C.cola_step(p, st, 0)
+        for i in range(first):
+            C.cola_step(p, st, i)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        for i in range(1, 1 + steps):
+        for i in range(first, first + steps):
             C.cola_step(p, st, i)
         torch.cuda.synchronize()
         out[name] = (time.perf_counter() - t0) * 1e3 / steps
