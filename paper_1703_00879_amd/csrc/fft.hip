@@ -459,6 +459,34 @@ struct RowCfg {
   static constexpr int LS = B + 1;   // odd LDS stride: transposed row loads stay conflict-light
 };
 
+// Split step of a forward real transform: B rows held in LDS as Z (the NC-point transform
+// of x_even + i x_odd, lds[k * LS + c]) give the NC + 1 half-complex values
+//   X_k = (Z_k + conj Z_{NC-k})/2 - (i/2) w^k (Z_k - conj Z_{NC-k}),  w = exp(-2 pi i / n),
+// handed to store(c, k, X_k).  Thread tid takes elements tid + i T (E T = NC B) and the
+// Nyquist value X_NC of row tid < B.
+template <int NC, int E, int B, int LS, int T, class Store>
+__device__ __forceinline__ void split_fwd_store(const float2* lds, const float2* tw, int tid,
+                                                const Store& store) {
+  auto val = [](float2 zk, float2 zc, float2 w) {
+    const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
+    const float2 od = make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y - zc.y));
+    const float2 t = cmul(w, od);   // w^k (Z_k - conj Z_{NC-k}) / 2
+    return make_float2(ev.x + t.y, ev.y - t.x);   // ev - i t
+  };
+#pragma unroll
+  for (int i = 0; i < E; ++i) {
+    const int e = tid + i * T;
+    const int c = e / NC, k = e % NC;
+    const float2 zk = lds[k * LS + c];
+    const float2 zc = cconj(lds[(k == 0 ? 0 : NC - k) * LS + c]);
+    store(c, k, val(zk, zc, tw[k]));
+  }
+  if (tid < B) {
+    const float2 z0 = lds[tid];
+    store(tid, NC, val(z0, cconj(z0), make_float2(-1.f, 0.f)));
+  }
+}
+
 // Forward Z pass: real rows of n = 2 NC floats (pitch 2*pitch floats) -> half-complex rows
 // of NC + 1 values (pitch `pitch`).  Twiddles tw[t] = exp(-2 pi i t / n).
 template <int NC>
@@ -493,19 +521,11 @@ k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nr
   }
   __syncthreads();
   lds_fft<NC, -1, E, B, LS, 2>(lds, tid, T, tw);
-  // X_k = (Z_k + conj Z_{NC-k})/2 - (i/2) w^k (Z_k - conj Z_{NC-k}),  w = exp(-2 pi i / n)
-  for (int e = tid; e < (NC + 1) * B; e += T) {
-    const int c = e / (NC + 1), k = e % (NC + 1);
-    if (r0 + c >= (O)nrows) continue;
-    const float2 zk = lds[(k == NC ? 0 : k) * LS + c];
-    const float2 zc = cconj(lds[(k == 0 ? 0 : NC - k) * LS + c]);
-    const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
-    const float2 od = make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y - zc.y));
-    const float2 w = (k == NC) ? make_float2(-1.f, 0.f) : tw[k];
-    const float2 t = cmul(w, od);          // w^k (Z_k - conj Z_{NC-k}) / 2
+  split_fwd_store<NC, E, B, LS, T>(lds, tw, tid, [&](int c, int k, float2 v) {
+    if (r0 + c >= (O)nrows) return;
     const O r = r0 + c;
-    out[(r / kN) * (O)plane + (r % kN) * (O)pitch + k] = make_float2(ev.x + t.y, ev.y - t.x);   // ev - i t
-  }
+    out[(r / kN) * (O)plane + (r % kN) * (O)pitch + k] = v;
+  });
 }
 
 // Inverse Z pass: half-complex rows (NC + 1 values) -> real rows of n = 2 NC floats,
@@ -640,19 +660,24 @@ k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
   }
   __syncthreads();
   lds_fft<NC, +1, E, B, LS, 2>(tile, lt, TC, tw);   // ends with a barrier
-  // element m of row c in tile t holds cells (2m, 2m + 1) of component t
+  // element m of row c in tile t holds cells (2m, 2m + 1) of component t; a wave writes
+  // 64 consecutive float4s, float 4q + j of the block being component t of cell w / 3
+  // (w the float's place in its row), so only the first float of each needs a division
   const O rows_here = (O)nrows - r0 < (O)B ? (O)nrows - r0 : (O)B;
-  const int nq = (int)rows_here * (kRowF / 4);
+  constexpr int kQ = kRowF / 4;   // float4s per interleaved row
+  const int nq = (int)rows_here * kQ;
   float4* dst = reinterpret_cast<float4*>(out + (O3)r0 * kRowF);
+  const float* tiles = reinterpret_cast<const float*>(&lds[0][0]);
   for (int q = tid; q < nq; q += T) {
+    const int c = q / kQ;
+    const int w0 = 4 * (q - c * kQ);
+    const int cell0 = w0 / 3, t0 = w0 - 3 * cell0;
     float v[4];
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
-      const int f = 4 * q + j;
-      const int c = f / kRowF, w = f % kRowF;
-      const int cell = w / 3, t = w % 3;
-      const float2 pr = lds[t][(cell >> 1) * LS + c];
-      v[j] = (cell & 1) ? pr.y : pr.x;
+      const bool wrap = t0 + j >= 3;   // t0 + j <= 5
+      const int t = wrap ? t0 + j - 3 : t0 + j, cell = wrap ? cell0 + 1 : cell0;
+      v[j] = tiles[2 * (t * NC * LS + (cell >> 1) * LS + c) + (cell & 1)];
     }
     dst[q] = make_float4(v[0], v[1], v[2], v[3]);
   }
@@ -719,12 +744,12 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
       float2 sv;
       if (MODEL == COLA_FR_HS1) {
         const float a0 = fabsf(f.x), a1 = fabsf(f.y);
-        sv = make_float2((rv[i].x - 1.f) * (a0 > thr ? thr / a0 : 1.f),
-                         (rv[i].y - 1.f) * (a1 > thr ? thr / a1 : 1.f));
+        sv = make_float2((rv[i].x - 1.f) * (a0 > thr ? thr * fast_rcp(a0) : 1.f),
+                         (rv[i].y - 1.f) * (a1 > thr ? thr * fast_rcp(a1) : 1.f));
       } else {
         const float x0 = vx * fmaxf(0.f, 1.f + f.x), x1 = vx * fmaxf(0.f, 1.f + f.y);
-        sv = make_float2((rv[i].x - 1.f) * (2.f / (1.f + sqrtf(1.f + x0))),
-                         (rv[i].y - 1.f) * (2.f / (1.f + sqrtf(1.f + x1))));
+        sv = make_float2((rv[i].x - 1.f) * (2.f * fast_rcp(1.f + fast_sqrt(1.f + x0))),
+                         (rv[i].y - 1.f) * (2.f * fast_rcp(1.f + fast_sqrt(1.f + x1))));
       }
       lds[m * LS + c] = sv;
       if (s_out && r0 + c < (O)nrows) {
@@ -735,18 +760,11 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
   }
   __syncthreads();
   lds_fft<NC, -1, E, B, LS, 2>(lds, tid, T, tw);
-  for (int e = tid; e < (NC + 1) * B; e += T) {
-    const int c = e / (NC + 1), k = e % (NC + 1);
-    if (r0 + c >= (O)nrows) continue;
-    const float2 zk = lds[(k == NC ? 0 : k) * LS + c];
-    const float2 zc = cconj(lds[(k == 0 ? 0 : NC - k) * LS + c]);
-    const float2 ev = make_float2(0.5f * (zk.x + zc.x), 0.5f * (zk.y + zc.y));
-    const float2 od = make_float2(0.5f * (zk.x - zc.x), 0.5f * (zk.y - zc.y));
-    const float2 w = (k == NC) ? make_float2(-1.f, 0.f) : tw[k];
-    const float2 t = cmul(w, od);
+  split_fwd_store<NC, E, B, LS, T>(lds, tw, tid, [&](int c, int k, float2 v) {
+    if (r0 + c >= (O)nrows) return;
     const O r = r0 + c;
-    data[(r / kN) * (O)plane + (r % kN) * (O)pitch + k] = make_float2(ev.x + t.y, ev.y - t.x);
-  }
+    data[(r / kN) * (O)plane + (r % kN) * (O)pitch + k] = v;
+  });
 }
 
 // ------------------------------------------------------------------ dispatch

@@ -12,8 +12,17 @@
 
 namespace cola {
 
+// Hardware reciprocal, square root and base-2 exponential (each within about 1 ulp): the
+// correctly rounded library forms expand to ten or more instructions apiece, which the
+// per-mode operators and the screening factors cannot afford in issue-limited passes.
+__device__ __forceinline__ float fast_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+__device__ __forceinline__ float fast_sqrt(float x) { return __builtin_amdgcn_sqrtf(x); }
+__device__ __forceinline__ float fast_exp(float x) {
+  return __builtin_amdgcn_exp2f(x * 1.44269504088896340736f);
+}
+
 __device__ __forceinline__ float smooth_window(float k2R2, int filter) {
-  if (filter == 0) return expf(-0.5f * k2R2);                 // Gaussian
+  if (filter == 0) return fast_exp(-0.5f * k2R2);             // Gaussian
   if (filter == 2) return k2R2 <= 1.f ? 1.f : 0.f;            // sharp-k, k R <= 1
   // spherical top-hat 3 (sin x - x cos x)/x^3; its Taylor series below x = 1/2, where
   // the closed form cancels in single precision
@@ -46,14 +55,14 @@ __device__ __forceinline__ float2 kspace_apply(const KOp& op, int ix, int iy, in
   } else if constexpr (KIND == K_FORCE) {
     if (n2 == 0 || nyq_c) return make_float2(0.f, 0.f);
     const float k2 = op.kf * op.kf * (float)n2;
-    const float gn = op.g_n / k2, g5 = op.g_5 / (k2 + op.a2m2);
+    const float gn = op.g_n * fast_rcp(k2), g5 = op.g_5 * fast_rcp(k2 + op.a2m2);
     const float2 g = make_float2(gn * a.x + g5 * b.x, gn * a.y + g5 * b.y);
     const float f = k_c * op.scale;   // -i k_c g
     return make_float2(f * g.y, -f * g.x);
   } else if constexpr (KIND == K_POT) {
     if (n2 == 0) return make_float2(0.f, 0.f);
     const float k2 = op.kf * op.kf * (float)n2;
-    const float f = op.g_n / k2 * op.scale;
+    const float f = op.g_n * fast_rcp(k2) * op.scale;
     return make_float2(f * a.x, f * a.y);
   } else if constexpr (KIND == K_SMOOTH) {
     if (n2 == 0) return make_float2(0.f, 0.f);
@@ -114,7 +123,7 @@ __device__ __forceinline__ float2 green_force(const KOp& op, int ix, int iy, int
   const int n2 = nx * nx + ny * ny + iz * iz;
   if (n2 == 0) return make_float2(0.f, 0.f);
   const float k2 = op.kf * op.kf * (float)n2;
-  const float gn = op.g_n / k2 * op.scale, g5 = op.g_5 / (k2 + op.a2m2) * op.scale;
+  const float gn = op.g_n * fast_rcp(k2) * op.scale, g5 = op.g_5 * fast_rcp(k2 + op.a2m2) * op.scale;
   return make_float2(gn * a.x + g5 * b.x, gn * a.y + g5 * b.y);
 }
 

@@ -43,6 +43,13 @@ __device__ __forceinline__ void cic_cell(int64_t p, int np, int nm, int ratio, f
   cic_axis(iz, disp[2 * N + p], nm, ratio, inv_cell, c.i0[2], c.i1[2], c.w0[2], c.w1[2]);
 }
 
+static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
+static int ilog2(int v) {
+  int l = 0;
+  while ((1 << (l + 1)) <= v) ++l;
+  return l;
+}
+
 static unsigned grid_for(int64_t n, int block, int64_t cap = 1 << 20) {
   return (unsigned)std::max<int64_t>(1, std::min<int64_t>((n + block - 1) / block, cap));
 }
@@ -76,7 +83,8 @@ void launch_fill(float* p, size_t n, float v, hipStream_t s) {
 //     -- from every particle of its own tile and from the class-c particles of the seven
 //     lower neighbour tiles T - delta with (c & delta) == delta -- and writes the tile
 //     once with plain stores, so the mesh needs no zeroing pass.
-constexpr int kBrickX = 4, kBrickY = 8, kBrickZ = 8;   // 256 particles per work-group
+constexpr int kBrickX = 4, kBrickY = 8, kBrickZ = 8;   // 256 particles per brick
+constexpr int kBinBricks = 4;                           // bricks per binning work-group
 constexpr int kScanBlock = 1024;                        // tiles per scan block
 constexpr float kFix = 16777216.f;                      // 2^24: deposit fixed-point unit
 
@@ -87,23 +95,41 @@ size_t bins_bytes(int64_t ntiles) {
 
 struct BinGeo {
   int np, nm, ratio, nt1, tile;
+  int lt;         // log2(tile); the tile side is always a power of two
+  int lnp, lnm;   // log2(np), log2(nm) when both are powers of two (the P2 kernels)
   float inv_cell;
   int64_t N;
 };
 
 // Lower CIC corner (cell) and offset of one axis; the same arithmetic as cic_axis().
+// P2: nm is a power of two, and the wrap is a mask (exact for negative cells too).
+template <bool P2>
 __device__ __forceinline__ int axis_cell(int ixq, float u, const BinGeo& g, float& d) {
   const float f = 0.5f + u * g.inv_cell;
   const float fl = floorf(f);
   d = f - fl;
+  if (P2) return (ixq * g.ratio + (int)fl) & (g.nm - 1);
   int i = (ixq * g.ratio + (int)fl) % g.nm;
   return i < 0 ? i + g.nm : i;
 }
 
-__device__ __forceinline__ bool brick_particle(const BinGeo& g, int& ix, int& iy, int& iz, int64_t& p) {
+template <bool P2>
+__device__ __forceinline__ bool brick_particle(const BinGeo& g, int b, int& ix, int& iy, int& iz,
+                                               int64_t& p) {
   const int nbz = (g.np + kBrickZ - 1) / kBrickZ, nby = (g.np + kBrickY - 1) / kBrickY;
-  const int b = (int)xcd_block(blockIdx.x, gridDim.x);
-  const int bz = b % nbz, by = (b / nbz) % nby, bx = b / (nbz * nby);
+  const int nbx = (g.np + kBrickX - 1) / kBrickX;
+  if (b >= nbx * nby * nbz) return false;
+  int bz, by, bx;
+  if (P2 && g.np >= kBrickY) {   // np / 8 bricks per axis, a power of two
+    const int l = g.lnp - 3;
+    bz = b & ((1 << l) - 1);
+    by = (b >> l) & ((1 << l) - 1);
+    bx = b >> (2 * l);
+  } else {
+    bz = b % nbz;
+    by = (b / nbz) % nby;
+    bx = b / (nbz * nby);
+  }
   const int t = threadIdx.x;
   ix = bx * kBrickX + (t >> 6);
   iy = by * kBrickY + ((t >> 3) & 7);
@@ -115,62 +141,91 @@ __device__ __forceinline__ bool brick_particle(const BinGeo& g, int& ix, int& iy
 
 // MODE 0: count into cnt[tile*8 + cls];  MODE 1: scatter the particle's CIC record
 // (dx, dy, dz, lower corner relative to its home tile) to entries[cur[tile*8 + cls]++].
-// The lanes of a wave that share a (tile, class) key are served by one atomic that adds
-// their number; in MODE 1 each lane takes the returned base plus its rank among them.  A
-// wave holds an 8 x 8 patch of one lattice plane, so it meets only a few keys.
-template <int MODE>
+// A work-group takes kBinBricks consecutive bricks and each thread one particle of each,
+// with all displacement loads issued up front.  The lanes of a wave that share a
+// (tile, class) key are served by one atomic that adds their number; in MODE 1 each lane
+// takes the returned base plus its rank among them.  A wave holds an 8 x 8 patch of one
+// lattice plane, so it meets only a few keys.
+template <int MODE, bool P2>
 __global__ void __launch_bounds__(256)
 k_bin(const float* __restrict__ disp, BinGeo g, uint32_t* __restrict__ cnt,
       uint32_t* __restrict__ cur, float4* __restrict__ entries) {
-  int ix, iy, iz;
-  int64_t p = 0;
-  unsigned key = 0xffffffffu;
-  float dx = 0.f, dy = 0.f, dz = 0.f;
-  unsigned local = 0;
-  const bool valid = brick_particle(g, ix, iy, iz, p);
-  if (valid) {
-    const int cx = axis_cell(ix, disp[p], g, dx);
-    const int cy = axis_cell(iy, disp[g.N + p], g, dy);
-    const int cz = axis_cell(iz, disp[2 * g.N + p], g, dz);
-    const int T = g.tile;
-    const int tile = ((cx / T) * g.nt1 + cy / T) * g.nt1 + cz / T;
-    const int cls = ((cx % T == T - 1) ? 1 : 0) | ((cy % T == T - 1) ? 2 : 0) | ((cz % T == T - 1) ? 4 : 0);
-    local = (unsigned)(cx % T) | ((unsigned)(cy % T) << 8) | ((unsigned)(cz % T) << 16);
-    key = (unsigned)tile * 8u + (unsigned)cls;
+  constexpr int S = kBinBricks;
+  const int b0 = (int)xcd_block(blockIdx.x, gridDim.x) * S;
+  bool valid[S];
+  int64_t p[S];
+  int ix[S], iy[S], iz[S];
+  float ux[S], uy[S], uz[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    p[s] = 0;
+    ix[s] = iy[s] = iz[s] = 0;
+    valid[s] = brick_particle<P2>(g, b0 + s, ix[s], iy[s], iz[s], p[s]);
+    ux[s] = uy[s] = uz[s] = 0.f;
+    if (valid[s]) {
+      ux[s] = disp[p[s]];
+      uy[s] = disp[g.N + p[s]];
+      uz[s] = disp[2 * g.N + p[s]];
+    }
   }
-  // group the wave's lanes by key with ballots (no memory traffic); group i's key and
-  // size land in lane i, which then makes the group's one atomic -- all groups' atomics
-  // go out as a single wave instruction
   const int lane = (int)__lane_id();
-  unsigned long long todo = __ballot(valid);
-  int it = 0, mygroup = 0;
-  uint32_t myrank = 0, gcnt = 0;
-  unsigned gkey = 0;
-  while (todo) {   // wave-uniform: every lane runs the same iterations, at most 64
-    const int leader = __ffsll((unsigned long long)todo) - 1;
-    const unsigned lkey = __shfl(key, leader);
-    const unsigned long long m = __ballot(key == lkey) & todo;
-    if (lane == it) {
-      gkey = lkey;
-      gcnt = (uint32_t)__popcll(m);
+  uint32_t gbase[S], myrank[S];
+  int mygroup[S];
+  float4 rec[S];
+#pragma unroll
+  for (int s = 0; s < S; ++s) {
+    unsigned key = 0xffffffffu;
+    rec[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (valid[s]) {
+      float dx, dy, dz;
+      const int cx = axis_cell<P2>(ix[s], ux[s], g, dx);
+      const int cy = axis_cell<P2>(iy[s], uy[s], g, dy);
+      const int cz = axis_cell<P2>(iz[s], uz[s], g, dz);
+      const int lt = g.lt, m = g.tile - 1;
+      const int tile = ((cx >> lt) * g.nt1 + (cy >> lt)) * g.nt1 + (cz >> lt);
+      const int cls = ((cx & m) == m ? 1 : 0) | ((cy & m) == m ? 2 : 0) | ((cz & m) == m ? 4 : 0);
+      const unsigned local = (unsigned)(cx & m) | ((unsigned)(cy & m) << 8) | ((unsigned)(cz & m) << 16);
+      rec[s] = make_float4(dx, dy, dz, __uint_as_float(local));
+      key = (unsigned)tile * 8u + (unsigned)cls;
     }
-    if ((m >> lane) & 1ull) {
-      mygroup = it;
-      myrank = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+    // group the wave's lanes by key with ballots (no memory traffic); group i's key and
+    // size land in lane i, which then makes the group's one atomic -- all groups' atomics
+    // go out as a single wave instruction
+    unsigned long long todo = __ballot(valid[s]);
+    int it = 0;
+    uint32_t gcnt = 0;
+    unsigned gkey = 0;
+    mygroup[s] = 0;
+    myrank[s] = 0;
+    while (todo) {   // wave-uniform: every lane runs the same iterations, at most 64
+      const int leader = __ffsll((unsigned long long)todo) - 1;
+      const unsigned lkey = __shfl(key, leader);
+      const unsigned long long m = __ballot(key == lkey) & todo;
+      if (lane == it) {
+        gkey = lkey;
+        gcnt = (uint32_t)__popcll(m);
+      }
+      if ((m >> lane) & 1ull) {
+        mygroup[s] = it;
+        myrank[s] = (uint32_t)__popcll(m & ((1ull << lane) - 1ull));
+      }
+      todo &= ~m;
+      ++it;
     }
-    todo &= ~m;
-    ++it;
-  }
-  uint32_t gbase = 0;
-  if (lane < it) {
-    if (MODE == 0)
-      atomicAdd(&cnt[gkey], gcnt);
-    else
-      gbase = atomicAdd(&cur[gkey], gcnt);
+    gbase[s] = 0;
+    if (lane < it) {
+      if (MODE == 0)
+        atomicAdd(&cnt[gkey], gcnt);
+      else
+        gbase[s] = atomicAdd(&cur[gkey], gcnt);
+    }
   }
   if (MODE == 1) {
-    const uint32_t base = __shfl(gbase, mygroup);
-    if (valid) entries[base + myrank] = make_float4(dx, dy, dz, __uint_as_float(local));
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+      const uint32_t base = __shfl(gbase[s], mygroup[s]);
+      if (valid[s]) entries[base + myrank[s]] = rec[s];
+    }
   }
 }
 
@@ -261,6 +316,14 @@ k_scan_apply(const uint32_t* __restrict__ cnt, const uint32_t* __restrict__ boff
     o4[0] = make_uint4(cc[0], cc[1], cc[2], cc[3]);
     o4[1] = make_uint4(cc[4], cc[5], cc[6], cc[7]);
   }
+}
+
+// Fixed-point sum -> density: the two 32-bit halves combine exactly in double (sums stay
+// below 2^53), so the one rounding to float gives the correctly rounded v * 2^-24, as a
+// direct 64-bit integer conversion would, in a handful of instructions.
+__device__ __forceinline__ float fix_to_float(unsigned long long v) {
+  const double d = (double)(uint32_t)(v >> 32) * 4294967296.0 + (double)(uint32_t)v;
+  return (float)(d * (1.0 / kFix));
 }
 
 template <int T>
@@ -365,9 +428,9 @@ k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__
   for (int i4 = threadIdx.x; i4 < T * T * T / 4; i4 += blockDim.x) {
     const int i = 4 * i4;
     const int lx = i / (T * T), ly = (i / T) % T, lz = i % T;
-    const float s = 1.f / kFix;
     *reinterpret_cast<float4*>(rho + (int64_t)(ox + lx) * rplane + (int64_t)(oy + ly) * rpitch + oz + lz) =
-        make_float4((float)acc[i] * s, (float)acc[i + 1] * s, (float)acc[i + 2] * s, (float)acc[i + 3] * s);
+        make_float4(fix_to_float(acc[i]), fix_to_float(acc[i + 1]), fix_to_float(acc[i + 2]),
+                    fix_to_float(acc[i + 3]));
   }
 }
 
@@ -381,19 +444,26 @@ void launch_deposit(const Layout& L, const float* disp, float* rho, void* bins, 
   g.tile = L.tile;
   g.inv_cell = L.inv_cell;
   g.N = L.N;
+  g.lt = ilog2(L.tile);
+  const bool p2 = is_pow2(L.np) && is_pow2(L.nm);
+  g.lnp = p2 ? ilog2(L.np) : -1;
+  g.lnm = p2 ? ilog2(L.nm) : -1;
   const int64_t nblk = (L.ntiles + kScanBlock - 1) / kScanBlock;
   uint32_t* cnt = static_cast<uint32_t*>(bins);
   uint32_t* cur = cnt + 8 * L.ntiles;
   uint32_t* start = cur + 8 * L.ntiles;
   uint32_t* bsum = start + L.ntiles;
-  const unsigned bricks = (unsigned)(((L.np + kBrickX - 1) / kBrickX) *
-                                     ((L.np + kBrickY - 1) / kBrickY) *
-                                     ((L.np + kBrickZ - 1) / kBrickZ));
+  const int64_t nbricks = (int64_t)((L.np + kBrickX - 1) / kBrickX) *
+                          ((L.np + kBrickY - 1) / kBrickY) * ((L.np + kBrickZ - 1) / kBrickZ);
+  const unsigned bricks = (unsigned)((nbricks + kBinBricks - 1) / kBinBricks);
   {
     ProfScope ps("bin_count", s);
     hipLaunchKernelGGL(k_fill, dim3(grid_for(8 * L.ntiles, 256)), dim3(256), 0, s,
                        reinterpret_cast<float*>(cnt), 8 * L.ntiles, 0.f);
-    hipLaunchKernelGGL(k_bin<0>, dim3(bricks), dim3(256), 0, s, disp, g, cnt, cur, entries);
+    if (p2)
+      hipLaunchKernelGGL((k_bin<0, true>), dim3(bricks), dim3(256), 0, s, disp, g, cnt, cur, entries);
+    else
+      hipLaunchKernelGGL((k_bin<0, false>), dim3(bricks), dim3(256), 0, s, disp, g, cnt, cur, entries);
     COLA_LAUNCH_CHECK();
   }
   {
@@ -406,7 +476,10 @@ void launch_deposit(const Layout& L, const float* disp, float* rho, void* bins, 
   }
   {
     ProfScope ps("bin_scatter", s);
-    hipLaunchKernelGGL(k_bin<1>, dim3(bricks), dim3(256), 0, s, disp, g, cnt, cur, entries);
+    if (p2)
+      hipLaunchKernelGGL((k_bin<1, true>), dim3(bricks), dim3(256), 0, s, disp, g, cnt, cur, entries);
+    else
+      hipLaunchKernelGGL((k_bin<1, false>), dim3(bricks), dim3(256), 0, s, disp, g, cnt, cur, entries);
     COLA_LAUNCH_CHECK();
   }
   ProfScope ps("deposit", s);
@@ -437,12 +510,34 @@ struct GatherDev {
 // MODE 0: scale-independent LPT (Psi1, Psi2 per particle, growth scalars from the table);
 // MODE 1: scale-dependent LPT (L'' and Delta fields on the particle grid);
 // MODE 2: force only (write F_p).
+//
+// Work order.  Each wave takes 64 consecutive particles of one Lagrangian z-line, so its
+// particle loads and (early on) its mesh rows are contiguous.  When the lattice allows
+// (np a multiple of 64 and of kGatherBrick), the waves of one XCD are further grouped into
+// bricks of kGatherBrick x kGatherBrick z-lines of 64 particles, taken brick after brick:
+// the particles an XCD has in flight then form a compact Lagrangian region rather than a
+// sheet of one lattice plane, and late in the run, when the particles of a halo come from
+// many lattice planes, their force cells are fetched once into that XCD's L2 and reused.
+// Otherwise blocks take consecutive particles.
+constexpr int kGatherBrick = 16;
+
 template <int MODE>
 __global__ void __launch_bounds__(256)
 k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int ppitch,
-         int64_t pplane) {
-  // consecutive particle chunks read overlapping mesh rows: keep them on one XCD
-  const int64_t p = xcd_block(blockIdx.x, gridDim.x) * (int64_t)blockDim.x + threadIdx.x;
+         int64_t pplane, int bricks) {
+  const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
+  int64_t p;
+  if (bricks) {
+    constexpr int kBlocksPerBrick = kGatherBrick * kGatherBrick / 4;
+    const int nbz = np / 64, nby = np / kGatherBrick;
+    const int brick = (int)(blk / kBlocksPerBrick);
+    const int line = (int)(blk % kBlocksPerBrick) * 4 + (int)(threadIdx.x >> 6);
+    const int bz = brick % nbz, by = (brick / nbz) % nby, bx = brick / (nbz * nby);
+    const int ix = bx * kGatherBrick + line / kGatherBrick, iy = by * kGatherBrick + line % kGatherBrick;
+    p = ((int64_t)ix * np + iy) * np + bz * 64 + (threadIdx.x & 63);
+  } else {
+    p = blk * (int64_t)blockDim.x + threadIdx.x;
+  }
   if (p >= N) return;
   CicCell c;
   cic_cell(p, np, nm, ratio, inv_cell, g.disp, N, c);
@@ -509,18 +604,19 @@ void launch_gather(const Layout& L, const GatherArgs& a, hipStream_t s) {
   g.force_out = a.force_out;
   const int ratio = L.nm / L.np;
   const dim3 grid((unsigned)((L.N + 255) / 256)), block(256);
+  const int bricks = (L.np % 64 == 0 && L.np % kGatherBrick == 0) ? 1 : 0;
   if (a.force_out) {
     ProfScope ps("gather_force", s);
     hipLaunchKernelGGL(k_gather<2>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_p, 2 * L.plane_p);
+                       2 * L.pitch_p, 2 * L.plane_p, bricks);
   } else if (a.psi1) {
     ProfScope ps("gather_kick_drift", s);
     hipLaunchKernelGGL(k_gather<0>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_p, 2 * L.plane_p);
+                       2 * L.pitch_p, 2 * L.plane_p, bricks);
   } else {
     ProfScope ps("gather_kick_drift", s);
     hipLaunchKernelGGL(k_gather<1>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_p, 2 * L.plane_p);
+                       2 * L.pitch_p, 2 * L.plane_p, bricks);
   }
   COLA_LAUNCH_CHECK();
 }
