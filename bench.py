@@ -51,10 +51,11 @@ def algorithmic_bytes(name, p):
         "fft_r2c_z": 4 * M + 8 * H,                  # read real mesh, write half-complex
         "fft_c2r_z": 8 * H + 4 * M,
         "fft_y_fwd": 16 * H, "fft_x_fwd": 16 * H, "fft_y_inv": 16 * H,
-        "fft_x_fwd_smooth": 8 * H + 16 * H,          # read delta; write delta_k and W delta_k
-        "fft_x_fwd_pot": 8 * H + 16 * H,
+        "fft_x_fwd_smooth": 8 * H + 8 * H,           # read delta; write X^-1[W delta_k]
+        "fft_x_fwd_pot": 8 * H + 16 * H,             # read delta; write delta_k and X^-1[Phi_k]
         "fft_z_screen": 8 * H + 4 * M + 8 * H,       # read delta_R and rho, write S
         "fft_x_fwd_force": 16 * H + 16 * H,          # read S and delta_k; write G0 and G
+        "fft_x_fwd_force_1src": 8 * H + 16 * H,      # read one combined source; write G0 and G
         "fft_y_inv_yz": 8 * H + 16 * H,              # read G; write the y and z components
         "fft_c2r_z3": 24 * H + 12 * M,               # read 3 force passes, write (Fx, Fy, Fz)
         "gather_kick_drift": 12 * M + 72 * N,        # force mesh; u, v, Psi1, Psi2 in; u, v out
@@ -98,8 +99,10 @@ def traffic_for(kernel):
 
 
 # rocprofv3 kernel symbols of one step -> the names the library's HIP-event profiler uses
-_SYMBOLS = [("k_fft_col_fwd_force", "fft_x_fwd_force"), ("k_fft_col_inv_yz", "fft_y_inv_yz"), ("k_fft_col_fwd_op<{n}, 3>", "fft_x_fwd_smooth"),
-            ("k_fft_col_fwd_op<{n}, 2>", "fft_x_fwd_pot"), ("k_fft_col<{n}, -1, 0>", "fft_y_fwd"),
+_SYMBOLS = [("k_fft_col_fwd_force<{n}, true>", "fft_x_fwd_force"),
+            ("k_fft_col_fwd_force<{n}, false>", "fft_x_fwd_force_1src"),
+            ("k_fft_col_inv_yz", "fft_y_inv_yz"), ("k_fft_col_fwd_op<{n}, 3,", "fft_x_fwd_smooth"),
+            ("k_fft_col_fwd_op<{n}, 2,", "fft_x_fwd_pot"), ("k_fft_col<{n}, -1, 0>", "fft_y_fwd"),
             ("k_fft_col<{n}, 1, 0>", "fft_y_inv"), ("k_fft_c2r_row3", "fft_c2r_z3"),
             ("k_fft_screen_row", "fft_z_screen"), ("k_fft_r2c_row", "fft_r2c_z"),
             ("k_gather", "gather_kick_drift"), ("k_deposit_tiles", "deposit"), ("k_bin<0>", "bin_count"),

@@ -213,30 +213,39 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
   float2* src = M[1];
   KOp base;
   base.kf = (float)(2.0 * M_PI / p.box);
-  if (sc.screen) {
-    KOp op = base;
-    op.scale = invM;
-    int kind = K_SMOOTH;
-    if (p.model == COLA_FR_HS1 || p.model == COLA_SYMMETRON) {   // potential screening
-      op.g_n = -sc.kappa;
-      kind = K_POT;
-    } else {
-      op.r_smooth = (float)p.r_smooth;
-      op.filter = p.filter;
-    }
-    fft_screen(pl, kind, op, M[1], M[2], R(M[0]), flat_out ? R(M[3]) : nullptr, p.model,
-               sc.cham_thr, sc.vx_pref, s);
-    if (flat_out) launch_unpad_mesh(L, R(M[3]), flat_out + L.M, s);
-    dk = M[1];
-    src = M[2];
-  } else if (flat_out) {
-    launch_unpad_mesh(L, R(M[0]), flat_out + L.M, s, 1.f);   // S = delta = rho - 1
-  }
   KOp op = base;
   op.g_n = -sc.kappa;
   op.g_5 = sc.fifth ? -sc.coupling * sc.kappa : 0.f;
   op.a2m2 = sc.a2m2;
   op.scale = invM;
+  if (sc.screen) {
+    KOp sop = base;
+    sop.scale = invM;
+    int kind = K_SMOOTH;
+    float cn = 0.f, c5 = 1.f;   // the row pass forms (rho - 1)(cn + c5 eps)
+    if (p.model == COLA_FR_HS1 || p.model == COLA_SYMMETRON) {   // potential screening
+      sop.g_n = -sc.kappa;
+      kind = K_POT;
+      dk = M[1];
+    } else {
+      // nDGP: the fifth force is massless (Sec. 5.2), so g_n delta_k / k^2 + g_5 S_k / k^2
+      // is the transform of g_n delta + g_5 delta eps over k^2: the row pass builds that
+      // one field and delta_k need not be kept
+      sop.r_smooth = (float)p.r_smooth;
+      sop.filter = p.filter;
+      cn = op.g_n;
+      c5 = op.g_5;
+      op.g_n = 1.f;
+      op.g_5 = 0.f;
+      op.a2m2 = 0.f;
+    }
+    fft_screen(pl, kind, sop, M[1], M[2], R(M[0]), flat_out ? R(M[3]) : nullptr, p.model,
+               sc.cham_thr, sc.vx_pref, cn, c5, s);
+    if (flat_out) launch_unpad_mesh(L, R(M[3]), flat_out + L.M, s);
+    src = M[2];
+  } else if (flat_out) {
+    launch_unpad_mesh(L, R(M[0]), flat_out + L.M, s, 1.f);   // S = delta = rho - 1
+  }
   float2* const work[3] = {M[0], M[1], M[2]};
   fft_c2r_force3(pl, op, dk, src, work, b.force, s);
 }

@@ -313,11 +313,11 @@ k_fft_col(float2* __restrict__ data, int64_t elemStride, int64_t tilesPerBlock,
 }
 
 // X pass of a forward transform fused with the X pass of the inverse transform through a
-// k-space operator: the forward result (delta_k) is written back in place and, multiplied
-// by the operator (smoothing window or Newtonian potential), transformed back through the
-// same LDS tile into `out`.  One read and two writes of the field instead of two reads
-// and two writes.
-template <int N, int KIND>
+// k-space operator: the forward result (delta_k), multiplied by the operator (smoothing
+// window or Newtonian potential), is transformed back through the same LDS tile into
+// `out`, and with KEEP also written back in place.  One read and one or two writes of the
+// field instead of two reads and two writes.
+template <int N, int KIND, bool KEEP>
 __global__ void __launch_bounds__(ColCfg<N>::T)
 k_fft_col_fwd_op(float2* __restrict__ data, float2* __restrict__ out, int64_t elemStride,
                  const float2* __restrict__ tw_g, KOp op) {
@@ -333,7 +333,7 @@ k_fft_col_fwd_op(float2* __restrict__ data, float2* __restrict__ out, int64_t el
   const int iy = col / op.pitch, iz = col % op.pitch;
   auto load = [&](int, int, int j, int c) -> float2 { return data[base + (O)j * es + c]; };
   auto store = [&](int j, int c, float2 v) {
-    data[base + (O)j * es + c] = v;
+    if (KEEP) data[base + (O)j * es + c] = v;
     lds[j * B + c] = kspace_apply<KIND>(op, j, iy, iz, v, v);
   };
   GStages<N, -1, E, B, B, 1, 0, 1, kLastToLds>::run(lds, tid, T, tw, load, store);
@@ -351,7 +351,7 @@ k_fft_col_fwd_op(float2* __restrict__ data, float2* __restrict__ out, int64_t el
 // the X transform and only two X transforms are needed, G0 = X^-1[-i k_x g] into o0 and
 // G = X^-1[g] into o1; the Y pass forms the y and z components from G.  The outputs may
 // alias dk and src: every read of a column precedes the first write to it.
-template <int N>
+template <int N, bool DK>
 __global__ void __launch_bounds__(ColCfg<N>::T)
 k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
                     int64_t elemStride, const float2* __restrict__ tw_g, KOp op) {
@@ -381,7 +381,7 @@ k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
     for (int r = 0; r < R0; ++r) {
       const int jj = j + r * (N / R0);
       const float2 sv = lds[jj * B + c0];
-      const float2 dv = dk ? dk[base + (O)jj * es + c0] : sv;
+      const float2 dv = DK ? dk[base + (O)jj * es + c0] : sv;
       g[i][r] = green_force(op, jj, iy, iz, dv, sv);
     }
   }
@@ -692,7 +692,7 @@ template <int NC, int MODEL>
 __global__ void __launch_bounds__(RowCfg<NC>::T)
 k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float* __restrict__ s_out,
                  int64_t nrows, int /*n*/, int pitch, int64_t plane, const float2* __restrict__ tw_g,
-                 float thr, float vx) {
+                 float thr, float vx, float cn, float c5) {
   constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
   __shared__ float2 lds[NC * LS];
   __shared__ float2 tw[2 * NC];   // twiddles exp(-2 pi i t / n), staged in LDS
@@ -741,17 +741,19 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
       const int e = tid + i * T;
       const int c = e / NC, m = e % NC;
       const float2 f = lds[m * LS + c];
-      float2 sv;
+      float e0, e1;
       if (MODEL == COLA_FR_HS1) {
         const float a0 = fabsf(f.x), a1 = fabsf(f.y);
-        sv = make_float2((rv[i].x - 1.f) * (a0 > thr ? thr * fast_rcp(a0) : 1.f),
-                         (rv[i].y - 1.f) * (a1 > thr ? thr * fast_rcp(a1) : 1.f));
+        e0 = a0 > thr ? thr * fast_rcp(a0) : 1.f;
+        e1 = a1 > thr ? thr * fast_rcp(a1) : 1.f;
       } else {
         const float x0 = vx * fmaxf(0.f, 1.f + f.x), x1 = vx * fmaxf(0.f, 1.f + f.y);
-        sv = make_float2((rv[i].x - 1.f) * (2.f * fast_rcp(1.f + fast_sqrt(1.f + x0))),
-                         (rv[i].y - 1.f) * (2.f * fast_rcp(1.f + fast_sqrt(1.f + x1))));
+        e0 = 2.f * fast_rcp(1.f + fast_sqrt(1.f + x0));
+        e1 = 2.f * fast_rcp(1.f + fast_sqrt(1.f + x1));
       }
-      lds[m * LS + c] = sv;
+      const float2 dl = make_float2(rv[i].x - 1.f, rv[i].y - 1.f);
+      const float2 sv = make_float2(dl.x * e0, dl.y * e1);
+      lds[m * LS + c] = make_float2(dl.x * (cn + c5 * e0), dl.y * (cn + c5 * e1));
       if (s_out && r0 + c < (O)nrows) {
         const O r = r0 + c;
         reinterpret_cast<float2*>(s_out + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[m] = sv;
@@ -883,9 +885,16 @@ static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, c
   op.pitch = P;
   op.plane = pl.plane;
   {
-    ProfScope ps("fft_x_fwd_force", s);
-    hipLaunchKernelGGL((k_fft_col_fwd_force<N>), dim3((unsigned)((int64_t)n * P / B)),
-                       dim3(ColCfg<N>::T), 0, s, dk, src, work[0], work[1], pl.plane, pl.tw, op);
+    const dim3 g((unsigned)((int64_t)n * P / B)), b(ColCfg<N>::T);
+    if (dk) {
+      ProfScope ps("fft_x_fwd_force", s);
+      hipLaunchKernelGGL((k_fft_col_fwd_force<N, true>), g, b, 0, s, dk, src, work[0], work[1],
+                         pl.plane, pl.tw, op);
+    } else {
+      ProfScope ps("fft_x_fwd_force_1src", s);
+      hipLaunchKernelGGL((k_fft_col_fwd_force<N, false>), g, b, 0, s, dk, src, work[0], work[1],
+                         pl.plane, pl.tw, op);
+    }
     COLA_LAUNCH_CHECK();
   }
   KOp none;
@@ -909,7 +918,8 @@ static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, c
 
 template <int N>
 static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* dk, float2* data,
-                        const float* rho, float* s_out, int model, float thr, float vx, hipStream_t s) {
+                        const float* rho, float* s_out, int model, float thr, float vx, float cn,
+                        float c5, hipStream_t s) {
   const int n = pl.n, P = pl.pitch;
   const int64_t rows = (int64_t)n * n;
   constexpr int B = ColCfg<N>::B;
@@ -922,10 +932,10 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
     const dim3 g((unsigned)xtiles), b(ColCfg<N>::T);
     if (kind == K_POT) {
       ProfScope ps("fft_x_fwd_pot", s);
-      hipLaunchKernelGGL((k_fft_col_fwd_op<N, K_POT>), g, b, 0, s, dk, data, pl.plane, pl.tw, op);
+      hipLaunchKernelGGL((k_fft_col_fwd_op<N, K_POT, true>), g, b, 0, s, dk, data, pl.plane, pl.tw, op);
     } else {
       ProfScope ps("fft_x_fwd_smooth", s);
-      hipLaunchKernelGGL((k_fft_col_fwd_op<N, K_SMOOTH>), g, b, 0, s, dk, data, pl.plane, pl.tw, op);
+      hipLaunchKernelGGL((k_fft_col_fwd_op<N, K_SMOOTH, false>), g, b, 0, s, dk, data, pl.plane, pl.tw, op);
     }
     COLA_LAUNCH_CHECK();
   }
@@ -937,10 +947,10 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
     const dim3 g((unsigned)((rows + BR - 1) / BR)), b(RowCfg<N / 2>::T);
     if (model == COLA_FR_HS1 || model == COLA_SYMMETRON)   // eps = min(1, thr/|Phi|)
       hipLaunchKernelGGL((k_fft_screen_row<N / 2, COLA_FR_HS1>), g, b, 0, s, data, rho, s_out, rows, n,
-                         P, pl.plane, pl.tw, thr, vx);
+                         P, pl.plane, pl.tw, thr, vx, cn, c5);
     else
       hipLaunchKernelGGL((k_fft_screen_row<N / 2, COLA_NDGP>), g, b, 0, s, data, rho, s_out, rows, n, P,
-                         pl.plane, pl.tw, thr, vx);
+                         pl.plane, pl.tw, thr, vx, cn, c5);
     COLA_LAUNCH_CHECK();
   }
   col_pass<N, -1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s, "fft_y_fwd");
@@ -958,9 +968,9 @@ void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const fl
 }
 
 void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* dk, float2* data, const float* rho,
-                float* s_out, int model, float thr, float vx, hipStream_t s) {
+                float* s_out, int model, float thr, float vx, float cn, float c5, hipStream_t s) {
   switch (pl.n) {
-#define CASE(N_) case N_: screen_impl<N_>(pl, kind, op, dk, data, rho, s_out, model, thr, vx, s); return;
+#define CASE(N_) case N_: screen_impl<N_>(pl, kind, op, dk, data, rho, s_out, model, thr, vx, cn, c5, s); return;
     CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
     CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
 #undef CASE

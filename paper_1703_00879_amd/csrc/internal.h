@@ -163,13 +163,18 @@ void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* ou
 void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* src,
                     float2* const work[3], float* f3, hipStream_t s);
 // Screened source in Fourier space.  dk holds the density contrast after the forward Z
-// and Y passes: one X pass completes delta_k in place and applies `kind` (K_POT: Newtonian
-// potential for f(R); K_SMOOTH: smoothed density for nDGP) on the way back into `data`;
-// then the inverse Y pass, one row pass doing inverse Z -> S = (rho - 1) eps -> forward Z,
-// and the forward Y pass: `data` ends holding S after the forward Z and Y passes (its X
-// pass is done by fft_c2r_force3).  s_out (optional, padded real) receives S.
+// and Y passes: one X pass completes delta_k (written back in place for K_POT, where the
+// force needs it; not kept for K_SMOOTH) and applies `kind` (K_POT: Newtonian potential
+// for f(R) and the symmetron; K_SMOOTH: smoothed density for nDGP) on the way back into
+// `data`; then the inverse Y pass, one row pass doing inverse Z -> eps -> forward Z of
+// (rho - 1) (cn + c5 eps), and the forward Y pass: `data` ends holding that field after
+// the forward Z and Y passes (its X pass is done by fft_c2r_force3).  cn = 0, c5 = 1
+// give S = delta eps; for a massless fifth force (nDGP) cn = g_n and c5 = g_5 fold the
+// Newtonian and fifth-force sources into one field with one Green's function 1/k^2.
+// s_out (optional, padded real) receives S = delta eps.
 void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* dk, float2* data,
-                const float* rho, float* s_out, int model, float thr, float vx, hipStream_t s);
+                const float* rho, float* s_out, int model, float thr, float vx, float cn,
+                float c5, hipStream_t s);
 
 // ------------------------------------------------------------------ kernels (launchers)
 void launch_fill(float* p, size_t n, float v, hipStream_t s);
