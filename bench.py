@@ -105,8 +105,8 @@ _SYMBOLS = [("k_fft_col_fwd_force<{n}, true>", "fft_x_fwd_force"),
             ("k_fft_col_fwd_op<{n}, 2,", "fft_x_fwd_pot"), ("k_fft_col<{n}, -1, 0>", "fft_y_fwd"),
             ("k_fft_col<{n}, 1, 0>", "fft_y_inv"), ("k_fft_c2r_row3", "fft_c2r_z3"),
             ("k_fft_screen_row", "fft_z_screen"), ("k_fft_r2c_row", "fft_r2c_z"),
-            ("k_gather", "gather_kick_drift"), ("k_deposit_tiles", "deposit"), ("k_bin<0>", "bin_count"),
-            ("k_bin<1>", "bin_scatter"), ("k_scan_", "bin_scan"), ("k_fill", "fill")]
+            ("k_gather", "gather_kick_drift"), ("k_deposit_tiles", "deposit"), ("k_bin<0,", "bin_count"),
+            ("k_bin<1,", "bin_scatter"), ("k_scan_", "bin_scan"), ("k_fill", "fill")]
 
 
 def _profile_name(symbol, n):
@@ -174,7 +174,7 @@ def summarize_rocprof(d, out_dir):
                       "bytes_per_launch": (fb + wb) if fb is not None and wb is not None else None,
                       "algorithmic_bytes_per_launch": algorithmic_bytes(name, p)}
     cmd = ("cd /tmp && export TMPDIR=/tmp; B=\"python3 $REPO/bench.py --steps 2 --warmup 1 "
-           "--no-cpu-baseline --no-profile\"; "
+           "--no-cpu-baseline --no-profile --no-models\"; "
            "rocprofv3 --kernel-trace --stats --output-format csv -d $D/trace -o trace -- $B; "
            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $D/fetch -o fetch -- $B; "
            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $D/write -o write -- $B; "
