@@ -76,6 +76,80 @@ def yardstick_bytes_per_step(p):
     return 152 * M + 84 * N
 
 
+def yardstick_bytes_for(p, C):
+    """Yardstick bytes of one step of any run: LCDM 96M + 84N; screened modified gravity
+    with scale-independent LPT (nDGP, f(R) with LCDM growth) 152M + 84N; with the per-step
+    LPT synthesis of scale-dependent growth (f(R), symmetron) 152M + 212N."""
+    M, N = p.nmesh1d ** 3, p.np1d ** 3
+    if p.model == C.LCDM:
+        return 96 * M + 84 * N
+    if p.model in (C.FR_HS1, C.SYMMETRON) and p.growth_mode == 0:
+        return 152 * M + 212 * N
+    return 152 * M + 84 * N
+
+
+def _mock_params(C, rng, j, sizes, seed0, n_steps):
+    """One mock of the ensemble and serving mixes: n_p drawn from `sizes`, n_mesh = 2 n_p,
+    L = 2 n_p Mpc/h, z_ini = 19, model uniform over LCDM, f(R) |f_R0| = 1e-6, 1e-5, 1e-4
+    and nDGP r_c H0 = 0.5, 1, all screened; seed = seed0 + j."""
+    n = int(rng.choice(sizes))
+    m = int(rng.integers(6))
+    kw = dict(np1d=n, nmesh1d=2 * n, box=2.0 * n, z_init=19.0, n_steps=int(n_steps),
+              seed=seed0 + j, screening=1)
+    if m == 0:
+        kw.update(model=C.LCDM)
+    elif m <= 3:
+        kw.update(model=C.FR_HS1, fr0_abs=(1e-6, 1e-5, 1e-4)[m - 1])
+    else:
+        kw.update(model=C.NDGP, rc_h0=(0.5, 1.0)[m - 4])
+    return C.Params(**kw)
+
+
+def bench_ensemble(C, torch, boxes=64, budget=160 << 30):
+    """A mixed ensemble of small boxes (seeded draw, seed 4: n_p in {64, 96, 128, 192,
+    256}, 10 steps) run one at a time on one stream, then all resident at once and
+    interleaved on four streams; aggregate particle-steps/s and yardstick HBM fraction."""
+    import numpy as np
+    from paper_1703_00879_amd.serve import GpuEngine, Request, Server, summarize
+    rng = np.random.default_rng(4)
+    ps = [_mock_params(C, rng, j, (64, 96, 128, 192, 256), 1000, 10) for j in range(boxes)]
+    yard = sum(yardstick_bytes_for(p, C) * p.n_steps for p in ps)
+    out = {"boxes": boxes, "n_steps": 10, "particle_steps": sum(p.np1d ** 3 * p.n_steps for p in ps)}
+    for name, streams, active in (("one_at_a_time", 1, 1), ("interleaved_4_streams", 4, boxes)):
+        res = Server(GpuEngine(n_streams=streams), budget, max_active=active).run(
+            [Request(p, 0.0, j) for j, p in enumerate(ps)])
+        sm = summarize(res)
+        out[name] = {"seconds": sm["span_s"], "particle_steps_per_s": sm["particle_steps_per_s"],
+                     "hbm_frac_yardstick": yard / sm["span_s"] / 1e9 / HBM_PEAK_GBS}
+        torch.cuda.empty_cache()
+    return out
+
+
+def bench_serving(C, torch, requests=96, budget=96 << 30):
+    """A Poisson stream of mock requests (n_p in {128, 256, 384}, 10-30 steps, models and
+    parameters as the ensemble, seed = 100000 + j) through the serving loop: first all at
+    once to measure the saturation rate, then arriving at 0.8 of it (arrival RNG seed 5).
+    Reports runs/hour and p50 / p99 time to z = 0."""
+    import numpy as np
+    from paper_1703_00879_amd.serve import GpuEngine, Request, Server, summarize
+    rng = np.random.default_rng(5)
+    ps = [_mock_params(C, rng, j, (128, 256, 384), 100000, rng.integers(10, 31))
+          for j in range(requests)]
+    srv = Server(GpuEngine(n_streams=4), budget, max_active=16)
+    sat = summarize(srv.run([Request(p, 0.0, j) for j, p in enumerate(ps)]))
+    torch.cuda.empty_cache()
+    lam = 0.8 * sat["runs"] / sat["span_s"]
+    t = np.cumsum(rng.exponential(1.0 / lam, size=requests))
+    t -= t[0]
+    st = summarize(srv.run([Request(p, float(a), j) for j, (p, a) in enumerate(zip(ps, t))]))
+    torch.cuda.empty_cache()
+    return {"requests": requests, "saturation_runs_per_hour": sat["runs_per_hour"],
+            "arrival_rate_per_s": lam, "runs_per_hour": st["runs_per_hour"],
+            "p50_time_to_z0_s": st["p50_s"], "p99_time_to_z0_s": st["p99_s"],
+            "particle_steps_per_s": st["particle_steps_per_s"],
+            "saturation_p99_time_to_z0_s": sat["p99_s"]}
+
+
 def source_hash():
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_1703_00879_amd", "csrc")
@@ -303,6 +377,10 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-models", action="store_true",
                     help="skip the per-step times of the other gravity models")
+    ap.add_argument("--no-serving", action="store_true",
+                    help="skip the ensemble and serving legs")
+    ap.add_argument("--serve-requests", type=int, default=96,
+                    help="requests in the serving stream (500 for the full stream)")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not record per-kernel HIP events in the timed region")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
@@ -405,8 +483,14 @@ def main():
         "kernels": kernels,
     }
     out["growth_triangles"] = bench_triangles(C, torch)
+    del st
+    torch.cuda.empty_cache()
     if not args.no_models:
         out["other_models_ms_per_step"] = bench_models(C, torch)
+    if not args.no_serving:
+        print("[bench] ensemble and serving", file=sys.stderr, flush=True)
+        out["ensemble"] = bench_ensemble(C, torch)
+        out["serving"] = bench_serving(C, torch, requests=args.serve_requests)
     if not args.no_cpu_baseline:
         print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
         out["cpu_baseline"] = cpu_baseline()
