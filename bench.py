@@ -248,7 +248,7 @@ def summarize_rocprof(d, out_dir):
                       "bytes_per_launch": (fb + wb) if fb is not None and wb is not None else None,
                       "algorithmic_bytes_per_launch": algorithmic_bytes(name, p)}
     cmd = ("cd /tmp && export TMPDIR=/tmp; B=\"python3 $REPO/bench.py --steps 2 --warmup 1 "
-           "--no-cpu-baseline --no-profile --no-models\"; "
+           "--no-cpu-baseline --no-profile --no-models --no-serving\"; "
            "rocprofv3 --kernel-trace --stats --output-format csv -d $D/trace -o trace -- $B; "
            "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $D/fetch -o fetch -- $B; "
            "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $D/write -o write -- $B; "

@@ -44,6 +44,21 @@ __device__ __forceinline__ float2 mul_i(float2 a) {
   return DIR < 0 ? make_float2(a.y, -a.x) : make_float2(-a.y, a.x);
 }
 
+// Streaming loads and stores that bypass cache retention (nontemporal): for passes whose
+// every element is touched once, so that what the caches hold is the pass's own spill and
+// twiddle traffic rather than data that will not be read again.
+typedef float nfloat2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ float2 load_stream(const float2* p) {
+  const nfloat2 v = __builtin_nontemporal_load(reinterpret_cast<const nfloat2*>(p));
+  return make_float2(v.x, v.y);
+}
+__device__ __forceinline__ void store_stream(float2* p, float2 v) {
+  nfloat2 w;
+  w.x = v.x;
+  w.y = v.y;
+  __builtin_nontemporal_store(w, reinterpret_cast<nfloat2*>(p));
+}
+
 // ------------------------------------------------------------------ small DFTs
 template <int R, int DIR>
 struct Dft;
@@ -350,7 +365,9 @@ k_fft_col_fwd_op(float2* __restrict__ data, float2* __restrict__ out, int64_t el
 // F_c = IFFT[-i k_c g]: along an X column k_y and k_z are constants, so they commute with
 // the X transform and only two X transforms are needed, G0 = X^-1[-i k_x g] into o0 and
 // G = X^-1[g] into o1; the Y pass forms the y and z components from G.  The outputs may
-// alias dk and src: every read of a column precedes the first write to it.
+// alias dk and src: every read of a column precedes the first write to it.  The column
+// data is touched once, so it streams past the caches and leaves the L2 to the register
+// spills of the two inverse transforms.
 template <int N, bool DK>
 __global__ void __launch_bounds__(ColCfg<N>::T)
 k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
@@ -368,7 +385,7 @@ k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
   const int col = (int)base + c0;
   const int iy = col / op.pitch, iz = col % op.pitch;
   {
-    auto load = [&](int, int, int j, int c) -> float2 { return src[base + (O)j * es + c]; };
+    auto load = [&](int, int, int j, int c) -> float2 { return load_stream(src + base + (O)j * es + c); };
     auto store = [&](int j, int c, float2 v) { lds[j * B + c] = v; };
     GStages<N, -1, E, B, B, 1, 0, 1, kLastToLds>::run(lds, tid, T, tw, load, store);
   }
@@ -381,7 +398,7 @@ k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
     for (int r = 0; r < R0; ++r) {
       const int jj = j + r * (N / R0);
       const float2 sv = lds[jj * B + c0];
-      const float2 dv = DK ? dk[base + (O)jj * es + c0] : sv;
+      const float2 dv = DK ? load_stream(dk + base + (O)jj * es + c0) : sv;
       g[i][r] = green_force(op, jj, iy, iz, dv, sv);
     }
   }
@@ -392,7 +409,7 @@ k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
     auto load = [&](int i, int r, int jj, int) -> float2 {
       return t == 0 ? grad_minus_i(op, jj, iy, iz, 0, g[i][r]) : g[i][r];
     };
-    auto store = [&](int j, int c, float2 v) { out[base + (O)j * es + c] = v; };
+    auto store = [&](int j, int c, float2 v) { store_stream(out + base + (O)j * es + c, v); };
     GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load, store);
     __syncthreads();   // the second transform reuses the LDS tile
   }
