@@ -298,8 +298,14 @@ def cpu_baseline(steps=8):
     for _ in range(steps):
         r.step()
     dt = time.perf_counter() - t
+    host = "unknown host CPU"
+    try:
+        with open("/proc/cpuinfo") as f:
+            host = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
+    except (OSError, StopIteration):
+        pass
     return {"value": p.n_part * steps / dt, "unit": "particle-steps/s", "cores": 1,
-            "kind": "oracle",
+            "kind": "oracle", "host_cpu": host,
             "sample": f"nDGP rcH0=1 screened, 128^3 particles / 256^3 mesh / L=256 Mpc/h "
                       f"(same spacing and cell as the workload), {steps} COLA steps of the "
                       f"30-step grid after 2LPT ICs; numpy FFT and CIC, one thread; "
