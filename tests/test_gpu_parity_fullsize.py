@@ -11,8 +11,9 @@ and every particle exactly.
   particle force is compared, for displacements along each of the three axes.
 - One COLA step: every particle's displacement and velocity is compared.
 
-The white noise and the scale-dependent growth table are checked on samples the oracle
-computes one by one.
+The same planar check runs on radix-3 meshes of 192^3, 384^3 and 768^3 cells (the sizes
+of the serving mix).  The white noise and the scale-dependent growth table are checked on
+samples the oracle computes one by one.
 
 Tolerances are those of test_gpu_parity:
 - meshes and forces: 1e-5 relative rms (screened source 1e-4);
@@ -120,6 +121,36 @@ def test_fullsize_planar_pm_force(ax):
     record(f"fullsize_planar_pm_force_ax{ax}", **e)
     assert e["rho"] < 1e-5 and e["src"] < 1e-4 and e["f"] < 1e-5 and e["fp"] < 1e-5, e
     assert e["f_across"] < 1e-5 and e["fp_across"] < 1e-5, e
+
+
+# Radix-3 meshes at the sizes of the serving mix (n_p = 384, 192, 96 on 768^3, 384^3,
+# 192^3 meshes, L = 2 n_p Mpc/h): f(R) with its potential screening and two sources,
+# screened nDGP with one combined source, LCDM.
+RADIX3 = [(C.FR_HS1, 384, 0), (C.NDGP, 192, 1), (C.LCDM, 96, 2)]
+
+
+@pytest.mark.parametrize("model,n_p,ax", RADIX3)
+def test_planar_pm_force_radix3_sizes(model, n_p, ax):
+    p = C.Params(model=model, fr0_abs=1e-5, rc_h0=1.0, screening=1, r_smooth=1.0, np1d=n_p,
+                 nmesh1d=2 * n_p, box=2.0 * n_p, z_init=19.0, n_steps=20, seed=3)
+    n, N, M = p.nmesh1d, n_p ** 3, p.nmesh1d ** 3
+    st = C.State(p)
+    C.cola_prepare(p, st)
+    u1 = profile(n_p, p.box, seed=11 + ax)
+    st.disp_f.zero_()
+    fill_planar(st.disp_f[ax], u1, ax, n_p)
+    F = torch.empty(3, N, dtype=torch.float32, device="cuda")
+    mesh = torch.empty(5, M, dtype=torch.float32, device="cuda")
+    a = 0.8
+    C.cola_pm_force(p, st, a, F, mesh)
+    torch.cuda.synchronize()
+    pl = planar_pm(u1.astype(np.float32).astype(np.float64), to_oracle(p), a)
+    e = dict(rho=relrms_planar(mesh[0], pl["rho"], ax, n),
+             src=relrms_planar(mesh[1], pl["src"], ax, n),
+             f=relrms_planar(mesh[2 + ax], pl["force"], ax, n),
+             fp=relrms_planar(F[ax], pl["fp"], ax, n_p))
+    record(f"planar_pm_force_radix3_model{model}_np{n_p}", **e)
+    assert e["rho"] < 1e-5 and e["src"] < 1e-4 and e["f"] < 1e-5 and e["fp"] < 1e-5, e
 
 
 def test_fullsize_planar_step():
