@@ -476,6 +476,51 @@ struct RowCfg {
   static constexpr int LS = B + 1;   // odd LDS stride: transposed row loads stay conflict-light
 };
 
+// Split step of an inverse real transform: B rows of NC + 1 half-complex values X_k give
+//   Z_k = (X_k + conj X_{NC-k}) + i exp(+2 pi i k / n) (X_k - conj X_{NC-k}),  k < NC,
+// the input of the NC-point inverse transform of (x_even + i x_odd), at tile[k * LS + c].
+// Each of TT threads holds NP pairs (X_k, X_{NC-k}), 1 <= k < NC/2, read straight from the
+// rows: every value is loaded once and both Z_k and Z_{NC-k} follow from the pair, so the
+// tile needs no mirror exchange.  The pair k = 0 is (X_0, X_NC) together with the
+// self-mirrored X_{NC/2}.  load() issues the reads (row(c) gives row c, or null past the
+// last row); store() needs the twiddles exp(-2 pi i t / n) in LDS.
+template <int NC, int NP>
+struct InvSplit {
+  static constexpr int H = NC / 2;
+  float2 xa[NP], xb[NP], xm[NP];
+  template <class Row>
+  __device__ __forceinline__ void load(int t, int TT, const Row& row) {
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int e = t + i * TT, c = e / H, k = e % H;
+      xa[i] = xb[i] = xm[i] = make_float2(0.f, 0.f);
+      const float2* rp = row(c);
+      if (rp) {
+        xa[i] = rp[k];
+        xb[i] = rp[k == 0 ? NC : NC - k];
+        if (k == 0) xm[i] = rp[H];
+      }
+    }
+  }
+  __device__ __forceinline__ void store(int t, int TT, const float2* tw, float2* tile, int LS) const {
+    auto z = [&](float2 xk, float2 xc, int k) {   // xc = conj X_{NC-k}
+      const float2 sm = cadd(xk, xc);
+      const float2 d = csub(xk, xc);
+      const float2 u = cmul(cconj(tw[k]), d);   // exp(+2 pi i k / n) d
+      return make_float2(sm.x - u.y, sm.y + u.x);   // sm + i u
+    };
+#pragma unroll
+    for (int i = 0; i < NP; ++i) {
+      const int e = t + i * TT, c = e / H, k = e % H;
+      tile[k * LS + c] = z(xa[i], cconj(xb[i]), k);
+      if (k == 0)
+        tile[H * LS + c] = z(xm[i], cconj(xm[i]), H);
+      else
+        tile[(NC - k) * LS + c] = z(xb[i], cconj(xa[i]), NC - k);
+    }
+  }
+};
+
 // Split step of a forward real transform: B rows held in LDS as Z (the NC-point transform
 // of x_even + i x_odd, lds[k * LS + c]) give the NC + 1 half-complex values
 //   X_k = (Z_k + conj Z_{NC-k})/2 - (i/2) w^k (Z_k - conj Z_{NC-k}),  w = exp(-2 pi i / n),
@@ -560,33 +605,16 @@ k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nr
   using O = Off<2 * NC>;
   constexpr int kN = 2 * NC;   // real row length
   const O r0 = (O)blockIdx.x * B;
-  // X_k and X_{NC-k} come straight from the row (the mirrored read hits the same lines);
-  // all loads are issued before any is used
-  float2 xk[E], xc[E];
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = tid + i * T;
-    const int c = e / NC, k = e % NC;
-    xk[i] = make_float2(0.f, 0.f);
-    xc[i] = make_float2(0.f, 0.f);
-    if (r0 + c < (O)nrows) {
+  {
+    InvSplit<NC, E / 2> sp;   // all row loads are issued before any is used
+    sp.load(tid, T, [&](int c) -> const float2* {
+      if (r0 + c >= (O)nrows) return nullptr;
       const O r = r0 + c;
-      const float2* row = in + (r / kN) * (O)plane + (r % kN) * (O)pitch;
-      xk[i] = row[k];
-      xc[i] = cconj(row[NC - k]);
-    }
-  }
-  for (int i = tid; i < 2 * NC; i += T) tw[i] = tw_g[i];   // after the row loads issue
-  __syncthreads();
-#pragma unroll
-  for (int i = 0; i < E; ++i) {
-    const int e = tid + i * T;
-    const int c = e / NC, k = e % NC;
-    const float2 sm = cadd(xk[i], xc[i]);
-    const float2 d = csub(xk[i], xc[i]);
-    const float2 w = cconj(tw[k]);           // exp(+2 pi i k / n)
-    const float2 t = cmul(w, d);
-    lds[k * LS + c] = make_float2(sm.x - t.y, sm.y + t.x);   // sm + i t
+      return in + (r / kN) * (O)plane + (r % kN) * (O)pitch;
+    });
+    for (int i = tid; i < 2 * NC; i += T) tw[i] = tw_g[i];   // after the row loads issue
+    __syncthreads();
+    sp.store(tid, T, tw, lds, LS);
   }
   __syncthreads();
   lds_fft<NC, +1, E, B, LS, 2>(lds, tid, T, tw);
@@ -633,47 +661,16 @@ k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
   const float2* in = comp == 0 ? in0 : (comp == 1 ? in1 : in2);
   float2* tile = lds[comp];
   const O r0 = (O)blockIdx.x * B;
-  // each row element X_k is read from HBM once; the mirrored X_{NC-k} of the split step
-  // comes back out of the LDS tile (X_NC, the Nyquist value, from a per-row slot)
-  __shared__ float2 nyq[3][B];
   {
-    float2 xk[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = lt + i * TC;
-      const int c = e / NC, k = e % NC;
-      xk[i] = make_float2(0.f, 0.f);
-      if (r0 + c < (O)nrows) {
-        const O r = r0 + c;
-        const float2* row = in + (r / kN) * (O)plane + (r % kN) * (O)pitch;
-        xk[i] = row[k];
-        if (k == 0) nyq[comp][c] = row[NC];
-      }
-    }
+    InvSplit<NC, E / 2> sp;   // each row value is read from HBM once
+    sp.load(lt, TC, [&](int c) -> const float2* {
+      if (r0 + c >= (O)nrows) return nullptr;
+      const O r = r0 + c;
+      return in + (r / kN) * (O)plane + (r % kN) * (O)pitch;
+    });
     for (int i = tid; i < 2 * NC; i += T) tw[i] = tw_g[i];   // after the row loads issue
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = lt + i * TC;
-      tile[(e % NC) * LS + e / NC] = xk[i];
-    }
     __syncthreads();
-    float2 xc[E];
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = lt + i * TC;
-      const int c = e / NC, k = e % NC;
-      xc[i] = cconj(k == 0 ? nyq[comp][c] : tile[(NC - k) * LS + c]);
-    }
-    __syncthreads();
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = lt + i * TC;
-      const int c = e / NC, k = e % NC;
-      const float2 sm = cadd(xk[i], xc[i]);
-      const float2 d = csub(xk[i], xc[i]);
-      const float2 t = cmul(cconj(tw[k]), d);   // exp(+2 pi i k / n) d
-      tile[k * LS + c] = make_float2(sm.x - t.y, sm.y + t.x);
-    }
+    sp.store(lt, TC, tw, tile, LS);
   }
   __syncthreads();
   lds_fft<NC, +1, E, B, LS, 2>(tile, lt, TC, tw);   // ends with a barrier
@@ -721,33 +718,25 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
   // latency hides behind the inverse transform
   float2 rv[E];
   {
-    float2 xk[E], xc[E];
+    InvSplit<NC, E / 2> sp;
+    sp.load(tid, T, [&](int c) -> const float2* {
+      if (r0 + c >= (O)nrows) return nullptr;
+      const O r = r0 + c;
+      return data + (r / kN) * (O)plane + (r % kN) * (O)pitch;
+    });
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int e = tid + i * T;
       const int c = e / NC, k = e % NC;
-      xk[i] = make_float2(0.f, 0.f);
-      xc[i] = make_float2(0.f, 0.f);
       rv[i] = make_float2(1.f, 1.f);
       if (r0 + c < (O)nrows) {
         const O r = r0 + c;
-        const float2* row = data + (r / kN) * (O)plane + (r % kN) * (O)pitch;
-        xk[i] = row[k];
-        xc[i] = cconj(row[NC - k]);
         rv[i] = reinterpret_cast<const float2*>(rho + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[k];
       }
     }
     for (int i = tid; i < 2 * NC; i += T) tw[i] = tw_g[i];   // after the row loads issue
     __syncthreads();
-#pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = tid + i * T;
-      const int c = e / NC, k = e % NC;
-      const float2 sm = cadd(xk[i], xc[i]);
-      const float2 d = csub(xk[i], xc[i]);
-      const float2 t = cmul(cconj(tw[k]), d);
-      lds[k * LS + c] = make_float2(sm.x - t.y, sm.y + t.x);
-    }
+    sp.store(tid, T, tw, lds, LS);
   }
   __syncthreads();
   lds_fft<NC, +1, E, B, LS, 2>(lds, tid, T, tw);
