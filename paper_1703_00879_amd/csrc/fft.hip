@@ -654,7 +654,7 @@ k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
   constexpr int kN = 2 * NC;
   constexpr int kRowF = 3 * kN;   // floats per interleaved row (a multiple of 4)
   static_assert(kRowF % 4 == 0, "interleaved rows must hold whole float4s");
-  __shared__ float2 lds[3][NC * LS];
+  __shared__ __align__(16) float2 lds[3][NC * LS];   // also read as float4 at the end
   __shared__ float2 tw[2 * NC];   // twiddles exp(-2 pi i t / n), staged in LDS
   const int tid = threadIdx.x;
   const int comp = tid / TC, lt = tid - comp * TC;
@@ -673,28 +673,27 @@ k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
     sp.store(lt, TC, tw, tile, LS);
   }
   __syncthreads();
-  lds_fft<NC, +1, E, B, LS, 2>(tile, lt, TC, tw);   // ends with a barrier
-  // element m of row c in tile t holds cells (2m, 2m + 1) of component t; a wave writes
-  // 64 consecutive float4s, float 4q + j of the block being component t of cell w / 3
-  // (w the float's place in its row), so only the first float of each needs a division
-  const O rows_here = (O)nrows - r0 < (O)B ? (O)nrows - r0 : (O)B;
-  constexpr int kQ = kRowF / 4;   // float4s per interleaved row
-  const int nq = (int)rows_here * kQ;
-  float4* dst = reinterpret_cast<float4*>(out + (O3)r0 * kRowF);
-  const float* tiles = reinterpret_cast<const float*>(&lds[0][0]);
-  for (int q = tid; q < nq; q += T) {
-    const int c = q / kQ;
-    const int w0 = 4 * (q - c * kQ);
-    const int cell0 = w0 / 3, t0 = w0 - 3 * cell0;
-    float v[4];
-#pragma unroll
-    for (int j = 0; j < 4; ++j) {
-      const bool wrap = t0 + j >= 3;   // t0 + j <= 5
-      const int t = wrap ? t0 + j - 3 : t0 + j, cell = wrap ? cell0 + 1 : cell0;
-      v[j] = tiles[2 * (t * NC * LS + (cell >> 1) * LS + c) + (cell & 1)];
-    }
-    dst[q] = make_float4(v[0], v[1], v[2], v[3]);
+  // The last Stockham stage writes the B interleaved output rows straight into LDS, over
+  // the three tiles (every group has read its tile by the stage's barrier): element m of
+  // row c of component t holds cells (2m, 2m + 1), at floats 3 (2m) + t and 3 (2m + 1) + t
+  // of the row.  The rows then leave as one contiguous block of 16-byte stores.
+  float* ilv = reinterpret_cast<float*>(&lds[0][0]);
+  static_assert(B * kRowF <= 3 * 2 * NC * LS, "interleaved rows must fit the three tiles");
+  {
+    auto load = [&](int, int, int j, int c) -> float2 { return tile[j * LS + c]; };
+    auto store = [&](int m, int c, float2 v) {
+      float* rowp = ilv + c * kRowF + 6 * m + comp;
+      rowp[0] = v.x;
+      rowp[3] = v.y;
+    };
+    GStages<NC, +1, E, B, LS, 2, 0, 1, kFirstFromLds | kLastToLds>::run(tile, lt, TC, tw, load, store);
   }
+  __syncthreads();
+  const O rows_here = (O)nrows - r0 < (O)B ? (O)nrows - r0 : (O)B;
+  const int nq = (int)rows_here * (kRowF / 4);
+  float4* dst = reinterpret_cast<float4*>(out + (O3)r0 * kRowF);
+  const float4* src4 = reinterpret_cast<const float4*>(ilv);
+  for (int q = tid; q < nq; q += T) dst[q] = src4[q];
 }
 
 // Screening in one row pass (Sec. 6): inverse Z transform of the filtered field (the
