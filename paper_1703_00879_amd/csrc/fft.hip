@@ -215,6 +215,11 @@ __device__ __forceinline__ void lds_fft(float2* lds, int tid, int T, const float
 // its in-place writes by a barrier; after a kLastToLds transform the caller must
 // synchronise before reading the tile.
 constexpr int kFirstFromLds = 1, kLastToLds = 2;
+// kStoreIR: the last stage calls store(j, c, v, i, r), naming the butterfly i and operand r
+// that produced the value.  The last stage's (i, r) -> element map equals the first
+// stage's when both have the same radix, so a following transform can take its first
+// operands from registers filled by this store.
+constexpr int kStoreIR = 4;
 
 template <int N, int DIR, int E, int B, int LS, int TWS, int S, int NS, int FL = 0>
 struct GStages {
@@ -263,10 +268,14 @@ struct GStages {
         const int idxD = (j / NS) * NS * R + k;
 #pragma unroll
         for (int r = 0; r < R; ++r) {
-          if constexpr (S + 1 == nst)
-            store(idxD + r * NS, c, v[i][r]);
-          else
+          if constexpr (S + 1 == nst) {
+            if constexpr ((FL & kStoreIR) != 0)
+              store(idxD + r * NS, c, v[i][r], i, r);
+            else
+              store(idxD + r * NS, c, v[i][r]);
+          } else {
             lds[(idxD + r * NS) * LS + c] = v[i][r];
+          }
         }
       }
       if constexpr (S + 1 < nst) {
@@ -713,9 +722,17 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
   using O = Off<2 * NC>;
   constexpr int kN = 2 * NC;   // real row length
   const O r0 = (O)blockIdx.x * B;
-  // the density pairs (x_2m, x_2m+1) of element m are loaded with the row, so that their
-  // latency hides behind the inverse transform
-  float2 rv[E];
+  // Thread (i, r) handles element m = j + r NC/RL of row c (b = tid + i T, c = b % B,
+  // j = b / B): the output of operand r of its butterfly i in the last inverse stage of
+  // radix RL.  Its density pair (x_2m, x_2m+1) is loaded with the row, so that the
+  // latency hides behind the inverse transform.
+  constexpr int RL = Plan<NC>::rad[Plan<NC>::nst - 1], NBL = E / RL;
+  constexpr bool kHandOff = RL == Plan<NC>::rad[0];
+  auto rho_row = [&](int c) -> const float2* {
+    const O r = r0 + c;
+    return reinterpret_cast<const float2*>(rho + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch));
+  };
+  float2 rv[NBL][RL];
   {
     InvSplit<NC, E / 2> sp;
     sp.load(tid, T, [&](int c) -> const float2* {
@@ -724,49 +741,67 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
       return data + (r / kN) * (O)plane + (r % kN) * (O)pitch;
     });
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = tid + i * T;
-      const int c = e / NC, k = e % NC;
-      rv[i] = make_float2(1.f, 1.f);
-      if (r0 + c < (O)nrows) {
-        const O r = r0 + c;
-        rv[i] = reinterpret_cast<const float2*>(rho + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[k];
-      }
+    for (int i = 0; i < NBL; ++i) {
+      const int b = tid + i * T, c = b % B, j = b / B;
+#pragma unroll
+      for (int r = 0; r < RL; ++r)
+        rv[i][r] = r0 + c < (O)nrows ? rho_row(c)[j + r * (NC / RL)] : make_float2(1.f, 1.f);
     }
     for (int i = tid; i < 2 * NC; i += T) tw[i] = tw_g[i];   // after the row loads issue
     __syncthreads();
     sp.store(tid, T, tw, lds, LS);
   }
   __syncthreads();
-  lds_fft<NC, +1, E, B, LS, 2>(lds, tid, T, tw);
-  // S = (rho - 1) eps(field) on the pair (x_2m, x_2m+1) held by element m
-  {
+  // field value f at the pair -> S = (rho - 1) eps(f) (written to s_out) and the value
+  // (rho - 1)(cn + c5 eps) that the forward transform takes
+  auto source = [&](float2 f, float2 rho2, int m, int c) {
+    float e0, e1;
+    if (MODEL == COLA_FR_HS1) {
+      const float a0 = fabsf(f.x), a1 = fabsf(f.y);
+      e0 = a0 > thr ? thr * fast_rcp(a0) : 1.f;
+      e1 = a1 > thr ? thr * fast_rcp(a1) : 1.f;
+    } else {
+      const float x0 = vx * fmaxf(0.f, 1.f + f.x), x1 = vx * fmaxf(0.f, 1.f + f.y);
+      e0 = 2.f * fast_rcp(1.f + fast_sqrt(1.f + x0));
+      e1 = 2.f * fast_rcp(1.f + fast_sqrt(1.f + x1));
+    }
+    const float2 dl = make_float2(rho2.x - 1.f, rho2.y - 1.f);
+    if (s_out && r0 + c < (O)nrows) {
+      const O r = r0 + c;
+      reinterpret_cast<float2*>(s_out + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[m] =
+          make_float2(dl.x * e0, dl.y * e1);
+    }
+    return make_float2(dl.x * (cn + c5 * e0), dl.y * (cn + c5 * e1));
+  };
+  if constexpr (kHandOff) {
+    // the last inverse stage hands its outputs to the first forward stage in registers
+    float2 tv[NBL][RL];
+    {
+      auto load = [&](int, int, int j, int c) -> float2 { return lds[j * LS + c]; };
+      auto store = [&](int m, int c, float2 f, int i, int r) { tv[i][r] = source(f, rv[i][r], m, c); };
+      GStages<NC, +1, E, B, LS, 2, 0, 1, kFirstFromLds | kStoreIR>::run(lds, tid, T, tw, load, store);
+    }
+    __syncthreads();   // every thread has read its last operands out of the tile
+    {
+      auto load = [&](int i, int r, int, int) -> float2 { return tv[i][r]; };
+      auto store = [&](int j, int c, float2 v) { lds[j * LS + c] = v; };
+      GStages<NC, -1, E, B, LS, 2, 0, 1, kLastToLds>::run(lds, tid, T, tw, load, store);
+    }
+  } else {
+    lds_fft<NC, +1, E, B, LS, 2>(lds, tid, T, tw);
 #pragma unroll
-    for (int i = 0; i < E; ++i) {
-      const int e = tid + i * T;
-      const int c = e / NC, m = e % NC;
-      const float2 f = lds[m * LS + c];
-      float e0, e1;
-      if (MODEL == COLA_FR_HS1) {
-        const float a0 = fabsf(f.x), a1 = fabsf(f.y);
-        e0 = a0 > thr ? thr * fast_rcp(a0) : 1.f;
-        e1 = a1 > thr ? thr * fast_rcp(a1) : 1.f;
-      } else {
-        const float x0 = vx * fmaxf(0.f, 1.f + f.x), x1 = vx * fmaxf(0.f, 1.f + f.y);
-        e0 = 2.f * fast_rcp(1.f + fast_sqrt(1.f + x0));
-        e1 = 2.f * fast_rcp(1.f + fast_sqrt(1.f + x1));
-      }
-      const float2 dl = make_float2(rv[i].x - 1.f, rv[i].y - 1.f);
-      const float2 sv = make_float2(dl.x * e0, dl.y * e1);
-      lds[m * LS + c] = make_float2(dl.x * (cn + c5 * e0), dl.y * (cn + c5 * e1));
-      if (s_out && r0 + c < (O)nrows) {
-        const O r = r0 + c;
-        reinterpret_cast<float2*>(s_out + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[m] = sv;
+    for (int i = 0; i < NBL; ++i) {
+      const int b = tid + i * T, c = b % B, j = b / B;
+#pragma unroll
+      for (int r = 0; r < RL; ++r) {
+        const int m = j + r * (NC / RL);
+        lds[m * LS + c] = source(lds[m * LS + c], rv[i][r], m, c);
       }
     }
+    __syncthreads();
+    lds_fft<NC, -1, E, B, LS, 2>(lds, tid, T, tw);
   }
   __syncthreads();
-  lds_fft<NC, -1, E, B, LS, 2>(lds, tid, T, tw);
   split_fwd_store<NC, E, B, LS, T>(lds, tw, tid, [&](int c, int k, float2 v) {
     if (r0 + c >= (O)nrows) return;
     const O r = r0 + c;
