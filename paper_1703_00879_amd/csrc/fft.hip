@@ -151,6 +151,10 @@ COLA_PLAN(1024, 16, 4, 8, 8, 4, 4)
 COLA_PLAN(1536, 24, 4, 8, 8, 8, 3)
 COLA_PLAN(2048, 16, 4, 8, 8, 8, 4)
 #undef COLA_PLAN
+// First and last radix equal: a transform's last stage can hand its outputs to the next
+// transform's first stage in registers (kStoreIR).
+template <int N>
+constexpr bool kHandOff = Plan<N>::rad[0] == Plan<N>::rad[Plan<N>::nst - 1];
 
 // One Stockham stage of radix R on B transforms of length N held in LDS as
 // lds[j * LS + c] (element j of transform c).  Butterfly b = tid + i*T maps to
@@ -356,15 +360,30 @@ k_fft_col_fwd_op(float2* __restrict__ data, float2* __restrict__ out, int64_t el
   const int col = (int)base + tid % B;   // (y, z) column of every element this thread touches
   const int iy = col / op.pitch, iz = col % op.pitch;
   auto load = [&](int, int, int j, int c) -> float2 { return data[base + (O)j * es + c]; };
-  auto store = [&](int j, int c, float2 v) {
-    if (KEEP) data[base + (O)j * es + c] = v;
-    lds[j * B + c] = kspace_apply<KIND>(op, j, iy, iz, v, v);
-  };
-  GStages<N, -1, E, B, B, 1, 0, 1, kLastToLds>::run(lds, tid, T, tw, load, store);
-  __syncthreads();
-  auto load2 = [&](int, int, int j, int c) -> float2 { return lds[j * B + c]; };
   auto store2 = [&](int j, int c, float2 v) { out[base + (O)j * es + c] = v; };
-  GStages<N, +1, E, B, B, 1, 0, 1, kFirstFromLds>::run(lds, tid, T, tw, load2, store2);
+  if constexpr (kHandOff<N>) {
+    // the operator is applied in the forward transform's last stage and the inverse
+    // starts from those registers
+    constexpr int R0 = Plan<N>::rad[0], NB0 = E / R0;
+    float2 hv[NB0][R0];
+    auto store = [&](int j, int c, float2 v, int i, int r) {
+      if (KEEP) data[base + (O)j * es + c] = v;
+      hv[i][r] = kspace_apply<KIND>(op, j, iy, iz, v, v);
+    };
+    GStages<N, -1, E, B, B, 1, 0, 1, kStoreIR>::run(lds, tid, T, tw, load, store);
+    __syncthreads();   // every thread has read its last operands out of the tile
+    auto load2 = [&](int i, int r, int, int) -> float2 { return hv[i][r]; };
+    GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load2, store2);
+  } else {
+    auto store = [&](int j, int c, float2 v) {
+      if (KEEP) data[base + (O)j * es + c] = v;
+      lds[j * B + c] = kspace_apply<KIND>(op, j, iy, iz, v, v);
+    };
+    GStages<N, -1, E, B, B, 1, 0, 1, kLastToLds>::run(lds, tid, T, tw, load, store);
+    __syncthreads();
+    auto load2 = [&](int, int, int j, int c) -> float2 { return lds[j * B + c]; };
+    GStages<N, +1, E, B, B, 1, 0, 1, kFirstFromLds>::run(lds, tid, T, tw, load2, store2);
+  }
 }
 
 // X pass of the forward transform of the (screened) source fused with the X passes of the
@@ -393,22 +412,26 @@ k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
   const int c0 = tid % B;
   const int col = (int)base + c0;
   const int iy = col / op.pitch, iz = col % op.pitch;
-  {
-    auto load = [&](int, int, int j, int c) -> float2 { return load_stream(src + base + (O)j * es + c); };
+  float2 g[NB0][R0];
+  auto load = [&](int, int, int j, int c) -> float2 { return load_stream(src + base + (O)j * es + c); };
+  if constexpr (!DK && kHandOff<N>) {
+    // one source: g is formed in the forward transform's last stage, in registers
+    auto store = [&](int jj, int, float2 v, int i, int r) { g[i][r] = green_force(op, jj, iy, iz, v, v); };
+    GStages<N, -1, E, B, B, 1, 0, 1, kStoreIR>::run(lds, tid, T, tw, load, store);
+  } else {
     auto store = [&](int j, int c, float2 v) { lds[j * B + c] = v; };
     GStages<N, -1, E, B, B, 1, 0, 1, kLastToLds>::run(lds, tid, T, tw, load, store);
-  }
-  __syncthreads();
-  float2 g[NB0][R0];
+    __syncthreads();
 #pragma unroll
-  for (int i = 0; i < NB0; ++i) {
-    const int j = (tid + i * T) / B;
+    for (int i = 0; i < NB0; ++i) {
+      const int j = (tid + i * T) / B;
 #pragma unroll
-    for (int r = 0; r < R0; ++r) {
-      const int jj = j + r * (N / R0);
-      const float2 sv = lds[jj * B + c0];
-      const float2 dv = DK ? load_stream(dk + base + (O)jj * es + c0) : sv;
-      g[i][r] = green_force(op, jj, iy, iz, dv, sv);
+      for (int r = 0; r < R0; ++r) {
+        const int jj = j + r * (N / R0);
+        const float2 sv = lds[jj * B + c0];
+        const float2 dv = DK ? load_stream(dk + base + (O)jj * es + c0) : sv;
+        g[i][r] = green_force(op, jj, iy, iz, dv, sv);
+      }
     }
   }
   __syncthreads();   // the tile is reused by the inverse transforms
