@@ -662,8 +662,9 @@ k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nr
 // (F_x, F_y, F_z) mesh (unpadded rows), so that the CIC gather reads 24 contiguous bytes
 // per pair of cells instead of three separate meshes.  The work-group splits into three
 // thread groups, one per component, each transforming the same B rows through its own
-// LDS tile as in k_fft_c2r_row; then all threads write the B interleaved rows -- one
-// contiguous block -- with 16-byte stores read out of the three tiles.
+// LDS tile as in k_fft_c2r_row; the last stage writes the interleaved rows into LDS over
+// the three tiles, and all threads copy them out -- one contiguous block -- with 16-byte
+// stores.
 template <int NC>
 struct Row3Cfg {
   static constexpr int E = Plan<NC>::E;
