@@ -304,8 +304,20 @@ def cpu_baseline(steps=8):
             host = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
+    # the small f(R) configuration (32^3 particles, 64^3 mesh, L = 200 Mpc/h, 10 steps):
+    # median step time of the whole run
+    ps = oracle.Params(model=oracle.MODEL_FR, fr0_abs=1e-5, screening=1, np1d=32, nmesh1d=64,
+                       box=200.0, z_init=19.0, n_steps=10, seed=1)
+    rs = Run(ps)
+    ts = []
+    for _ in range(ps.n_steps):
+        t0 = time.perf_counter()
+        rs.step()
+        ts.append(time.perf_counter() - t0)
+    small_ms = 1e3 * sorted(ts)[len(ts) // 2]
     return {"value": p.n_part * steps / dt, "unit": "particle-steps/s", "cores": 1,
             "kind": "oracle", "host_cpu": host,
+            "fr5_32_64_median_step_ms": small_ms,
             "sample": f"nDGP rcH0=1 screened, 128^3 particles / 256^3 mesh / L=256 Mpc/h "
                       f"(same spacing and cell as the workload), {steps} COLA steps of the "
                       f"30-step grid after 2LPT ICs; numpy FFT and CIC, one thread; "
