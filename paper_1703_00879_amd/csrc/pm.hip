@@ -84,7 +84,7 @@ void launch_fill(float* p, size_t n, float v, hipStream_t s) {
 //     lower neighbour tiles T - delta with (c & delta) == delta -- and writes the tile
 //     once with plain stores, so the mesh needs no zeroing pass.
 constexpr int kBrickX = 4, kBrickY = 8, kBrickZ = 8;   // 256 particles per brick
-constexpr int kBinBricks = 4;                           // bricks per binning work-group
+constexpr int kBinBricks = 2;                           // bricks per binning work-group
 constexpr int kScanBlock = 1024;                        // tiles per scan block
 constexpr float kFix = 16777216.f;                      // 2^24: deposit fixed-point unit
 // Threads per tile work-group: the LDS accumulator (32 KB for 16^3 cells) allows four
