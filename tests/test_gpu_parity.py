@@ -182,23 +182,35 @@ def _min_image_rms_cells(x_gpu, x_or, p):
     return float(np.sqrt(np.mean(np.sum(d * d, axis=0)) / 3.0) / (p.box / p.nmesh1d))
 
 
+_CONFIG1 = {}   # (model, growth_mode) -> (GPU run, oracle run) of the 10-step configuration
+
+
+def _config1(model, growth_mode):
+    """f(R) |fR0| = 1e-5 with screening, 32^3 particles, 64^3 mesh, L = 200 Mpc/h, 2LPT at
+    z = 19, 10 steps to z = 0 (and the same run for the other models, all from the same
+    seed), on the GPU and in the oracle."""
+    key = (model, growth_mode)
+    if key not in _CONFIG1:
+        p = C.Params(model=model, fr0_abs=1e-5, rc_h0=1.0, np1d=32, nmesh1d=64, box=200.0,
+                     z_init=19.0, n_steps=10, seed=1, growth_mode=growth_mode)
+        st = _ic_state(p)
+        for i in range(p.n_steps):
+            C.cola_step(p, st, i)
+        xyz = torch.empty(3, p.np1d ** 3, dtype=torch.float32, device="cuda")
+        C.cola_positions(p, st, xyz)
+        k, P, nm = C.cola_power_spectrum(p, st)
+        r = Run(to_oracle(p)).run()
+        ko, Po, nmo = power_spectrum(r.u, to_oracle(p))
+        _CONFIG1[key] = (p, xyz.cpu().numpy(), (k, P, nm), r, (ko, Po, nmo))
+    return _CONFIG1[key]
+
+
 @pytest.mark.parametrize("model,growth_mode", [(C.FR_HS1, 0), (C.NDGP, 0), (C.LCDM, 0),
                                                (C.FR_HS1, 1), (C.SYMMETRON, 0)])
 def test_full_run_config1_positions_and_pk(model, growth_mode):
-    # f(R) |fR0| = 1e-5 with screening, 32^3 particles, 64^3 mesh, L = 200 Mpc/h, 2LPT at
-    # z = 19, 10 steps to z = 0 (and the same run for nDGP r_c H0 = 1, LCDM, and f(R)
-    # with LCDM growth factors, the paper's production mode of Sec. 7.1)
-    p = C.Params(model=model, fr0_abs=1e-5, rc_h0=1.0, np1d=32, nmesh1d=64, box=200.0,
-                 z_init=19.0, n_steps=10, seed=1, growth_mode=growth_mode)
-    st = _ic_state(p)
-    for i in range(p.n_steps):
-        C.cola_step(p, st, i)
-    xyz = torch.empty(3, p.np1d ** 3, dtype=torch.float32, device="cuda")
-    C.cola_positions(p, st, xyz)
-    k, P, nm = C.cola_power_spectrum(p, st)
-    r = Run(to_oracle(p)).run()
-    err = _min_image_rms_cells(xyz.cpu().numpy(), r.positions(), p)
-    ko, Po, nmo = power_spectrum(r.u, to_oracle(p))
+    # f(R) with LCDM growth factors is the paper's production mode of Sec. 7.1
+    p, xyz, (k, P, nm), r, (ko, Po, nmo) = _config1(model, growth_mode)
+    err = _min_image_rms_cells(xyz, r.positions(), p)
     half = p.nmesh1d // 4     # k <= k_Nyq / 2
     record(f"run_config1_model{model}_growth{growth_mode}", pos_cells=err,
            pk=np.max(np.abs(P[1:half] / Po[1:half] - 1)))
@@ -206,6 +218,20 @@ def test_full_run_config1_positions_and_pk(model, growth_mode):
     assert np.array_equal(nm[1:half], nmo[1:half].astype(np.int64))
     assert np.allclose(k[1:half], ko[1:half], rtol=1e-5)
     assert np.max(np.abs(P[1:half] / Po[1:half] - 1)) < 1e-3
+
+
+@pytest.mark.parametrize("model,growth_mode", [(C.FR_HS1, 0), (C.NDGP, 0), (C.FR_HS1, 1),
+                                               (C.SYMMETRON, 0)])
+def test_boost_config1(model, growth_mode):
+    """P_MG / P_LCDM at the same seed and number of steps (Sec. 7), GPU against oracle:
+    0.1 % per bin up to half the Nyquist wavenumber."""
+    _, _, (k, P, _), _, (_, Po, _) = _config1(model, growth_mode)
+    _, _, (_, PL, _), _, (_, PLo, _) = _config1(C.LCDM, 0)
+    half = 64 // 4
+    b, bo = P[1:half] / PL[1:half], Po[1:half] / PLo[1:half]
+    record(f"boost_config1_model{model}_growth{growth_mode}", boost=float(np.max(np.abs(b / bo - 1))),
+           boost_first_bin=float(bo[0]))
+    assert np.max(np.abs(b / bo - 1)) < 1e-3
 
 
 def test_power_spectrum_same_particles():
