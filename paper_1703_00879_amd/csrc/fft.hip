@@ -309,11 +309,19 @@ struct ColCfg {
 // Strided pass: tile t covers columns [col0, col0 + B) of block t / tilesPerBlock, element
 // j of column c at base + j * elemStride + c.  The twiddles are staged in LDS so that no
 // butterfly stage waits on the global-load queue.
-template <int N, int DIR, int KIND>
-__global__ void __launch_bounds__(ColCfg<N>::T)
+// Columns per tile of the X passes (element stride one x-plane): these run faster with
+// more work-groups per CU, so 512- and 1024-point columns go 8 to a tile (two or four
+// work-groups per CU) where the Y passes take 16.
+template <int N>
+struct XCfg {
+  static constexpr int B = (N == 512 || N == 1024) ? 8 : ColCfg<N>::B;
+};
+
+template <int N, int DIR, int KIND, int BB = ColCfg<N>::B>
+__global__ void __launch_bounds__(N * BB / ColCfg<N>::E)
 k_fft_col(float2* __restrict__ data, int64_t elemStride, int64_t tilesPerBlock,
           int64_t blockStride, int64_t ntiles, const float2* __restrict__ tw_g, KOp op) {
-  constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
+  constexpr int B = BB, E = ColCfg<N>::E, T = N * BB / E;
   __shared__ float2 lds[N * B];
   __shared__ float2 tw[N];
   const int tid = threadIdx.x;
@@ -345,12 +353,11 @@ k_fft_col(float2* __restrict__ data, int64_t elemStride, int64_t tilesPerBlock,
 // window or Newtonian potential), is transformed back through the same LDS tile into
 // `out`, and with KEEP also written back in place.  One read and one or two writes of the
 // field instead of two reads and two writes.
-// Tile of the forward-operator-inverse X pass: 1024-point columns go 8 to a 64 KB tile,
-// two work-groups per CU, which measured 25 % faster than one 16-column tile per CU
-// (the Y passes, by contrast, are faster with 16 columns).
+// Tile of the forward-operator-inverse X pass: the X-pass tile (for 1024-point columns 8
+// to a 64 KB tile, two work-groups per CU, 25 % faster than one 16-column tile per CU).
 template <int N>
 struct OpCfg {
-  static constexpr int B = N == 1024 ? 8 : ColCfg<N>::B;
+  static constexpr int B = XCfg<N>::B;
   static constexpr int E = ColCfg<N>::E;
   static constexpr int T = N * B / E;
 };
@@ -854,12 +861,12 @@ bool fft_size_supported(int n) {
   }
 }
 
-template <int N, int DIR, int KIND>
+template <int N, int DIR, int KIND, int BB = ColCfg<N>::B>
 static void col_pass(float2* data, int64_t elemStride, int64_t tiles, int64_t tilesPerBlock,
                      int64_t blockStride, const float2* tw, const KOp& op, hipStream_t s,
                      const char* name) {
   ProfScope ps(name, s);
-  hipLaunchKernelGGL((k_fft_col<N, DIR, KIND>), dim3((unsigned)tiles), dim3(ColCfg<N>::T), 0, s,
+  hipLaunchKernelGGL((k_fft_col<N, DIR, KIND, BB>), dim3((unsigned)tiles), dim3(N * BB / ColCfg<N>::E), 0, s,
                      data, elemStride, tilesPerBlock, blockStride, tiles, tw, op);
   COLA_LAUNCH_CHECK();
 }
@@ -880,10 +887,11 @@ static void r2c_impl(const FFTPlan& pl, const float* in, float2* out, bool x_pas
   // Y pass: per x-plane, tiles of B z-columns, element stride = pitch
   col_pass<N, -1, K_COPY>(out, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, op, s,
                           "fft_y_fwd");
-  // X pass: tiles of B (y, z) columns, element stride = plane
+  // X pass: tiles of XCfg B (y, z) columns, element stride = plane
+  constexpr int BX = XCfg<N>::B;
   if (x_pass)
-    col_pass<N, -1, K_COPY>(out, pl.plane, (int64_t)n * P / B, (int64_t)n * P / B, 0, pl.tw, op,
-                            s, "fft_x_fwd");
+    col_pass<N, -1, K_COPY, BX>(out, pl.plane, (int64_t)n * P / BX, (int64_t)n * P / BX, 0, pl.tw,
+                                op, s, "fft_x_fwd");
 }
 
 template <int N>
@@ -896,16 +904,17 @@ static void c2r_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* data
   op.n = n;
   op.pitch = P;
   op.plane = pl.plane;
-  const int64_t xtiles = (int64_t)n * P / B;
+  constexpr int BX = XCfg<N>::B;
+  const int64_t xtiles = (int64_t)n * P / BX;
   const int64_t ES = pl.plane;
   switch (kind) {
-    case K_COPY: col_pass<N, 1, K_COPY>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv"); break;
-    case K_FORCE: col_pass<N, 1, K_FORCE>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_force"); break;
-    case K_POT: col_pass<N, 1, K_POT>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_pot"); break;
-    case K_SMOOTH: col_pass<N, 1, K_SMOOTH>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_smooth"); break;
-    case K_LPT: col_pass<N, 1, K_LPT>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_lpt"); break;
-    case K_HESS: col_pass<N, 1, K_HESS>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_hess"); break;
-    case K_GRAD: col_pass<N, 1, K_GRAD>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_grad"); break;
+    case K_COPY: col_pass<N, 1, K_COPY, BX>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv"); break;
+    case K_FORCE: col_pass<N, 1, K_FORCE, BX>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_force"); break;
+    case K_POT: col_pass<N, 1, K_POT, BX>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_pot"); break;
+    case K_SMOOTH: col_pass<N, 1, K_SMOOTH, BX>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_smooth"); break;
+    case K_LPT: col_pass<N, 1, K_LPT, BX>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_lpt"); break;
+    case K_HESS: col_pass<N, 1, K_HESS, BX>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_hess"); break;
+    case K_GRAD: col_pass<N, 1, K_GRAD, BX>(data, ES, xtiles, xtiles, 0, pl.tw, op, s, "fft_x_inv_grad"); break;
     default: throw Error{COLA_E_ARG, "unknown k-space operator"};
   }
   KOp none;
