@@ -176,8 +176,8 @@ def traffic_for(kernel):
 _SYMBOLS = [("k_fft_col_fwd_force<{n}, true>", "fft_x_fwd_force"),
             ("k_fft_col_fwd_force<{n}, false>", "fft_x_fwd_force_1src"),
             ("k_fft_col_inv_yz", "fft_y_inv_yz"), ("k_fft_col_fwd_op<{n}, 3,", "fft_x_fwd_smooth"),
-            ("k_fft_col_fwd_op<{n}, 2,", "fft_x_fwd_pot"), ("k_fft_col<{n}, -1, 0>", "fft_y_fwd"),
-            ("k_fft_col<{n}, 1, 0>", "fft_y_inv"), ("k_fft_c2r_row3", "fft_c2r_z3"),
+            ("k_fft_col_fwd_op<{n}, 2,", "fft_x_fwd_pot"), ("k_fft_col<{n}, -1, 0, 16>", "fft_y_fwd"),
+            ("k_fft_col<{n}, 1, 0, 16>", "fft_y_inv"), ("k_fft_c2r_row3", "fft_c2r_z3"),
             ("k_fft_screen_row", "fft_z_screen"), ("k_fft_r2c_row", "fft_r2c_z"),
             ("k_gather", "gather_kick_drift"), ("k_deposit_tiles", "deposit"), ("k_bin<0,", "bin_count"),
             ("k_bin<1,", "bin_scatter"), ("k_scan_", "bin_scan"), ("k_fill", "fill")]
