@@ -108,14 +108,14 @@ def _mock_params(C, rng, j, sizes, seed0, n_steps):
 def bench_ensemble(C, torch, boxes=64, budget=160 << 30):
     """A mixed ensemble of small boxes (seeded draw, seed 4: n_p in {64, 96, 128, 192,
     256}, 10 steps) run one at a time on one stream, then all resident at once and
-    interleaved on four streams; aggregate particle-steps/s and yardstick HBM fraction."""
+    interleaved on eight streams; aggregate particle-steps/s and yardstick HBM fraction."""
     import numpy as np
     from paper_1703_00879_amd.serve import GpuEngine, Request, Server, summarize
     rng = np.random.default_rng(4)
     ps = [_mock_params(C, rng, j, (64, 96, 128, 192, 256), 1000, 10) for j in range(boxes)]
     yard = sum(yardstick_bytes_for(p, C) * p.n_steps for p in ps)
     out = {"boxes": boxes, "n_steps": 10, "particle_steps": sum(p.np1d ** 3 * p.n_steps for p in ps)}
-    for name, streams, active in (("one_at_a_time", 1, 1), ("interleaved_4_streams", 4, boxes)):
+    for name, streams, active in (("one_at_a_time", 1, 1), ("interleaved_8_streams", 8, boxes)):
         res = Server(GpuEngine(n_streams=streams), budget, max_active=active).run(
             [Request(p, 0.0, j) for j, p in enumerate(ps)])
         sm = summarize(res)
