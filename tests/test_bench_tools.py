@@ -1,0 +1,116 @@
+"""Host-side pieces of bench.py: the algorithmic byte counts, the yardstick, the mapping of
+kernel symbols to step names, and the rocprofv3 summary built from synthetic CSV files."""
+
+import csv
+import importlib.util
+import json
+import os
+
+import pytest
+
+from paper_1703_00879_amd import cola as C
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="module")
+def bench():
+    spec = importlib.util.spec_from_file_location("bench", os.path.join(ROOT, "bench.py"))
+    mod = importlib.util.module_from_spec(spec)
+    spec.loader.exec_module(mod)
+    return mod
+
+
+def test_yardstick_per_particle_step(bench):
+    # 1300 B per screened scale-independent particle-step at M = 8N; LCDM 852 B; with the
+    # per-step LPT synthesis of scale-dependent growth 1428 B
+    p = bench.workload_params(C)
+    N = p.np1d ** 3
+    assert bench.yardstick_bytes_per_step(p) == 1300 * N
+    assert bench.yardstick_bytes_for(p, C) == 1300 * N
+    assert bench.yardstick_bytes_for(p.with_(model=C.LCDM), C) == 852 * N
+    assert bench.yardstick_bytes_for(p.with_(model=C.FR_HS1, growth_mode=0), C) == 1428 * N
+    assert bench.yardstick_bytes_for(p.with_(model=C.FR_HS1, growth_mode=1), C) == 1300 * N
+
+
+def test_algorithmic_bytes(bench):
+    p = bench.workload_params(C)
+    n, N = p.nmesh1d, p.np1d ** 3
+    M, H = n ** 3, n * n * (n // 2 + 1)
+    ab = lambda k: bench.algorithmic_bytes(k, p)  # noqa: E731
+    assert ab("gather_kick_drift") == 12 * M + 72 * N
+    assert ab("fft_c2r_z3") == 24 * H + 12 * M
+    assert ab("fft_x_fwd_smooth") == 16 * H and ab("fft_x_fwd_pot") == 24 * H
+    assert ab("fft_x_fwd_force_1src") == 24 * H and ab("fft_x_fwd_force") == 32 * H
+    assert ab("deposit") == 16 * N + 4 * M
+    assert ab("no_such_kernel") is None
+
+
+@pytest.mark.parametrize("symbol,name", [
+    ("void cola::k_fft_col<1024, -1, 0, 16>(HIP_vector_type<float, 2u>*, long)", "fft_y_fwd"),
+    ("void cola::k_fft_col<1024, 1, 0, 16>(HIP_vector_type<float, 2u>*, long)", "fft_y_inv"),
+    ("void cola::k_fft_col_fwd_force<1024, false>(float2 const*)", "fft_x_fwd_force_1src"),
+    ("void cola::k_fft_col_fwd_force<1024, true>(float2 const*)", "fft_x_fwd_force"),
+    ("void cola::k_fft_col_fwd_op<1024, 3, false>(float2*)", "fft_x_fwd_smooth"),
+    ("void cola::k_fft_col_fwd_op<1024, 2, true>(float2*)", "fft_x_fwd_pot"),
+    ("void cola::k_fft_screen_row<512, 2>(float2*)", "fft_z_screen"),
+    ("void cola::k_fft_c2r_row3<512>(float2 const*)", "fft_c2r_z3"),
+    ("void cola::k_gather<0>(cola::GatherDev, long)", "gather_kick_drift"),
+    ("void cola::k_bin<0, true>(float const*)", "bin_count"),
+    ("void cola::k_bin<1, true>(float const*)", "bin_scatter"),
+    ("void cola::k_deposit_tiles<16>(float4 const*)", "deposit"),
+])
+def test_profile_names(bench, symbol, name):
+    assert bench._profile_name(symbol, 1024) == name
+
+
+def _write(path, header, rows):
+    os.makedirs(os.path.dirname(path), exist_ok=True)
+    with open(path, "w", newline="") as f:
+        w = csv.writer(f)
+        w.writerow(header)
+        w.writerows(rows)
+
+
+def test_summarize_rocprof_on_synthetic_runs(bench, tmp_path):
+    """Three steps (the first is the warm-up): the gather ends each step; the summary
+    covers the two steps after the first gather, scales FETCH_SIZE and WRITE_SIZE by the
+    factors that make a 1 GiB copy read 1 GiB, and writes both profile files."""
+    d = tmp_path / "prof"
+    gather = "void cola::k_gather<0>(cola::GatherDev, long)"
+    c2r3 = "void cola::k_fft_c2r_row3<512>(float2 const*)"
+    trace, fetch, write = [], [], []
+    did = 0
+    for step in range(3):
+        for name, ms, kib_r, kib_w in ((c2r3, 5.0, 1000.0, 3000.0), (gather, 4.0, 2000.0, 500.0)):
+            did += 1
+            t0 = 1_000_000_000 * did
+            trace.append([did, name, t0, t0 + int(ms * 1e6)])
+            fetch.append([did, name, "FETCH_SIZE", kib_r])
+            write.append([did, name, "WRITE_SIZE", kib_w])
+    _write(str(d / "trace" / "trace_kernel_trace.csv"),
+           ["Dispatch_Id", "Kernel_Name", "Start_Timestamp", "End_Timestamp"], trace)
+    _write(str(d / "fetch" / "fetch_counter_collection.csv"),
+           ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"], fetch)
+    _write(str(d / "write" / "write_counter_collection.csv"),
+           ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"], write)
+    gib_kib = (1 << 30) / 1024
+    copy = "__amd_rocclr_copyBuffer"
+    _write(str(d / "cfetch" / "cfetch_counter_collection.csv"),
+           ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"],
+           [[1, copy, "FETCH_SIZE", gib_kib / 2], [2, copy, "FETCH_SIZE", gib_kib / 2]])
+    _write(str(d / "cwrite" / "cwrite_counter_collection.csv"),
+           ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"],
+           [[1, copy, "WRITE_SIZE", gib_kib]])
+    out = tmp_path / "profiles"
+    t = bench.summarize_rocprof(str(d), str(out))
+    assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
+    g, c = t["kernels"]["gather_kick_drift"], t["kernels"]["fft_c2r_z3"]
+    assert g["launches_per_step"] == 1 and c["launches_per_step"] == 1
+    assert g["avg_ms"] == pytest.approx(4.0) and c["ms_per_step"] == pytest.approx(5.0)
+    assert g["bytes_per_launch"] == pytest.approx(1024 * (2 * 2000.0 + 500.0))
+    assert c["bytes_per_launch"] == pytest.approx(1024 * (2 * 1000.0 + 3000.0))
+    saved = json.load(open(out / "traffic_ndgp_512_1024.json"))
+    assert saved["source_hash"] == bench.source_hash()
+    md = open(out / "pm_step_ndgp_512_1024.md").read()
+    assert "| fft_c2r_z3 | 1 | 5.000 |" in md and "rocprofv3 --kernel-trace" in md
