@@ -315,3 +315,62 @@ def test_growth_triangles_rejects_non_triangles():
     with pytest.raises(C.ColaError):
         C.cola_growth_triangles(p, tri, 0.01, out)   # before a_ini
     C.cola_growth_triangles(p, tri[:0], 1.0, out[:0])
+
+
+def test_pm_force_unperturbed_lattice_is_exactly_uniform():
+    """Degenerate case: with u = 0 every cell receives the same mass through weights 1/2
+    per axis, so the fixed-point deposit gives rho = 1 exactly, and every force vanishes."""
+    p = C.Params(model=C.NDGP, rc_h0=1.0, np1d=32, nmesh1d=64, box=128.0)
+    st = prepared(p)
+    st.disp_f.zero_()
+    N, M = p.np1d ** 3, p.nmesh1d ** 3
+    F = torch.empty(3, N, dtype=torch.float32, device="cuda")
+    mesh = torch.empty(5, M, dtype=torch.float32, device="cuda")
+    C.cola_pm_force(p, st, 0.7, F, mesh)
+    sync()
+    assert bool((mesh[0] == 1.0).all())
+    assert float(mesh[1:].abs().max()) == 0.0 and float(F.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("model", [C.LCDM, C.FR_HS1, C.NDGP])
+def test_pm_force_all_particles_in_one_cell(model):
+    """Degenerate clustering: every particle moved into the cell at the origin (one tile,
+    one class: a single deposit segment and thousands of LDS atomics on eight cells).  The
+    force is that of a point mass on the mesh; the screened source follows the oracle."""
+    p = C.Params(model=model, fr0_abs=1e-5, rc_h0=1.0, np1d=16, nmesh1d=32, box=64.0)
+    st = prepared(p)
+    n_p, L = p.np1d, p.box
+    q = (np.arange(n_p) * L / n_p + 0.5 * L / p.nmesh1d).astype(np.float64)
+    qx, qy, qz = np.meshgrid(q, q, q, indexing="ij")
+    target = 0.3 * L / p.nmesh1d                       # inside the first cell on every axis
+    u = np.stack([target - qx.ravel(), target - qy.ravel(), target - qz.ravel()]).astype(np.float32)
+    st.disp_f.copy_(torch.from_numpy(u))
+    N, M = n_p ** 3, p.nmesh1d ** 3
+    F = torch.empty(3, N, dtype=torch.float32, device="cuda")
+    mesh = torch.empty(5, M, dtype=torch.float32, device="cuda")
+    C.cola_pm_force(p, st, 0.9, F, mesh)
+    sync()
+    mesh = mesh.cpu().numpy()
+    Fo, mo = pm_force(u.astype(np.float64), to_oracle(p), 0.9)
+    # every particle sits at the same point, where the CIC self-force nearly cancels: its
+    # error is measured against the scale of the force field it is interpolated from
+    dF = F.cpu().numpy().astype(np.float64) - Fo
+    e = dict(rho=relrms(mesh[0], mo["rho"]), src=relrms(mesh[1], mo["src"]),
+             fx=relrms(mesh[2], mo["force"][0]),
+             fp_field=float(np.sqrt(np.mean(dF * dF)) / np.sqrt(np.mean(mo["force"] ** 2))))
+    record(f"pm_force_one_cell_model{model}", **e)
+    assert abs(float(mesh[0].sum()) / M - 1.0) < 1e-6          # mass conserved
+    assert e["rho"] < 1e-5 and e["src"] < 1e-4 and e["fx"] < 1e-5, e
+    assert e["fp_field"] < 1e-5, e
+
+
+def test_zero_amplitude_run_stays_on_the_lattice():
+    """sigma8 -> 0: the initial displacements and every force vanish, so ten COLA steps
+    leave the particles on the lattice."""
+    p = C.Params(model=C.FR_HS1, fr0_abs=1e-5, np1d=16, nmesh1d=32, box=64.0, n_steps=10,
+                 sigma8=1e-30)
+    st = _ic_state(p)
+    for i in range(p.n_steps):
+        C.cola_step(p, st, i)
+    sync()
+    assert float(st.disp_f.abs().max()) < 1e-20 and float(st.vel_f.abs().max()) < 1e-20
