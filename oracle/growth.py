@@ -15,10 +15,11 @@ import numpy as np
 from scipy import integrate
 
 from .background import E, kappa, dlna_dtau
-from .params import MODEL_SYMMETRON
+from .params import MODEL_SYMMETRON, READ_D2_HALF_K
 
 
-def solve_growth(k, a_out, om, mu_fn, g2_fn, a_ini, rtol=1e-12, atol=1e-14, breaks=()):
+def solve_growth(k, a_out, om, mu_fn, g2_fn, a_ini, rtol=1e-12, atol=1e-14, breaks=(),
+                 half_k=False):
     """Return an array G[len(a_out), len(k), 6] of (D1, D1', D1'', D2, D2', D2'')
     at the requested scale factors (a_out sorted ascending, a_out[0] >= a_ini).
 
@@ -27,36 +28,43 @@ def solve_growth(k, a_out, om, mu_fn, g2_fn, a_ini, rtol=1e-12, atol=1e-14, brea
     breaks: scale factors where the right-hand side is not smooth (the symmetron's
     switch-on at a_*, App. C); the integration restarts there with a tiny first step, so
     that the narrow feature that follows is resolved rather than stepped over.
+    half_k: the alternative reading of the D2 source, D1(k/sqrt2, a)^2 in place of the
+    printed D1(k, a)^2 (k1 = k2 = k/sqrt2 is the triangle gamma_2 is taken at); D1 at
+    k/sqrt2 is then integrated alongside.
     """
     k = np.atleast_1d(np.asarray(k, dtype=np.float64))
     a_out = np.asarray(a_out, dtype=np.float64)
     K = k.size
+    kh = k / np.sqrt(2.0)
 
     def rhs_tau(a, y):
-        D1, dD1, D2, dD2 = y[:K], y[K:2 * K], y[2 * K:3 * K], y[3 * K:]
+        D1, dD1, D2, dD2 = y[:K], y[K:2 * K], y[2 * K:3 * K], y[3 * K:4 * K]
         kap = kappa(a, om)
         mu = mu_fn(k, a)
         g2 = g2_fn(k, a)
         Ea = E(a, om)
         dd1 = kap * mu * D1
-        dd2 = kap * mu * D2 - kap * mu * D1 * D1 - 2.0 * a ** 4 * Ea * Ea * g2 * D1 * D1
-        return dD1, dd1, dD2, dd2
+        Ds = y[4 * K:5 * K] if half_k else D1   # the growth factor squared in the D2 source
+        dd2 = kap * mu * D2 - kap * mu * Ds * Ds - 2.0 * a ** 4 * Ea * Ea * g2 * Ds * Ds
+        if not half_k:
+            return dD1, dd1, dD2, dd2
+        return dD1, dd1, dD2, dd2, y[5 * K:], kap * mu_fn(kh, a) * y[4 * K:5 * K]
 
     def rhs(a, y):
-        dD1, dd1, dD2, dd2 = rhs_tau(a, y)
         f = 1.0 / (a ** 3 * E(a, om))
-        return np.concatenate([dD1 * f, dd1 * f, dD2 * f, dd2 * f])
+        return np.concatenate([d * f for d in rhs_tau(a, y)])
 
     g0 = dlna_dtau(a_ini, om)
     y0 = np.concatenate([np.ones(K), np.full(K, g0), np.full(K, -3.0 / 7.0),
-                         np.full(K, -6.0 / 7.0 * g0)])
+                         np.full(K, -6.0 / 7.0 * g0)]
+                        + ([np.ones(K), np.full(K, g0)] if half_k else []))
     out = np.empty((a_out.size, K, 6))
     need = a_out > a_ini
     if np.any(need):
         Ys = iter(_integrate_pieces(rhs, y0, a_ini, a_out[need], breaks, rtol, atol))
     for i, a in enumerate(a_out):
         y = next(Ys) if need[i] else y0
-        dD1, dd1, dD2, dd2 = rhs_tau(a, y)
+        dD1, dd1, dD2, dd2 = rhs_tau(a, y)[:4]
         out[i, :, 0] = y[:K]
         out[i, :, 1] = dD1
         out[i, :, 2] = dd1
@@ -103,13 +111,15 @@ def growth_table(p, model, a_out):
     Returns G[len(a_out), n_k, 6] and a flag saying whether it is k-dependent.
     """
     breaks = growth_breaks(p, model)
+    half = bool(p.readings & READ_D2_HALF_K)
     if not p.scale_dependent:
         G = solve_growth(np.array([0.0]), a_out, p.omega_m, model.mu, model.gamma2_orth,
-                         p.a_ini, breaks=breaks)
+                         p.a_ini, breaks=breaks, half_k=half)
         return G, False
     n2 = distinct_n2(p.np1d)
     k = 2.0 * np.pi * np.sqrt(n2.astype(np.float64)) / p.box
-    G = solve_growth(k, a_out, p.omega_m, model.mu, model.gamma2_orth, p.a_ini, breaks=breaks)
+    G = solve_growth(k, a_out, p.omega_m, model.mu, model.gamma2_orth, p.a_ini, breaks=breaks,
+                     half_k=half)
     return G, True
 
 

@@ -18,7 +18,7 @@ import numpy as np
 
 from .background import E, omega_m_of_a
 from .params import (MODEL_LCDM, MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, FILTER_GAUSS,
-                     FILTER_TOPHAT, FILTER_SHARPK, H0_OVER_C)
+                     FILTER_TOPHAT, FILTER_SHARPK, H0_OVER_C, READ_X_TOTAL_DENSITY, READ_X_NO_A3)
 
 
 # ----------------------------------------------------------------------------- f(R)
@@ -77,11 +77,20 @@ def dgp_mu(a, om, rc):
     return 1.0 + 1.0 / (3.0 * dgp_beta(a, om, rc))
 
 
-def dgp_gamma2E_orth(a, om, rc):
-    """gamma_2^E = -(H0/H)^2 (r_c H0)^2 Om^2 / (6 beta^3 a^6) (1 - cos^2 theta) (Sec. 5.2),
-    at cos theta = 0."""
+def dgp_gamma2E(a, om, rc, cos2=0.0):
+    """gamma_2^E = -(H0/H)^2 (r_c H0)^2 Om^2 / (6 beta^3 a^6) (1 - cos^2 theta) (Sec. 5.2).
+
+    Pinned against the nDGP field equation (Sec. 6.2, eq. ndgpfieldeq): the O(A1 A2)
+    response of that equation to two plane waves, solved on a mesh with the nonlinear
+    coefficient 2 (r_c H0)^2 / (3 beta a^4) (the printed 2 r_c^2 / a^4 lacks the 1/(3 beta)
+    that reproduces both this gamma_2^E and the printed prefactor of the Vainshtein x)."""
     b = dgp_beta(a, om, rc)
-    return -(rc * rc * om * om) / (6.0 * E(a, om) ** 2 * b ** 3 * a ** 6)
+    return -(rc * rc * om * om) / (6.0 * E(a, om) ** 2 * b ** 3 * a ** 6) * (1.0 - cos2)
+
+
+def dgp_gamma2E_orth(a, om, rc):
+    """gamma_2^E of Sec. 5.2 at cos theta = 0 (the orthogonal triangle of Sec. 4.2)."""
+    return dgp_gamma2E(a, om, rc, 0.0)
 
 
 # ----------------------------------------------------------------------------- symmetron
@@ -223,17 +232,28 @@ def eps_potential(phi_n, phi_crit):
     return out
 
 
-def vainshtein_x(rho_over_mean, a, om, rc, beta):
-    """x = 8 (r_c H0)^2 Omega_m (rho/rho_bar) / (9 beta^2 a^3) (Sec. 6.2, with the
-    physical mean density rho_bar_0 a^-3 of the Vainshtein radius), rho/rho_bar
-    clamped at 0."""
-    y = np.maximum(0.0, np.asarray(rho_over_mean, dtype=np.float64))
-    return 8.0 * rc * rc * om * y / (9.0 * beta * beta * a ** 3)
+def vainshtein_x(delta_bar, a, om, rc, beta, readings=0):
+    """x = 8 (r_c H0)^2 Omega_m delta_bar / (9 beta^2 a^3) (Sec. 6.2), delta_bar the mean
+    density contrast inside the radius (here the smoothed delta_R), clamped at -1.
+
+    Reading: the spherical solution of the nDGP field equation (Sec. 6.2, eq.
+    ndgpfieldeq) integrates r^2 x the equation to a quadratic in phi'/r whose source is
+    kappa delta_bar / (9 beta): x is proportional to the mean overdensity, so the mean
+    density is unscreened (eps = 1), and kappa = 1.5 Om a over the a^4 of the nonlinear
+    term leaves a^-3.  The printed rho/rho_bar and the printed form without a^-3 are the
+    READ_X_TOTAL_DENSITY and READ_X_NO_A3 readings.  For delta_bar >= -1, x > -8/9 (beta^2
+    a^3 > (r_c H0)^2 Om), so 1 + x > 0.  Pinned by the numerical radial solution of the
+    field equation for top-hat over- and underdensities."""
+    d = np.maximum(-1.0, np.asarray(delta_bar, dtype=np.float64))
+    y = d + 1.0 if readings & READ_X_TOTAL_DENSITY else d
+    a3 = 1.0 if readings & READ_X_NO_A3 else a ** 3
+    return 8.0 * rc * rc * om * y / (9.0 * beta * beta * a3)
 
 
 def eps_vainshtein(x):
     """eps = 2 (sqrt(1+x) - 1)/x = 2/(1 + sqrt(1+x)) (Sec. 6.2, read so that eps -> 1
-    as x -> 0 and eps -> 2/sqrt(x) deep inside the Vainshtein radius)."""
+    as x -> 0 and eps -> 2/sqrt(x) deep inside the Vainshtein radius; x in (-1, 0) in
+    underdense regions gives eps > 1)."""
     return 2.0 / (1.0 + np.sqrt(1.0 + np.asarray(x, dtype=np.float64)))
 
 

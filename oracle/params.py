@@ -20,6 +20,15 @@ FILTER_GAUSS = 0
 FILTER_TOPHAT = 1
 FILTER_SHARPK = 2
 
+# Alternative readings of passages the paper leaves ambiguous (bit flags of Params.readings;
+# the default 0 takes the readings stated in the module docstrings):
+READ_X_TOTAL_DENSITY = 1   # Vainshtein x from rho/rho_bar = 1 + delta_R, as printed (Sec. 6.2),
+                           # instead of the mean overdensity delta_R that the field equation gives
+READ_X_NO_A3 = 2           # Vainshtein x without the a^-3 of the physical mean density
+READ_D2_HALF_K = 4         # second-order growth source D1(k/sqrt2, a)^2, the k1 = k2 = k/sqrt2
+                           # argument of gamma_2, instead of the printed D1(k, a)^2 (Sec. 4.2)
+READ_ALL = READ_X_TOTAL_DENSITY | READ_X_NO_A3 | READ_D2_HALF_K
+
 H0_OVER_C = 1.0 / 2997.92458   # h/Mpc
 
 
@@ -47,6 +56,7 @@ class Params:
     z_init: float = 19.0
     n_steps: int = 10
     seed: int = 1
+    readings: int = 0             # bit flags READ_* above
 
     @property
     def a_ini(self):

@@ -75,7 +75,7 @@ def planar_pm(u1, p, a, model=None):
             elif p.model == MODEL_NDGP:
                 dR = np.fft.ifft(dk * window(np.abs(k) * p.r_smooth, p.filter)).real
                 beta = dgp_beta(a, p.omega_m, p.rc_h0)
-                eps = eps_vainshtein(vainshtein_x(1.0 + dR, a, p.omega_m, p.rc_h0, beta))
+                eps = eps_vainshtein(vainshtein_x(dR, a, p.omega_m, p.rc_h0, beta, p.readings))
             else:
                 raise ValueError(p.model)
             S = delta * eps

@@ -10,7 +10,7 @@ Steps, in the paper's order:
    * f(R): Phi_N/c^2 = Phi (H0/c)^2 / a^2 (the code potential is a^2 times the
      conventional one), eps = min(1, |3 f_R(a) / (2 Phi_N)|) (Sec. 6.1);
    * nDGP: delta_R = density smoothed with W(kR) (Gaussian by default),
-     x = 8 (r_c H0)^2 Om (1 + delta_R) / (9 beta^2 a^3), eps = 2/(1 + sqrt(1 + x)) (Sec. 6.2);
+     x = 8 (r_c H0)^2 Om delta_R / (9 beta^2 a^3), eps = 2/(1 + sqrt(1 + x)) (Sec. 6.2);
    screened source S = delta * eps (S = delta when screening is off);
 4. linear field equation nabla^2 phi = a^2 m^2 phi + C kappa S (Sec. 6, App. B):
    phi_k = -C kappa S_k / (k^2 + a^2 m^2), phi_0 = 0;
@@ -107,7 +107,7 @@ def screened_source(delta, delta_k, p, a, model):
         k = np.sqrt(kx * kx + ky * ky + kz * kz)
         dR = np.fft.irfftn(delta_k * window(k * p.r_smooth, p.filter), s=(n, n, n), axes=(0, 1, 2))
         beta = dgp_beta(a, p.omega_m, p.rc_h0)
-        eps = eps_vainshtein(vainshtein_x(1.0 + dR, a, p.omega_m, p.rc_h0, beta))
+        eps = eps_vainshtein(vainshtein_x(dR, a, p.omega_m, p.rc_h0, beta, p.readings))
     else:
         raise ValueError(p.model)
     return delta * eps

@@ -119,7 +119,7 @@ def test_fr_screening_deep_potential_closed_form():
 
 
 def test_ndgp_screening_plane_wave_closed_form():
-    # delta_R = W(kR) A cos exactly for a plane wave; eps from x(1 + delta_R) (Sec. 6.2)
+    # delta_R = W(kR) A cos exactly for a plane wave; eps from x(delta_R) (Sec. 6.2)
     a = 0.9
     for filt in (0, 1, 2):
         p = Params(model=MODEL_NDGP, screening=1, nmesh1d=16, box=32.0, rc_h0=2.0,
@@ -128,7 +128,7 @@ def test_ndgp_screening_plane_wave_closed_form():
         kk = np.sqrt(k @ k)
         dR = window(kk * p.r_smooth, filt) * d
         beta = dgp_beta(a, 0.3, 2.0)
-        eps = eps_vainshtein(vainshtein_x(1 + dR, a, 0.3, 2.0, beta))
+        eps = eps_vainshtein(vainshtein_x(dR, a, 0.3, 2.0, beta))
         S = screened_source(d, np.fft.rfftn(d), p, a, Model(p))
         assert np.allclose(S, d * eps, rtol=1e-12, atol=1e-13)
 
@@ -169,7 +169,7 @@ def _brute_force_force(delta, p, a):
         elif p.screening and p.model == MODEL_NDGP:
             dR = inv(dk * window(np.sqrt(k2) * p.r_smooth, p.filter)).real
             b = dgp_beta(a, p.omega_m, p.rc_h0)
-            S = delta * eps_vainshtein(vainshtein_x(1 + dR, a, p.omega_m, p.rc_h0, b))
+            S = delta * eps_vainshtein(vainshtein_x(dR, a, p.omega_m, p.rc_h0, b))
         Sk = fwd(S)
         den = k2 + m.a2m2(a)
         tot = tot + np.where(k2 > 0, -m.coupling(a) * kap / np.where(k2 > 0, den, 1), 0) * Sk
