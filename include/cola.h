@@ -52,6 +52,18 @@ typedef int32_t cola_status;
 #define COLA_SMOOTH_TOPHAT 1
 #define COLA_SMOOTH_SHARPK 2
 
+/* Bit flags of cola_params.readings: alternative readings of passages the paper leaves
+ * ambiguous.  With readings = 0 the library takes these readings:
+ *  - Vainshtein x (Sec. 6.2) = 8 (r_c H0)^2 Omega_m delta_R / (9 beta^2 a^3), delta_R the
+ *    smoothed density contrast clamped at -1: the spherical solution of the nDGP field
+ *    equation (eq. ndgpfieldeq) makes x proportional to the mean overdensity inside the
+ *    radius, and kappa over the a^4 of its nonlinear term leaves a^-3;
+ *  - the second-order growth source uses D1(k, a)^2, as printed (Sec. 4.2, App. B). */
+#define COLA_READ_X_TOTAL_DENSITY 1  /* x from rho/rho_bar = 1 + delta_R, as printed */
+#define COLA_READ_X_NO_A3 2          /* x without the a^-3, as printed */
+#define COLA_READ_D2_HALF_K 4        /* D2 source D1(k/sqrt2, a)^2: the k1 = k2 = k/sqrt2 of gamma_2 */
+#define COLA_READ_ALL 7
+
 /* Run parameters.  Background: flat LCDM (App. B).  Initial power: Eisenstein-Hu
  * no-wiggle shape normalised to sigma8 of linear LCDM at z = 0 and scaled back to
  * a_ini with the LCDM growth factor.  Model inputs per Sec. 5; screening per Sec. 6.
@@ -63,7 +75,7 @@ typedef int32_t cola_status;
  * box > 0, z_init > 0,
  * 1 <= n_steps <= 4096, fr0_abs > 0 for f(R), rc_h0 > 0 for nDGP, sym_beta >= 0,
  * sym_mass > 0 and 0 < sym_astar < 1 for the symmetron, r_smooth >= 0, filter in 0..2,
- * model in 0..3, growth_mode in 0..1, screening in 0..1. */
+ * model in 0..3, growth_mode in 0..1, screening in 0..1, readings & ~COLA_READ_ALL = 0. */
 typedef struct cola_params {
   double omega_m, omega_b, h, n_s, sigma8, t_cmb;
   double fr0_abs;     /* |f_R0| of Hu-Sawicki f(R) (Sec. 5.1) */
@@ -73,7 +85,8 @@ typedef struct cola_params {
   double z_init;      /* initial redshift; a_ini = 1/(1 + z_init) */
   uint64_t seed;      /* seed of the counter-based white noise */
   int32_t model, screening, filter, growth_mode;
-  int32_t np1d, nmesh1d, n_steps, reserved;
+  int32_t np1d, nmesh1d, n_steps;
+  int32_t readings;   /* COLA_READ_* bit flags; 0 = the readings stated above */
   /* symmetron (App. C): beta(a) = sym_beta sqrt(s), m^2(a) = (sym_mass H0)^2 s with
    * s = 1 - (sym_astar / a)^3 after a = sym_astar, beta = m = 0 before; the field equation
    * couples with C = 2 beta^2 and screens with eps = min(1, |Phi_crit/Phi_N|), Phi_crit the

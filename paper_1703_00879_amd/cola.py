@@ -18,6 +18,7 @@ LIB_PATH = os.environ.get("COLA_LIBRARY") or os.path.join(_PKG, "_lib", "libcola
 COLA_OK = 0
 LCDM, FR_HS1, NDGP, SYMMETRON = 0, 1, 2, 3
 SMOOTH_GAUSS, SMOOTH_TOPHAT, SMOOTH_SHARPK = 0, 1, 2
+READ_X_TOTAL_DENSITY, READ_X_NO_A3, READ_D2_HALF_K = 1, 2, 4
 
 EXPORTED = ["cola_query_sizes", "cola_validate", "cola_prepare", "cola_make_ic", "cola_pm_force",
             "cola_step", "cola_power_spectrum", "cola_positions", "cola_growth_table",
@@ -41,7 +42,7 @@ class _Params(ctypes.Structure):
                 ("model", ctypes.c_int32), ("screening", ctypes.c_int32),
                 ("filter", ctypes.c_int32), ("growth_mode", ctypes.c_int32),
                 ("np1d", ctypes.c_int32), ("nmesh1d", ctypes.c_int32),
-                ("n_steps", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("n_steps", ctypes.c_int32), ("readings", ctypes.c_int32),
                 ("sym_beta", ctypes.c_double), ("sym_mass", ctypes.c_double),
                 ("sym_astar", ctypes.c_double)]
 
@@ -83,12 +84,13 @@ class Params:
     np1d: int = 32
     nmesh1d: int = 64
     n_steps: int = 10
+    readings: int = 0
 
     def with_(self, **kw):
         return replace(self, **kw)
 
     def _c(self):
-        return _Params(**{f.name: getattr(self, f.name) for f in fields(self)}, reserved=0)
+        return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
 
 
 _lib = None

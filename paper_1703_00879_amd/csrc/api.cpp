@@ -129,7 +129,9 @@ static void check_ptr(const void* p, const char* what) {
     throw Error{COLA_E_ARG, std::string(what) + " must be 256-byte aligned"};
 }
 
-static Bufs carve(const cola_params& p, const cola_state* st) {
+// Device pointers of every buffer of a state.  `work` replaces st->work when given (the
+// allocation-free step runs on the library's own scratch array).
+static Bufs carve(const cola_params& p, const cola_state* st, void* work = nullptr) {
   if (!st) throw Error{COLA_E_ARG, "state is NULL"};
   Bufs b;
   b.L = make_layout(p);
@@ -138,7 +140,10 @@ static Bufs carve(const cola_params& p, const cola_state* st) {
   check_ptr(st->vel, "state.vel");
   check_ptr(st->lpt, "state.lpt");
   check_ptr(st->tables, "state.tables");
-  check_ptr(st->work, "state.work");
+  if (!work) {
+    check_ptr(st->work, "state.work");
+    work = st->work;
+  }
   b.growth = at<double>(st->tables, L.off_growth);
   b.ref = at<double>(st->tables, L.off_ref);
   b.tw_m = at<float2>(st->tables, L.off_tw_m);
@@ -146,11 +151,11 @@ static Bufs carve(const cola_params& p, const cola_state* st) {
   b.pk_scratch = at<void>(st->tables, L.off_scratch);
   b.pk_out = at<float4>(st->tables, L.off_scratch + pk_scratch_bytes(L, 2048));
   b.pk_cnt = reinterpret_cast<unsigned long long*>(b.pk_out + 2048);
-  for (int i = 0; i < 6; ++i) b.mesh[i] = at<float2>(st->work, L.off_mesh[i]);
-  b.force = at<float>(st->work, L.off_mesh[3]);
-  for (int i = 0; i < 6; ++i) b.pf[i] = L.kdep ? at<float2>(st->work, L.off_pfield[i]) : nullptr;
-  b.bins = at<void>(st->work, L.off_bins);
-  b.entries = at<float4>(st->work, L.off_entries);
+  for (int i = 0; i < 6; ++i) b.mesh[i] = at<float2>(work, L.off_mesh[i]);
+  b.force = at<float>(work, L.off_mesh[3]);
+  for (int i = 0; i < 6; ++i) b.pf[i] = L.kdep ? at<float2>(work, L.off_pfield[i]) : nullptr;
+  b.bins = at<void>(work, L.off_bins);
+  b.entries = at<float4>(work, L.off_entries);
   if (L.kdep) {
     b.phi1 = at<float2>(st->lpt, 0);
     b.phi2 = at<float2>(st->lpt, align_up(L.pgrid_elems * sizeof(float2)));
@@ -240,7 +245,7 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
       op.a2m2 = 0.f;
     }
     fft_screen(pl, kind, sop, M[1], M[2], R(M[0]), flat_out ? R(M[3]) : nullptr, p.model,
-               sc.cham_thr, sc.vx_pref, cn, c5, s);
+               sc.cham_thr, sc.vx_pref, sc.vx_off, cn, c5, s);
     if (flat_out) launch_unpad_mesh(L, R(M[3]), flat_out + L.M, s);
     src = M[2];
   } else if (flat_out) {
@@ -248,6 +253,57 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
   }
   float2* const work[3] = {M[0], M[1], M[2]};
   fft_c2r_force3(pl, op, dk, src, work, b.force, s);
+}
+
+// One COLA step on the given work area (st->work when null, else the library's scratch).
+static void step_impl(const cola_params* p, cola_state* st, int32_t i, void* work, hipStream_t s) {
+  if (!p) throw Error{COLA_E_ARG, "params is NULL"};
+  const Bufs b = carve(*p, st, work);
+  const Layout& L = b.L;
+  if (!st->prepared || st->next_step < 0) throw Error{COLA_E_STATE, "no initial conditions"};
+  if (i != st->next_step) throw Error{COLA_E_STATE, "step index out of order"};
+  if (i < 0 || i >= p->n_steps) throw Error{COLA_E_STATE, "step index beyond n_steps"};
+  const Cosmo cz{p->omega_m, 1.0 - p->omega_m};
+  const double ai = a_of_step(*p, i), an = a_of_step(*p, i + 1);
+  const double a_lo = (i == 0) ? ai : 0.5 * (a_of_step(*p, i - 1) + ai);
+  const double a_hi = 0.5 * (ai + an);
+  GatherArgs g{};
+  g.dtk = tau_between(cz, a_lo, a_hi);
+  g.dtd = tau_between(cz, ai, an);
+  g.table = b.growth;
+  g.slice0 = (int64_t)i * L.n_k * 6;
+  g.slice1 = (int64_t)(i + 1) * L.n_k * 6;
+  if (L.kdep) {
+    // L''(q, a_i) and Psi_LPT(a_{i+1}) - Psi_LPT(a_i) from the stored k-space fields
+    const FFTPlan pp = plan_part(b);
+    for (int c = 0; c < 6; ++c) {
+      KOp op;
+      op.kf = (float)(2.0 * M_PI / p->box);
+      op.a = b.phi1;
+      op.b = b.phi2;
+      op.table = b.growth;
+      op.tab_slice0 = g.slice0;
+      op.tab_slice1 = g.slice1;
+      op.lpt_mode = c < 3 ? 0 : 1;
+      op.kdep = 1;
+      op.comp = c % 3;
+      op.scale = (float)(1.0 / (double)L.N);
+      fft_c2r(pp, K_LPT, op, b.pf[c], R(b.pf[c]), s);
+      if (c < 3)
+        g.lpp[c] = R(b.pf[c]);
+      else
+        g.dlt[c - 3] = R(b.pf[c]);
+    }
+  } else {
+    g.psi1 = b.psi1;
+    g.psi2 = b.psi2;
+  }
+  pm_core(*p, b, st->disp, ai, nullptr, s);
+  g.F3 = b.force;
+  g.disp = st->disp;
+  g.vel = st->vel;
+  launch_gather(L, g, s);
+  st->next_step = i + 1;
 }
 
 }  // namespace cola
@@ -405,55 +461,7 @@ cola_status cola_pm_force(const cola_params* p, cola_state* st, double a, float*
 }
 
 cola_status cola_step(const cola_params* p, cola_state* st, int32_t i, hipStream_t s) {
-  return guarded([&] {
-    if (!p) throw Error{COLA_E_ARG, "params is NULL"};
-    const Bufs b = carve(*p, st);
-    const Layout& L = b.L;
-    if (!st->prepared || st->next_step < 0) throw Error{COLA_E_STATE, "no initial conditions"};
-    if (i != st->next_step) throw Error{COLA_E_STATE, "step index out of order"};
-    if (i < 0 || i >= p->n_steps) throw Error{COLA_E_STATE, "step index beyond n_steps"};
-    const Cosmo cz{p->omega_m, 1.0 - p->omega_m};
-    const double ai = a_of_step(*p, i), an = a_of_step(*p, i + 1);
-    const double a_lo = (i == 0) ? ai : 0.5 * (a_of_step(*p, i - 1) + ai);
-    const double a_hi = 0.5 * (ai + an);
-    GatherArgs g{};
-    g.dtk = tau_between(cz, a_lo, a_hi);
-    g.dtd = tau_between(cz, ai, an);
-    g.table = b.growth;
-    g.slice0 = (int64_t)i * L.n_k * 6;
-    g.slice1 = (int64_t)(i + 1) * L.n_k * 6;
-    if (L.kdep) {
-      // L''(q, a_i) and Psi_LPT(a_{i+1}) - Psi_LPT(a_i) from the stored k-space fields
-      const FFTPlan pp = plan_part(b);
-      for (int c = 0; c < 6; ++c) {
-        KOp op;
-        op.kf = (float)(2.0 * M_PI / p->box);
-        op.a = b.phi1;
-        op.b = b.phi2;
-        op.table = b.growth;
-        op.tab_slice0 = g.slice0;
-        op.tab_slice1 = g.slice1;
-        op.lpt_mode = c < 3 ? 0 : 1;
-        op.kdep = 1;
-        op.comp = c % 3;
-        op.scale = (float)(1.0 / (double)L.N);
-        fft_c2r(pp, K_LPT, op, b.pf[c], R(b.pf[c]), s);
-        if (c < 3)
-          g.lpp[c] = R(b.pf[c]);
-        else
-          g.dlt[c - 3] = R(b.pf[c]);
-      }
-    } else {
-      g.psi1 = b.psi1;
-      g.psi2 = b.psi2;
-    }
-    pm_core(*p, b, st->disp, ai, nullptr, s);
-    g.F3 = b.force;
-    g.disp = st->disp;
-    g.vel = st->vel;
-    launch_gather(L, g, s);
-    st->next_step = i + 1;
-  });
+  return guarded([&] { step_impl(p, st, i, nullptr, s); });
 }
 
 cola_status cola_power_spectrum(const cola_params* p, cola_state* st, int32_t nbins, double* k_out,
@@ -461,6 +469,7 @@ cola_status cola_power_spectrum(const cola_params* p, cola_state* st, int32_t nb
   return guarded([&] {
     if (!p || !k_out || !p_out) throw Error{COLA_E_ARG, "NULL argument"};
     const Bufs b = carve(*p, st);
+    if (!st->prepared) throw Error{COLA_E_STATE, "state not prepared"};
     if (nbins < 1 || nbins > 2048) throw Error{COLA_E_ARG, "nbins must be in [1, 2048]"};
     launch_deposit(b.L, st->disp, R(b.mesh[0]), b.bins, b.entries, s);
     fft_r2c(plan_mesh(b), R(b.mesh[0]), b.mesh[1], s);

@@ -755,7 +755,7 @@ template <int NC, int MODEL>
 __global__ void __launch_bounds__(RowCfg<NC>::T)
 k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float* __restrict__ s_out,
                  int64_t nrows, int /*n*/, int pitch, int64_t plane, const float2* __restrict__ tw_g,
-                 float thr, float vx, float cn, float c5) {
+                 float thr, float vx, float vx0, float cn, float c5) {
   constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
   __shared__ float2 lds[NC * LS];
   __shared__ float2 tw[2 * NC];   // twiddles exp(-2 pi i t / n), staged in LDS
@@ -802,7 +802,9 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
       e0 = a0 > thr ? thr * fast_rcp(a0) : 1.f;
       e1 = a1 > thr ? thr * fast_rcp(a1) : 1.f;
     } else {
-      const float x0 = vx * fmaxf(0.f, 1.f + f.x), x1 = vx * fmaxf(0.f, 1.f + f.y);
+      // x = vx max(-1, delta_R) + vx0: vx0 = 0 for the mean-overdensity reading, vx for
+      // the total-density one (1 + x > 1/9 either way)
+      const float x0 = fmaf(vx, fmaxf(-1.f, f.x), vx0), x1 = fmaf(vx, fmaxf(-1.f, f.y), vx0);
       e0 = 2.f * fast_rcp(1.f + fast_sqrt(1.f + x0));
       e1 = 2.f * fast_rcp(1.f + fast_sqrt(1.f + x1));
     }
@@ -1001,8 +1003,8 @@ static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, c
 
 template <int N>
 static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* dk, float2* data,
-                        const float* rho, float* s_out, int model, float thr, float vx, float cn,
-                        float c5, hipStream_t s) {
+                        const float* rho, float* s_out, int model, float thr, float vx, float vx0,
+                        float cn, float c5, hipStream_t s) {
   const int n = pl.n, P = pl.pitch;
   const int64_t rows = (int64_t)n * n;
   constexpr int B = ColCfg<N>::B;
@@ -1029,10 +1031,10 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
     const dim3 g((unsigned)((rows + BR - 1) / BR)), b(RowCfg<N / 2>::T);
     if (model == COLA_FR_HS1 || model == COLA_SYMMETRON)   // eps = min(1, thr/|Phi|)
       hipLaunchKernelGGL((k_fft_screen_row<N / 2, COLA_FR_HS1>), g, b, 0, s, data, rho, s_out, rows, n,
-                         P, pl.plane, pl.tw, thr, vx, cn, c5);
+                         P, pl.plane, pl.tw, thr, vx, vx0, cn, c5);
     else
       hipLaunchKernelGGL((k_fft_screen_row<N / 2, COLA_NDGP>), g, b, 0, s, data, rho, s_out, rows, n, P,
-                         pl.plane, pl.tw, thr, vx, cn, c5);
+                         pl.plane, pl.tw, thr, vx, vx0, cn, c5);
     COLA_LAUNCH_CHECK();
   }
   col_pass<N, -1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s, "fft_y_fwd");
@@ -1050,9 +1052,10 @@ void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const fl
 }
 
 void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* dk, float2* data, const float* rho,
-                float* s_out, int model, float thr, float vx, float cn, float c5, hipStream_t s) {
+                float* s_out, int model, float thr, float vx, float vx0, float cn, float c5,
+                hipStream_t s) {
   switch (pl.n) {
-#define CASE(N_) case N_: screen_impl<N_>(pl, kind, op, dk, data, rho, s_out, model, thr, vx, cn, c5, s); return;
+#define CASE(N_) case N_: screen_impl<N_>(pl, kind, op, dk, data, rho, s_out, model, thr, vx, vx0, cn, c5, s); return;
     CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
     CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
 #undef CASE

@@ -143,7 +143,9 @@ StepScalars step_scalars(const cola_params& p, double a) {
     const double beta = 1.0 + 2.0 * p.rc_h0 * E * (1.0 - 0.5 * oma);
     s.beta = (float)beta;
     s.coupling = (float)(1.0 / (3.0 * beta));
-    s.vx_pref = (float)(8.0 * p.rc_h0 * p.rc_h0 * om / (9.0 * beta * beta * a * a * a));
+    const double a3 = (p.readings & COLA_READ_X_NO_A3) ? 1.0 : a * a * a;
+    s.vx_pref = (float)(8.0 * p.rc_h0 * p.rc_h0 * om / (9.0 * beta * beta * a3));
+    s.vx_off = (p.readings & COLA_READ_X_TOTAL_DENSITY) ? s.vx_pref : 0.f;
   }
   return s;
 }
@@ -180,6 +182,7 @@ void validate(const cola_params& p) {
   if (!fft_size_supported(p.np1d) || !fft_size_supported(p.nmesh1d)) bad("FFT size not supported");
   if (!(p.box > 0) || !(p.z_init > 0)) bad("box and z_init must be > 0");
   if (p.n_steps < 1 || p.n_steps > 4096) bad("n_steps must be in [1, 4096]");
+  if (p.readings & ~COLA_READ_ALL) bad("readings has unknown bits");
 }
 
 Layout make_layout(const cola_params& p) {

@@ -179,7 +179,10 @@ __device__ __forceinline__ void growth_model(const GrowthDev& g, double k, doubl
   }
 }
 
-// d y / d ln a for y = (D1, D1', D2, D2'), ' = d/dtau; d/dln a = (a^2 E)^-1 d/dtau
+// d y / d ln a for y = (D1, D1', D2, D2'), ' = d/dtau; d/dln a = (a^2 E)^-1 d/dtau.
+// HALF (the COLA_READ_D2_HALF_K reading): y also carries (D1, D1') at k/sqrt2, and the D2
+// source takes that D1 squared in place of D1(k)^2.
+template <bool HALF>
 __device__ __forceinline__ void growth_rhs(const GrowthDev& g, double k, double lna, const double* y,
                                            double* dy) {
   const double a = exp(lna);
@@ -187,25 +190,33 @@ __device__ __forceinline__ void growth_rhs(const GrowthDev& g, double k, double 
   growth_model(g, k, a, mu, g2t);
   const double kap = 1.5 * g.om * a;
   const double f = 1.0 / (a * a * dE(a, g.om));
+  const double ds = HALF ? y[4] : y[0];
   dy[0] = y[1] * f;
   dy[1] = kap * mu * y[0] * f;
   dy[2] = y[3] * f;
-  dy[3] = (kap * mu * y[2] - kap * mu * y[0] * y[0] - g2t * y[0] * y[0]) * f;
+  dy[3] = (kap * mu * y[2] - kap * mu * ds * ds - g2t * ds * ds) * f;
+  if constexpr (HALF) {
+    dy[4] = y[5] * f;
+    dy[5] = kap * growth_mu(g, k * M_SQRT1_2, a) * y[4] * f;
+  }
 }
 
-__device__ __forceinline__ void store_slice(const GrowthDev& g, double k, double a, const double y[4],
+template <bool HALF>
+__device__ __forceinline__ void store_slice(const GrowthDev& g, double k, double a, const double* y,
                                             double* out) {
   double mu, g2t;
   growth_model(g, k, a, mu, g2t);
   const double kap = 1.5 * g.om * a;
+  const double ds = HALF ? y[4] : y[0];
   out[0] = y[0];
   out[1] = y[1];
   out[2] = kap * mu * y[0];
   out[3] = y[2];
   out[4] = y[3];
-  out[5] = kap * mu * y[2] - kap * mu * y[0] * y[0] - g2t * y[0] * y[0];
+  out[5] = kap * mu * y[2] - kap * mu * ds * ds - g2t * ds * ds;
 }
 
+template <bool HALF>
 __global__ void __launch_bounds__(64) k_growth_ode(GrowthDev g, double* __restrict__ table, double* __restrict__ ref) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t > g.n_k) return;
@@ -219,18 +230,27 @@ __global__ void __launch_bounds__(64) k_growth_ode(GrowthDev g, double* __restri
   }
   const double ai = g.a_ini;
   const double g0 = ai * ai * dE(ai, g.om);
-  double y[4] = {1.0, g0, -3.0 / 7.0, -6.0 / 7.0 * g0};
+  constexpr int NV = HALF ? 6 : 4;
+  double y[NV];
+  y[0] = 1.0;
+  y[1] = g0;
+  y[2] = -3.0 / 7.0;
+  y[3] = -6.0 / 7.0 * g0;
+  if constexpr (HALF) {
+    y[4] = 1.0;
+    y[5] = g0;
+  }
   double lna = log(ai);
   const int nsl = (t == g.n_k) ? 1 : g.n_steps + 1;
   for (int i = 0; i < nsl; ++i) {
     const double a_target = (t == g.n_k) ? 1.0 : ai + i * (1.0 - ai) / g.n_steps;
     const double l1 = log(a_target);
-    rk4_to<4>(y, lna, l1, growth_kink(gg),
-              [&](double l, const double* yy, double* dy) { growth_rhs(gg, k, l, yy, dy); });
+    rk4_to<NV>(y, lna, l1, growth_kink(gg),
+               [&](double l, const double* yy, double* dy) { growth_rhs<HALF>(gg, k, l, yy, dy); });
     if (t == g.n_k)
-      store_slice(gg, k, a_target, y, ref);
+      store_slice<HALF>(gg, k, a_target, y, ref);
     else
-      store_slice(gg, k, a_target, y, table + ((int64_t)i * g.n_k + t) * 6);
+      store_slice<HALF>(gg, k, a_target, y, table + ((int64_t)i * g.n_k + t) * 6);
   }
 }
 
@@ -251,8 +271,12 @@ void launch_growth_ode(const cola_params& p, const Layout& L, double* table, dou
   g.n_steps = p.n_steps;
   g.n_k = L.n_k;
   const int64_t threads = L.n_k + 1;
-  hipLaunchKernelGGL(k_growth_ode, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, s, g, table,
-                     ref);
+  if (p.readings & COLA_READ_D2_HALF_K)
+    hipLaunchKernelGGL(k_growth_ode<true>, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, s, g,
+                       table, ref);
+  else
+    hipLaunchKernelGGL(k_growth_ode<false>, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, s, g,
+                       table, ref);
   COLA_LAUNCH_CHECK();
 }
 

@@ -99,7 +99,9 @@ struct StepScalars {         // PM-force scalars at scale factor a
   float kappa, a2m2, coupling;
   float cham_thr;   // potential screening threshold on |Phi_code|: Phi_crit(a) a^2/(H0/c)^2,
                     // Phi_crit = (3/2)|f_R(a)| for f(R), the App. C integral for the symmetron
-  float vx_pref;    // nDGP: x = vx_pref (1 + delta_R), 8 (rc H0)^2 Om / (9 beta^2 a^3)
+  float vx_pref;    // nDGP: x = vx_pref max(-1, delta_R) + vx_off,
+                    // vx_pref = 8 (rc H0)^2 Om / (9 beta^2 a^3) (a^3 -> 1 under READ_X_NO_A3)
+  float vx_off;     // 0, or vx_pref under COLA_READ_X_TOTAL_DENSITY (x from 1 + delta_R)
   float beta;
   int fifth, screen;  // fifth force on, screening on
 };
@@ -173,8 +175,8 @@ void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const fl
 // Newtonian and fifth-force sources into one field with one Green's function 1/k^2.
 // s_out (optional, padded real) receives S = delta eps.
 void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* dk, float2* data,
-                const float* rho, float* s_out, int model, float thr, float vx, float cn,
-                float c5, hipStream_t s);
+                const float* rho, float* s_out, int model, float thr, float vx, float vx0,
+                float cn, float c5, hipStream_t s);
 
 // ------------------------------------------------------------------ kernels (launchers)
 void launch_fill(float* p, size_t n, float v, hipStream_t s);

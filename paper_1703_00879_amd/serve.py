@@ -164,12 +164,16 @@ class Server:
                         rid=run.req.rid, arrival=run.req.arrival, admitted=run.admitted,
                         finished=eng.finish_time(run.last), particle_steps=p.np1d ** 3 * p.n_steps,
                         state=eng.release(run.handle, self.keep))
-                    used -= run.footprint
+                    if not self.keep:   # a kept state stays resident and keeps its footprint
+                        used -= run.footprint
                     progressed = True
                 else:
                     still.append(run)
             active = still
             if not progressed:
+                if not active and pending and used + fps[pending[0]] > self.budget:
+                    raise RuntimeError("the HBM budget is held by kept states: request "
+                                       f"{requests[pending[0]].rid} can never be admitted")
                 if active:
                     eng.idle(50e-6)   # every admitted run has `depth` steps in flight
                 elif pending:

@@ -68,11 +68,12 @@ def test_white_noise_integer_stream_and_gaussians():
     assert np.max(np.abs(g - ref) / np.maximum(1.0, np.abs(ref))) < 2e-5
 
 
-@pytest.mark.parametrize("model,growth_mode", [(C.LCDM, 0), (C.FR_HS1, 0), (C.NDGP, 0),
-                                               (C.FR_HS1, 1), (C.SYMMETRON, 0)])
-def test_growth_tables_fp64(model, growth_mode):
+@pytest.mark.parametrize("model,growth_mode,readings", [
+    (C.LCDM, 0, 0), (C.FR_HS1, 0, 0), (C.NDGP, 0, 0), (C.FR_HS1, 1, 0), (C.SYMMETRON, 0, 0),
+    (C.FR_HS1, 0, C.READ_D2_HALF_K), (C.SYMMETRON, 0, C.READ_D2_HALF_K)])
+def test_growth_tables_fp64(model, growth_mode, readings):
     p = C.Params(model=model, growth_mode=growth_mode, np1d=16, nmesh1d=32, box=100.0,
-                 n_steps=5)
+                 n_steps=5, readings=readings)
     st = prepared(p)
     op = to_oracle(p)
     a_grid = time_grid(op)[0]
@@ -98,6 +99,11 @@ PM_CASES = {
     "ndgp_sharpk": dict(model=C.NDGP, rc_h0=2.0, filter=2, r_smooth=1.7, np1d=16, nmesh1d=32,
                         box=40.0, a=1.0, rms=1.0, clustered=True),
     "ndgp_unscreened": dict(model=C.NDGP, screening=0, np1d=16, nmesh1d=32, box=64.0, a=0.4, rms=1.0),
+    "ndgp_printed_x": dict(model=C.NDGP, rc_h0=2.0, np1d=32, nmesh1d=64, box=64.0, a=0.6, rms=2.0,
+                           clustered=True,
+                           readings=C.READ_X_TOTAL_DENSITY | C.READ_X_NO_A3),
+    "ndgp_x_total_density": dict(model=C.NDGP, rc_h0=1.0, np1d=16, nmesh1d=32, box=40.0, a=0.3,
+                                 rms=1.0, clustered=True, readings=C.READ_X_TOTAL_DENSITY),
     "radix3_24_48": dict(model=C.NDGP, np1d=24, nmesh1d=48, box=96.0, a=0.8, rms=2.0, clustered=True),
     "ragged_12_24": dict(model=C.FR_HS1, fr0_abs=1e-7, np1d=12, nmesh1d=24, box=48.0, a=0.6, rms=1.0),
     "ratio1_32_32": dict(model=C.LCDM, np1d=32, nmesh1d=32, box=100.0, a=1.0, rms=1.0),
@@ -251,6 +257,9 @@ def test_step_order_and_state_errors():
     st = C.State(p)
     with pytest.raises(C.ColaError) as e:
         C.cola_step(p, st, 0)
+    assert e.value.status == -3
+    with pytest.raises(C.ColaError) as e:   # P(k) needs the twiddles of a prepared state
+        C.cola_power_spectrum(p, st)
     assert e.value.status == -3
     C.cola_make_ic(p, st)
     with pytest.raises(C.ColaError) as e:

@@ -140,3 +140,15 @@ def test_percentile_and_summary():
     assert s["runs"] == 5
     assert s["runs_per_hour"] == pytest.approx(3600 * 5 / s["span_s"])
     assert s["p99_s"] >= s["p50_s"] > 0
+
+
+def test_kept_states_hold_their_footprint():
+    # a finished run whose state is kept stays resident: its footprint counts against the
+    # budget, so admission never overcommits, and a request that can never fit is an error
+    reqs = [_req(64, 2, s, 0.0) for s in range(3)]
+    eng = FakeEngine(n_streams=2)
+    fp = 64 ** 3 * 100
+    res = Server(eng, 3 * fp, max_active=3, keep_states=True).run(reqs)
+    assert len(res) == 3
+    with pytest.raises(RuntimeError):
+        Server(FakeEngine(n_streams=2), 2 * fp, max_active=3, keep_states=True).run(reqs)
