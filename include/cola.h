@@ -158,6 +158,21 @@ cola_status cola_pm_force(const cola_params* p, cola_state* st, double a,
  * increments it. */
 cola_status cola_step(const cola_params* p, cola_state* st, int32_t i, hipStream_t stream);
 
+/* Size of the library's own scratch array: the largest work area cola_step_static runs
+ * (cola_sizes.work_bytes; e.g. 64^3 particles on a 128^3 mesh). */
+#define COLA_STATIC_WORK_BYTES ((size_t)128 << 20)
+
+/* cola_step without a work buffer, for callers that cannot allocate device memory
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc).
+ * Same step, same kernels and the same results as cola_step; st->work is ignored and may
+ * be NULL: the meshes and bins live in a scratch array of COLA_STATIC_WORK_BYTES that the
+ * library holds on every device it runs on until the process ends.  The call allocates
+ * nothing.  A run whose work_bytes exceed COLA_STATIC_WORK_BYTES gets COLA_E_SIZE before
+ * any launch.  All calls on one device share its array, so calls that overlap on one
+ * device (different streams, or host threads) race: serialise them.  The initial
+ * conditions still need cola_make_ic with a work buffer, which may be shared by runs. */
+cola_status cola_step_static(const cola_params* p, cola_state* st, int32_t i, hipStream_t stream);
+
 /* Shell-averaged power spectrum of the current particles (the P(k) output of Sec. 8):
  * CIC on the PM mesh, FFT, P_b = < L^3 |delta_k|^2 / (M^2 W_CIC^2) > over shells
  * b = floor(|nu| + 1/2), modes weighted 2 for 0 < nu_z < n/2.  Host outputs k_out,

@@ -10,7 +10,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIBDIR = os.path.join(PKG, "_lib")
 LIB = os.path.join(LIBDIR, "libcola.so")
-SOURCES = ["fft.hip", "pm.hip", "ic.hip", "host.cpp", "api.cpp"]
+SOURCES = ["fft.hip", "pm.hip", "ic.hip", "noalloc.hip", "host.cpp", "api.cpp"]
 ARCH = os.environ.get("COLA_OFFLOAD_ARCH", "gfx950")
 
 

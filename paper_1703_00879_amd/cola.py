@@ -21,7 +21,7 @@ SMOOTH_GAUSS, SMOOTH_TOPHAT, SMOOTH_SHARPK = 0, 1, 2
 READ_X_TOTAL_DENSITY, READ_X_NO_A3, READ_D2_HALF_K = 1, 2, 4
 
 EXPORTED = ["cola_query_sizes", "cola_validate", "cola_prepare", "cola_make_ic", "cola_pm_force",
-            "cola_step", "cola_power_spectrum", "cola_positions", "cola_growth_table",
+            "cola_step", "cola_step_static", "cola_power_spectrum", "cola_positions", "cola_growth_table",
             "cola_white_noise", "cola_growth_triangles", "cola_profile_enable", "cola_profile_read",
             "cola_profile_reset",
             "cola_status_string", "cola_last_error"]
@@ -109,7 +109,7 @@ def load_library(path=LIB_PATH):
     sig = {
         "cola_query_sizes": [P, S], "cola_validate": [P], "cola_prepare": [P, St, vp],
         "cola_make_ic": [P, St, vp], "cola_pm_force": [P, St, d, vp, vp, vp],
-        "cola_step": [P, St, i32, vp],
+        "cola_step": [P, St, i32, vp], "cola_step_static": [P, St, i32, vp],
         "cola_power_spectrum": [P, St, i32, vp, vp, vp, vp],
         "cola_positions": [P, St, vp, vp],
         "cola_growth_table": [P, St, i32, vp, i64, vp, vp],
@@ -203,6 +203,11 @@ def cola_pm_force(p, state, a, force_out=None, mesh_out=None, stream=None):
 def cola_step(p, state, i, stream=None):
     _check(load_library().cola_step(ctypes.byref(p._c()), ctypes.byref(state.c), int(i),
                                     _stream(stream)))
+
+
+def cola_step_static(p, state, i, stream=None):
+    _check(load_library().cola_step_static(ctypes.byref(p._c()), ctypes.byref(state.c), int(i),
+                                           _stream(stream)))
 
 
 def cola_power_spectrum(p, state, nbins=None, stream=None):

@@ -464,6 +464,14 @@ cola_status cola_step(const cola_params* p, cola_state* st, int32_t i, hipStream
   return guarded([&] { step_impl(p, st, i, nullptr, s); });
 }
 
+cola_status cola_step_static(const cola_params* p, cola_state* st, int32_t i, hipStream_t s) {
+  return guarded([&] {
+    if (!p) throw Error{COLA_E_ARG, "params is NULL"};
+    const Layout L = make_layout(*p);
+    step_impl(p, st, i, static_work(L.work_bytes), s);
+  });
+}
+
 cola_status cola_power_spectrum(const cola_params* p, cola_state* st, int32_t nbins, double* k_out,
                                 double* p_out, int64_t* nmodes_out, hipStream_t s) {
   return guarded([&] {

@@ -86,6 +86,15 @@ struct Layout {
 Layout make_layout(const cola_params& p);
 void validate(const cola_params& p);   // throws Error{COLA_E_ARG}
 
+// ------------------------------------------------------------------ static scratch
+// Size of the library's scratch array (the work area of cola_step_static) and the number
+// of devices it keeps addresses for.
+constexpr size_t kStaticWorkBytes = COLA_STATIC_WORK_BYTES;
+constexpr int kMaxDevices = 64;
+// Device address of this device's scratch array (looked up once per device); throws
+// Error{COLA_E_SIZE} when `need` exceeds it.
+void* static_work(size_t need);
+
 // ------------------------------------------------------------------ host physics (FP64)
 struct Cosmo {
   double om, ol;
