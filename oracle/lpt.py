@@ -18,6 +18,8 @@ Potentials (Sec. 3):
 
 import numpy as np
 
+from . import fftlib
+
 from .rng import white_noise
 
 
@@ -84,7 +86,7 @@ def delta_k_from_noise(w, p, spec):
     power spectrum P sampled at N points."""
     n = p.np1d
     N = n ** 3
-    Wk = np.fft.rfftn(w)
+    Wk = fftlib.rfftn(w)
     (kx, ky, kz), _ = kvec(n, p.box)
     k = np.sqrt(kx * kx + ky * ky + kz * kz)
     amp = np.zeros(k.shape)
@@ -103,19 +105,19 @@ def twolpt_source(phi1_k, n, L):
     d = {}
     for i in range(3):
         for j in range(i, 3):
-            d[i, j] = np.fft.irfftn(phi1_k * hessian_factor(n, L, i, j), s=(n, n, n), axes=(0, 1, 2))
+            d[i, j] = fftlib.irfftn(phi1_k * hessian_factor(n, L, i, j), n)
     return (d[0, 0] * d[1, 1] + d[0, 0] * d[2, 2] + d[1, 1] * d[2, 2]
             - d[0, 1] ** 2 - d[0, 2] ** 2 - d[1, 2] ** 2)
 
 
 def phi2_from_phi1(phi1_k, n, L):
     S = twolpt_source(phi1_k, n, L)
-    return -np.fft.rfftn(S) * inv_laplacian(n, L)
+    return -fftlib.rfftn(S) * inv_laplacian(n, L)
 
 
 def displacement(phi_k, n, L):
     """Psi = grad_q phi, returned as (3, n, n, n) real arrays."""
-    return np.stack([np.fft.irfftn(phi_k * grad_factor(n, L, ax), s=(n, n, n), axes=(0, 1, 2))
+    return np.stack([fftlib.irfftn(phi_k * grad_factor(n, L, ax), n)
                      for ax in range(3)])
 
 
@@ -125,6 +127,35 @@ def lpt_field_scale_dependent(phi1_k, phi2_k, X1, X2, n, L, n2_index):
     n2 = n2_grid(n)
     c = X1[n2_index(n2)] * phi1_k + X2[n2_index(n2)] * phi2_k
     return displacement(c, n, L)
+
+
+def lpt_field_sparse(modes, n, L, planes):
+    """IDFT[i k (X1 phi1_k + X2 phi2_k)] of a field whose half-complex coefficients are zero
+    except at the listed modes, by direct summation at the grid points of the x-planes
+    `planes` (App. A's transform, evaluated mode by mode).
+
+    modes: ((nu_x, nu_y, nu_z), c) with c = X1 phi1_k + X2 phi2_k at that mode,
+    nu_x, nu_y in [-n/2, n/2 - 1] and 0 < nu_z < n/2, so each stored mode and its implicit
+    conjugate partner at -nu give (1/N) (c e^{i k.q} + conj) = (2/N) Re(c e^{i k.q});
+    i k_c is zero on the axis-c Nyquist plane (nu_c = -n/2).  q = L i / n at grid index i.
+    Returns (3, len(planes), n, n)."""
+    planes = np.asarray(planes)
+    N = n ** 3
+    out = np.zeros((3, planes.size, n, n))
+    idx = np.arange(n)
+    for (nu, c) in modes:
+        nu = np.asarray(nu, dtype=np.int64)
+        assert 0 < nu[2] < n // 2 and all(-n // 2 <= v < n // 2 for v in nu[:2])
+        ex = np.exp(2j * np.pi * nu[0] * planes / n)
+        ey = np.exp(2j * np.pi * nu[1] * idx / n)
+        ez = np.exp(2j * np.pi * nu[2] * idx / n)
+        ph = ex[:, None, None] * ey[None, :, None] * ez[None, None, :]
+        for ax in range(3):
+            if nu[ax] == -n // 2:
+                continue
+            k = 2.0 * np.pi * nu[ax] / L
+            out[ax] += (2.0 / N) * np.real(1j * k * c * ph)
+    return out
 
 
 def initial_fields(p, spec, noise=None):

@@ -12,6 +12,8 @@ Shot noise is not subtracted.  Bins 0 .. nbins-1.
 
 import numpy as np
 
+from . import fftlib
+
 from .lpt import kvec
 from .pm import density_contrast
 
@@ -28,7 +30,7 @@ def shell_index(n2):
 def power_spectrum_mesh(delta, L, nbins):
     n = delta.shape[0]
     M = n ** 3
-    dk = np.fft.rfftn(delta)
+    dk = fftlib.rfftn(delta)
     (kx, ky, kz), (nx, ny, nz) = kvec(n, L)
     n2 = np.broadcast_to(nx * nx + ny * ny + nz * nz, dk.shape)
     kmag = np.sqrt(np.broadcast_to(kx * kx + ky * ky + kz * kz, dk.shape))

@@ -21,6 +21,8 @@ Steps, in the paper's order:
 
 import numpy as np
 
+from . import fftlib
+
 from .background import kappa
 from .lpt import grad_factor, inv_laplacian, kvec
 from .models import (Model, eps_chameleon, eps_potential, eps_vainshtein, vainshtein_x, window,
@@ -96,7 +98,7 @@ def screened_source(delta, delta_k, p, a, model):
     if not p.screening or not model.has_fifth_force:
         return delta.copy()
     if p.model in (MODEL_FR, MODEL_SYMMETRON):
-        Phi = np.fft.irfftn(-kappa(a, p.omega_m) * delta_k * inv_laplacian(n, L), s=(n, n, n), axes=(0, 1, 2))
+        Phi = fftlib.irfftn(-kappa(a, p.omega_m) * delta_k * inv_laplacian(n, L), n)
         phi_n = Phi * H0_OVER_C ** 2 / (a * a)
         if p.model == MODEL_FR:
             eps = eps_chameleon(phi_n, fr_fR_abs(a, p.omega_m, p.fr0_abs))
@@ -105,7 +107,7 @@ def screened_source(delta, delta_k, p, a, model):
     elif p.model == MODEL_NDGP:
         (kx, ky, kz), _ = kvec(n, L)
         k = np.sqrt(kx * kx + ky * ky + kz * kz)
-        dR = np.fft.irfftn(delta_k * window(k * p.r_smooth, p.filter), s=(n, n, n), axes=(0, 1, 2))
+        dR = fftlib.irfftn(delta_k * window(k * p.r_smooth, p.filter), n)
         beta = dgp_beta(a, p.omega_m, p.rc_h0)
         eps = eps_vainshtein(vainshtein_x(dR, a, p.omega_m, p.rc_h0, beta, p.readings))
     else:
@@ -118,14 +120,14 @@ def force_mesh(delta, p, a, model=None):
     plus the screened source S."""
     model = model or Model(p)
     n, L = p.nmesh1d, p.box
-    dk = np.fft.rfftn(delta)
+    dk = fftlib.rfftn(delta)
     inv_k2 = inv_laplacian(n, L)
     kap = kappa(a, p.omega_m)
     tot_k = -kap * dk * inv_k2
     S = delta
     if model.has_fifth_force:
         S = screened_source(delta, dk, p, a, model)
-        Sk = np.fft.rfftn(S)
+        Sk = fftlib.rfftn(S)
         (kx, ky, kz), _ = kvec(n, L)
         k2 = kx * kx + ky * ky + kz * kz
         den = k2 + model.a2m2(a)
@@ -133,7 +135,7 @@ def force_mesh(delta, p, a, model=None):
         nz = k2 > 0
         g5[nz] = -model.coupling(a) * kap / den[nz]
         tot_k = tot_k + g5 * Sk
-    F = np.stack([np.fft.irfftn(-grad_factor(n, L, ax) * tot_k, s=(n, n, n), axes=(0, 1, 2))
+    F = np.stack([fftlib.irfftn(-grad_factor(n, L, ax) * tot_k, n)
                   for ax in range(3)])
     return F, S
 

@@ -125,3 +125,28 @@ def test_2lpt_two_orthogonal_waves_closed_form():
     psi1 = displacement(phi1, n, L)
     want1 = np.stack([-A1 / k1 * np.sin(k1 * X), -A2 / k2 * np.sin(k2 * Y), np.zeros_like(X)])
     assert np.allclose(psi1, want1, atol=1e-12 * np.abs(want1).max())
+
+
+def test_sparse_lpt_field_equals_the_transform():
+    # direct summation over a few stored modes equals the FFT synthesis of the same
+    # half-complex fields (App. A), Nyquist modes included
+    from oracle.lpt import lpt_field_sparse, lpt_field_scale_dependent
+    n, L = 16, 40.0
+    rng = np.random.default_rng(5)
+    modes = [((3, -5, 2), None), ((-8, 2, 5), None), ((7, -8, 7), None), ((0, 1, 1), None)]
+    phi1 = np.zeros((n, n, n // 2 + 1), complex)
+    phi2 = np.zeros_like(phi1)
+    sparse = []
+    X1 = rng.uniform(0.5, 2.0, 3 * (n // 2) ** 2 + 1)
+    X2 = rng.uniform(-1.0, 0.0, X1.size)
+    for nu, _ in modes:
+        a, b = rng.standard_normal(2) + 1j * rng.standard_normal(2)
+        phi1[nu[0] % n, nu[1] % n, nu[2]] = a
+        phi2[nu[0] % n, nu[1] % n, nu[2]] = b
+        n2 = nu[0] ** 2 + nu[1] ** 2 + nu[2] ** 2
+        sparse.append((nu, X1[n2] * a + X2[n2] * b))
+    ref = lpt_field_scale_dependent(phi1, phi2, X1, X2, n, L, lambda n2: n2)
+    planes = np.arange(n)
+    got = lpt_field_sparse(sparse, n, L, planes)
+    assert np.max(np.abs(got - ref)) < 1e-13 * np.max(np.abs(ref))
+    assert np.abs(ref).max() > 0
