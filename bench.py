@@ -1,20 +1,27 @@
 """Benchmark of the COLA particle-mesh step on one MI355X.
 
-Workload: nDGP with r_c H0 = 1 and Vainshtein screening (Gaussian smoothing R = 1 Mpc/h),
-Np = 512^3 particles, Nmesh = 1024^3, L = 1024 Mpc/h, seeded Gaussian initial conditions
-(Eisenstein-Hu no-wiggle spectrum, Om = 0.3, h = 0.7, ns = 0.96, sigma8 = 0.8), 2LPT at
-z = 19, 30 COLA steps to z = 0.
+Workload (the headline): Hu-Sawicki f(R), n = 1, |f_R0| = 1e-5, chameleon screening, with
+its own scale-dependent growth factors D1(k,a), D2(k,a) (the LPT terms are rebuilt every
+step by inverse FFTs on the particle grid, App. A); Np = 1024^3 particles stored as FP32
+Lagrangian displacements, Nmesh = 2048^3 FP32 mesh, L = 2048 Mpc/h; seeded Gaussian
+initial conditions (Eisenstein-Hu no-wiggle spectrum, Om = 0.3, h = 0.7, ns = 0.96,
+sigma8 = 0.8), 2LPT at z = 19, 20 COLA steps to z = 0.  FP64 only in the growth tables and
+the step coefficients.
 
-A step is one cola_step: CIC deposit, forward FFT, smoothed-density screening (inverse
-FFT, real-space factor, forward FFT), the fused Green's-function / fifth-force / gradient
-inverse FFTs, and the CIC gather fused with the kick and drift.  The initial conditions
-(growth tables + 2LPT) run before the timed region; the power spectrum after it.
+A step is one cola_step: the per-step LPT synthesis (six particle-grid inverse FFTs), CIC
+deposit, forward FFT, potential screening (inverse FFT of the Newtonian potential, the
+real-space factor, forward FFT of S), the fused Green's-function / fifth-force / gradient
+inverse FFTs, and the CIC gather fused with the kick and drift.  Warm-up steps run from
+their own initial conditions; the K timed steps start from new ones, so the default
+K = 20 times one whole run to z = 0 (initial conditions, made before each run, are never
+inside a timed interval).
 
 Prints one JSON line.  `value` is particle-steps per second over exactly K timed steps
 (bracketed by device synchronisation); `roofline` reports the kernel with the largest
 share of the step against the MI355X HBM peak, timed with HIP events on its launch
 stream; `cpu_baseline` times the FP64 oracle on host cores on a bounded sample of the
-same workload.
+same workload.  A secondary block repeats the measurement for nDGP (r_c H0 = 1,
+Vainshtein screening) with 512^3 particles on a 1024^3 mesh in L = 1024 Mpc/h, 30 steps.
 """
 
 import argparse
@@ -31,18 +38,32 @@ HBM_PEAK_GBS = 8000.0
 METRIC = "PM particle-steps/s + % HBM peak; mock runs/hour and p99 time-to-z=0"
 
 
+WORKLOAD = ("f(R) Hu-Sawicki n=1 |fR0|=1e-5 chameleon-screened, scale-dependent D1(k,a), "
+            "D2(k,a) (LPT terms rebuilt by particle-grid FFTs every step), Np=1024^3 FP32 "
+            "Lagrangian displacements, Nmesh=2048^3 FP32, L=2048 Mpc/h, 2LPT at z=19, 20 COLA steps")
+SECONDARY = ("nDGP rcH0=1 Vainshtein-screened (Gaussian R=1 Mpc/h), Np=512^3, Nmesh=1024^3, "
+             "L=1024 Mpc/h, 2LPT at z=19, 30 COLA steps")
+
+
 def workload_params(C):
+    return C.Params(model=C.FR_HS1, fr0_abs=1e-5, screening=1, growth_mode=0,
+                    np1d=1024, nmesh1d=2048, box=2048.0, z_init=19.0, n_steps=20, seed=1)
+
+
+def secondary_params(C):
     return C.Params(model=C.NDGP, rc_h0=1.0, screening=1, filter=0, r_smooth=1.0,
                     np1d=512, nmesh1d=1024, box=1024.0, z_init=19.0, n_steps=30, seed=1)
 
 
 def algorithmic_bytes(name, p):
     """Bytes a kernel must move per launch (single-precision fields, unpadded):
-    mesh M = n^3 real cells, half-complex H = n^2 (n/2 + 1) complex values, N particles."""
+    mesh M = n^3 real cells, half-complex H = n^2 (n/2 + 1) complex values, N particles,
+    and on the particle grid (the LPT transforms) Hp = np^2 (np/2 + 1)."""
     n = p.nmesh1d
     M = n ** 3
     H = n * n * (n // 2 + 1)
     N = p.np1d ** 3
+    Hp = p.np1d ** 2 * (p.np1d // 2 + 1)
     table = {
         "bin_count": 12 * N,                         # read u; tile counts are negligible
         "bin_scan": 0,
@@ -53,33 +74,29 @@ def algorithmic_bytes(name, p):
         "fft_y_fwd": 16 * H, "fft_x_fwd": 16 * H, "fft_y_inv": 16 * H,
         "fft_x_fwd_smooth": 8 * H + 8 * H,           # read delta; write X^-1[W delta_k]
         "fft_x_fwd_pot": 8 * H + 16 * H,             # read delta; write delta_k and X^-1[Phi_k]
-        "fft_z_screen": 8 * H + 4 * M + 8 * H,       # read delta_R and rho, write S
+        "fft_z_screen": 8 * H + 4 * M + 8 * H,       # read the filtered field and rho, write S
         "fft_x_fwd_force": 16 * H + 16 * H,          # read S and delta_k; write G0 and G
         "fft_x_fwd_force_1src": 8 * H + 16 * H,      # read one combined source; write G0 and G
         "fft_y_inv_yz": 8 * H + 16 * H,              # read G; write the y and z components
         "fft_c2r_z3": 24 * H + 12 * M,               # read 3 force passes, write (Fx, Fy, Fz)
-        "gather_kick_drift": 12 * M + 72 * N,        # force mesh; u, v, Psi1, Psi2 in; u, v out
+        "gather_kick_drift": 12 * M + 72 * N,        # force mesh; u, v and the LPT terms in; u, v out
+        "fft_x_inv_lpt": 16 * Hp + 8 * Hp,           # read phi1_k, phi2_k; write one component
+        "lpt_fft_y_inv": 16 * Hp,
+        "lpt_fft_c2r_z": 8 * Hp + 4 * N,             # write one real particle-grid field
         "fill": 0,
     }
     return table.get(name)
 
 
-def yardstick_bytes_per_step(p):
-    """Algorithmic bytes of one screened, scale-independent step: deposit (12N + 4M),
-    a forward R2C (16M), screening (C2R of W delta_k, the real-space factor and the R2C
-    of S: 52M), the fused Green's function (20M), three force C2Rs (48M) and the
-    gather with kick and drift (12M + 72N); 152M + 84N in total, counting each 3D FFT
-    as one read and one write of a real-sized mesh per pair of passes."""
-    n = p.nmesh1d
-    M = n ** 3
-    N = p.np1d ** 3
-    return 152 * M + 84 * N
-
-
 def yardstick_bytes_for(p, C):
-    """Yardstick bytes of one step of any run: LCDM 96M + 84N; screened modified gravity
-    with scale-independent LPT (nDGP, f(R) with LCDM growth) 152M + 84N; with the per-step
-    LPT synthesis of scale-dependent growth (f(R), symmetron) 152M + 212N."""
+    """Algorithmic bytes of one step, counting each 3D FFT as one read and one write of a
+    real-sized mesh per pair of passes.  Deposit 12N + 4M, forward R2C 16M, screening
+    (C2R of the filtered field, the real-space factor, R2C of S) 52M, the Green's function
+    16M (LCDM) or 20M, three force C2Rs 48M, gather with kick and drift 12M + 72N, and for
+    scale-dependent growth the LPT synthesis 128N (read phi1_k, phi2_k; six particle-grid
+    C2Rs; the six fields read by the gather).  LCDM 96M + 84N; screened modified gravity
+    with scale-independent LPT (nDGP, f(R) with LCDM growth) 152M + 84N; with
+    scale-dependent growth (f(R), symmetron) 152M + 212N."""
     M, N = p.nmesh1d ** 3, p.np1d ** 3
     if p.model == C.LCDM:
         return 96 * M + 84 * N
@@ -158,10 +175,14 @@ def source_hash():
     return h.hexdigest()[:16]
 
 
+TRAFFIC_FILE = "traffic_fr5_1024_2048.json"
+PROFILE_FILE = "pm_step_fr5_1024_2048.md"
+
+
 def traffic_for(kernel):
     """HBM bytes per launch of `kernel` from the committed counter summary, or None if
     the summary is missing or was taken on different kernel sources."""
-    path = os.path.join(ROOT, "profiles", "traffic_ndgp_512_1024.json")
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
     try:
         d = json.load(open(path))
     except (OSError, ValueError):
@@ -173,42 +194,66 @@ def traffic_for(kernel):
 
 
 # rocprofv3 kernel symbols of one step -> the names the library's HIP-event profiler uses
+# ({n}: mesh size; {np}: particle-grid size; {nph} = np/2, the complex row length of the
+# particle grid's real transforms); the first pattern that matches wins
 _SYMBOLS = [("k_fft_col_fwd_force<{n}, true>", "fft_x_fwd_force"),
             ("k_fft_col_fwd_force<{n}, false>", "fft_x_fwd_force_1src"),
             ("k_fft_col_inv_yz", "fft_y_inv_yz"), ("k_fft_col_fwd_op<{n}, 3,", "fft_x_fwd_smooth"),
-            ("k_fft_col_fwd_op<{n}, 2,", "fft_x_fwd_pot"), ("k_fft_col<{n}, -1, 0, 16>", "fft_y_fwd"),
-            ("k_fft_col<{n}, 1, 0, 16>", "fft_y_inv"), ("k_fft_c2r_row3", "fft_c2r_z3"),
+            ("k_fft_col_fwd_op<{n}, 2,", "fft_x_fwd_pot"), ("k_fft_col<{n}, -1, 0,", "fft_y_fwd"),
+            ("k_fft_col<{n}, 1, 0,", "fft_y_inv"), ("k_fft_col<{np}, 1, 4,", "fft_x_inv_lpt"),
+            ("k_fft_col<{np}, 1, 0,", "lpt_fft_y_inv"), ("k_fft_c2r_row3", "fft_c2r_z3"),
+            ("k_fft_c2r_row<{nph}>", "lpt_fft_c2r_z"),
             ("k_fft_screen_row", "fft_z_screen"), ("k_fft_r2c_row", "fft_r2c_z"),
             ("k_gather", "gather_kick_drift"), ("k_deposit_tiles", "deposit"), ("k_bin<0,", "bin_count"),
             ("k_bin<1,", "bin_scatter"), ("k_scan_", "bin_scan"), ("k_fill", "fill")]
 
 
-def _profile_name(symbol, n):
+def _profile_name(symbol, n, np_=None):
+    np_ = np_ or n // 2
     for pat, name in _SYMBOLS:
-        if pat.format(n=n) in symbol:
+        if pat.format(n=n, np=np_, nph=np_ // 2) in symbol:
             return name
     return symbol.split("(")[0].replace("void ", "")
 
 
-def summarize_rocprof(d, out_dir):
-    """Condense the rocprofv3 runs of `python3 bench.py --steps 2 --warmup 1 --no-profile`
-    under directory d (trace/, fetch/, write/: kernel trace and FETCH_SIZE / WRITE_SIZE
-    counters; cfetch/, cwrite/: the same counters for `bench.py --calibrate-copy`) into
-    per-kernel figures of the two timed steps, written to out_dir as a markdown table and
-    the traffic file bench.py reads."""
+def profile_command(steps, warmup):
+    """The rocprofv3 runs whose summary summarize_rocprof condenses (D = output directory,
+    REPO = repository root): a kernel trace and the FETCH_SIZE and WRITE_SIZE counters of
+    the bench's own timed steps, and the same counters for a plain 1 GiB device copy."""
+    b = (f"python3 $REPO/bench.py --steps {steps} --warmup {warmup} --headline-only "
+         "--no-profile")
+    c = "python3 $REPO/bench.py --calibrate-copy"
+    return "; ".join([
+        "cd /tmp && export TMPDIR=/tmp",
+        f"rocprofv3 --kernel-trace --stats --output-format csv -d $D/trace -o trace -- {b}",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d $D/fetch -o fetch -- {b}",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d $D/write -o write -- {b}",
+        f"rocprofv3 --pmc FETCH_SIZE --output-format csv -d $D/cfetch -o cfetch -- {c}",
+        f"rocprofv3 --pmc WRITE_SIZE --output-format csv -d $D/cwrite -o cwrite -- {c}",
+        f"python3 $REPO/bench.py --summarize-rocprof $D --steps {steps} --warmup {warmup}"])
+
+
+def summarize_rocprof(d, out_dir, steps, warmup=0):
+    """Condense the rocprofv3 runs of profile_command(steps, warmup) under directory d
+    (trace/, fetch/, write/: kernel trace and FETCH_SIZE / WRITE_SIZE counters of the
+    headline run; cfetch/, cwrite/: the same counters for `bench.py --calibrate-copy`) into
+    per-kernel figures, written to out_dir as a markdown table and the traffic file bench.py
+    reads.  The gather ends every step, so the timed steps are the last `steps` gathers of
+    the trace; the summary covers the dispatches after the first of them up to the last,
+    i.e. timed steps 2..K (timed step 1 follows the initial conditions of its run)."""
     import csv
     from collections import defaultdict
     from paper_1703_00879_amd import cola as C
     p = workload_params(C)
-    n = p.nmesh1d
+    n, np_ = p.nmesh1d, p.np1d
 
     def rows(path):
         with open(path) as f:
             return list(csv.DictReader(f))
 
     def step_window(recs, key):
-        """Dispatch ids after the first gather (end of the warm-up step) up to the last."""
-        ids = sorted(int(r["Dispatch_Id"]) for r in recs if "k_gather" in r[key])
+        ids = sorted({int(r["Dispatch_Id"]) for r in recs if "k_gather" in r[key]})
+        ids = ids[-steps:]
         return ids[0], ids[-1], len(ids) - 1
 
     tr = rows(os.path.join(d, "trace", "trace_kernel_trace.csv"))
@@ -217,7 +262,7 @@ def summarize_rocprof(d, out_dir):
     for r in tr:
         i = int(r["Dispatch_Id"])
         if lo < i <= hi:
-            dur[_profile_name(r["Kernel_Name"], n)].append(
+            dur[_profile_name(r["Kernel_Name"], n, np_)].append(
                 (int(r["End_Timestamp"]) - int(r["Start_Timestamp"])) * 1e-6)
 
     def counter(sub, name):
@@ -226,7 +271,7 @@ def summarize_rocprof(d, out_dir):
         acc = defaultdict(list)
         for r in recs:
             if a < int(r["Dispatch_Id"]) <= b and r["Counter_Name"] == name:
-                acc[_profile_name(r["Kernel_Name"], n)].append(float(r["Counter_Value"]))
+                acc[_profile_name(r["Kernel_Name"], n, np_)].append(float(r["Counter_Value"]))
         return acc
 
     def copy_factor(sub, name):
@@ -247,25 +292,22 @@ def summarize_rocprof(d, out_dir):
                       "fetch_bytes_per_launch": fb, "write_bytes_per_launch": wb,
                       "bytes_per_launch": (fb + wb) if fb is not None and wb is not None else None,
                       "algorithmic_bytes_per_launch": algorithmic_bytes(name, p)}
-    cmd = ("cd /tmp && export TMPDIR=/tmp; B=\"python3 $REPO/bench.py --steps 2 --warmup 1 "
-           "--no-cpu-baseline --no-profile --no-models --no-serving\"; "
-           "rocprofv3 --kernel-trace --stats --output-format csv -d $D/trace -o trace -- $B; "
-           "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $D/fetch -o fetch -- $B; "
-           "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $D/write -o write -- $B; "
-           "rocprofv3 --pmc FETCH_SIZE --output-format csv -d $D/cfetch -o cfetch -- "
-           "python3 $REPO/bench.py --calibrate-copy; "
-           "rocprofv3 --pmc WRITE_SIZE --output-format csv -d $D/cwrite -o cwrite -- "
-           "python3 $REPO/bench.py --calibrate-copy; "
-           "python3 $REPO/bench.py --summarize-rocprof $D")
-    traffic = {"source_hash": source_hash(), "workload": "nDGP 512^3 particles, 1024^3 mesh",
+    cmd = profile_command(steps, warmup)
+    traffic = {"source_hash": source_hash(), "workload": WORKLOAD, "steps_covered": nsteps,
                "fetch_scale": kf, "write_scale": kw, "command": cmd, "kernels": kern}
     os.makedirs(out_dir, exist_ok=True)
-    with open(os.path.join(out_dir, "traffic_ndgp_512_1024.json"), "w") as f:
+    with open(os.path.join(out_dir, TRAFFIC_FILE), "w") as f:
         json.dump(traffic, f, indent=1)
     tot = sum(k["ms_per_step"] for k in kern.values())
-    lines = ["# PM step kernels, nDGP 512^3 particles / 1024^3 mesh (rocprofv3)", "",
-             f"Source hash {traffic['source_hash']}; {nsteps} timed steps after one warm-up step.",
-             "", "Command (from the repository root on the GPU host, D = output directory):", "",
+    yard = yardstick_bytes_for(p, C)
+    counted = sum(k["bytes_per_launch"] * k["launches_per_step"] for k in kern.values()
+                  if k["bytes_per_launch"] is not None)
+    lines = [f"# PM step kernels: {WORKLOAD} (rocprofv3)", "",
+             f"Source hash {traffic['source_hash']}; timed steps 2..{steps} of the bench's "
+             f"{steps}-step timed run ({nsteps} steps, after {warmup} warm-up steps on a run of "
+             "their own).", "",
+             "Command (from the repository root on the GPU host, D = output directory, "
+             "REPO = repository root):", "",
              "```", cmd.replace("; ", "\n"), "```", "",
              f"HBM bytes = FETCH_SIZE x {kf:.3f} + WRITE_SIZE x {kw:.3f} (KiB per dispatch), the "
              "factors that make the counters of a plain 1 GiB device copy read 1 GiB each.", "",
@@ -278,50 +320,51 @@ def summarize_rocprof(d, out_dir):
         lines.append(f"| {name} | {k['launches_per_step']:g} | {k['avg_ms']:.3f} | "
                      f"{k['ms_per_step']:.2f} | {100 * k['ms_per_step'] / tot:.1f} | {g(hb)} | {g(ab)} "
                      f"| {r(hb)} | {r(ab)} |")
-    lines += ["", f"Sum of kernel time per step: {tot:.2f} ms."]
-    with open(os.path.join(out_dir, "pm_step_ndgp_512_1024.md"), "w") as f:
+    lines += ["", f"Sum of kernel time per step: {tot:.2f} ms.",
+              f"Counted HBM bytes per step: {counted / 1e9:.1f} GB "
+              f"({counted / 1e9 / (tot / 1e3) / HBM_PEAK_GBS:.3f} of the 8 TB/s peak over the summed "
+              f"kernel time); yardstick {yard / 1e9:.1f} GB "
+              f"({yard / 1e9 / (tot / 1e3) / HBM_PEAK_GBS:.3f})."]
+    with open(os.path.join(out_dir, PROFILE_FILE), "w") as f:
         f.write("\n".join(lines) + "\n")
     return traffic
 
 
-def cpu_baseline(steps=8):
-    """The FP64 oracle on the host: the same workload (nDGP r_c H0 = 1, screened,
-    2 Mpc/h particle spacing, 1 Mpc/h cells, 30-step time grid, same seed) on a
-    128^3-particle / 256^3-mesh / 256 Mpc/h sub-box, timing `steps` COLA steps."""
-    import numpy as np  # noqa: F401
+def cpu_baseline(steps=2):
+    """The FP64 oracle on the host, on a bounded sample of the headline workload: F5 with
+    scale-dependent growth, screened, on a 128^3-particle / 256^3-mesh / 256 Mpc/h sub-box
+    (the workload's 2 Mpc/h particle spacing and 1 Mpc/h cells, its 20-step time grid and
+    seed), timing `steps` COLA steps after the 2LPT initial conditions: once with serial
+    transforms and once with the transforms on every host core.  The deposit and gather
+    (numpy bincount / fancy indexing) run on one thread either way."""
     import oracle
+    from oracle import fftlib
     from oracle.cola import Run
-    p = oracle.Params(model=oracle.MODEL_NDGP, rc_h0=1.0, screening=1, r_smooth=1.0,
-                      np1d=128, nmesh1d=256, box=256.0, z_init=19.0, n_steps=30, seed=1)
-    r = Run(p)
-    t = time.perf_counter()
-    for _ in range(steps):
-        r.step()
-    dt = time.perf_counter() - t
+    p = oracle.Params(model=oracle.MODEL_FR, fr0_abs=1e-5, screening=1, growth_mode=0,
+                      np1d=128, nmesh1d=256, box=256.0, z_init=19.0, n_steps=20, seed=1)
     host = "unknown host CPU"
     try:
         with open("/proc/cpuinfo") as f:
             host = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
     except (OSError, StopIteration):
         pass
-    # the small f(R) configuration (32^3 particles, 64^3 mesh, L = 200 Mpc/h, 10 steps):
-    # median step time of the whole run
-    ps = oracle.Params(model=oracle.MODEL_FR, fr0_abs=1e-5, screening=1, np1d=32, nmesh1d=64,
-                       box=200.0, z_init=19.0, n_steps=10, seed=1)
-    rs = Run(ps)
-    ts = []
-    for _ in range(ps.n_steps):
-        t0 = time.perf_counter()
-        rs.step()
-        ts.append(time.perf_counter() - t0)
-    small_ms = 1e3 * sorted(ts)[len(ts) // 2]
-    return {"value": p.n_part * steps / dt, "unit": "particle-steps/s", "cores": 1,
+    cores = len(os.sched_getaffinity(0))
+    res = {}
+    for w in (1, cores):
+        fftlib.set_workers(w)
+        r = Run(p)
+        t = time.perf_counter()
+        for _ in range(steps):
+            r.step()
+        res[w] = time.perf_counter() - t
+    fftlib.set_workers(1)
+    return {"value": p.n_part * steps / res[cores], "unit": "particle-steps/s", "cores": cores,
             "kind": "oracle", "host_cpu": host,
-            "fr5_32_64_median_step_ms": small_ms,
-            "sample": f"nDGP rcH0=1 screened, 128^3 particles / 256^3 mesh / L=256 Mpc/h "
-                      f"(same spacing and cell as the workload), {steps} COLA steps of the "
-                      f"30-step grid after 2LPT ICs; numpy FFT and CIC, one thread; "
-                      f"{dt:.1f} s"}
+            "value_one_core": p.n_part * steps / res[1],
+            "sample": f"F5 scale-dependent, screened, 128^3 particles / 256^3 mesh / L=256 Mpc/h "
+                      f"(the workload's spacing and cell), {steps} COLA steps of the 20-step grid "
+                      f"after 2LPT ICs: {res[cores]:.1f} s with scipy FFTs on {cores} threads, "
+                      f"{res[1]:.1f} s on one (CIC deposit and gather single-threaded numpy)"}
 
 
 # FP64 operations of one classical Runge-Kutta step of the triangle system: four
@@ -387,16 +430,81 @@ def bench_models(C, torch, steps=3):
     return out
 
 
+def run_timed(C, torch, p, st, warmup, steps, profile, log):
+    """`warmup` untimed steps from initial conditions of their own, then exactly `steps`
+    timed cola_step calls starting from new initial conditions.  A run has p.n_steps
+    steps; when the timed steps go beyond one run they continue on further runs, each from
+    new initial conditions made outside the timed intervals.  Every timed interval is
+    bracketed by device synchronisation.  Returns (seconds, kernel profile, IC ms)."""
+    ic_ms = []
+
+    def new_run():
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        C.cola_make_ic(p, st)
+        torch.cuda.synchronize()
+        ic_ms.append((time.perf_counter() - t) * 1e3)
+
+    done = 0
+    while done < warmup:
+        new_run()
+        k = min(p.n_steps, warmup - done)
+        for i in range(k):
+            C.cola_step(p, st, i)
+        done += k
+    torch.cuda.synchronize()
+    log(f"{warmup} warm-up steps done; initial conditions {ic_ms[-1] if ic_ms else 0:.0f} ms")
+    if profile:
+        C.cola_profile_reset()
+    elapsed, i = 0.0, p.n_steps
+    left = steps
+    while left:
+        if i == p.n_steps:
+            new_run()
+            i = 0
+        k = min(left, p.n_steps - i)
+        if profile:
+            C.cola_profile_enable(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for j in range(i, i + k):
+            C.cola_step(p, st, j)
+        torch.cuda.synchronize()
+        elapsed += time.perf_counter() - t0
+        C.cola_profile_enable(False)
+        i += k
+        left -= k
+    prof = C.cola_profile_read() if profile else {}
+    return elapsed, prof, ic_ms
+
+
+def roofline_of(p, prof, traffic=None):
+    """The kernel with the largest share of the timed steps: its algorithmic bytes per
+    launch over its average launch time (HIP events on its launch stream)."""
+    if not prof:
+        return None
+    dom, (dom_ms, dom_cnt) = max(prof.items(), key=lambda kv: kv[1][0])
+    by = algorithmic_bytes(dom, p)
+    avg_s = dom_ms / dom_cnt / 1e3
+    ach = by / avg_s / 1e9 if by else None
+    return {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": ach / HBM_PEAK_GBS if ach else None,
+            "traffic": traffic(dom) if traffic else None, "avg_launch_ms": avg_s * 1e3,
+            "algorithmic_bytes_per_launch": by}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=28)
+    ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-models", action="store_true",
                     help="skip the per-step times of the other gravity models")
     ap.add_argument("--no-serving", action="store_true",
                     help="skip the ensemble and serving legs")
+    ap.add_argument("--headline-only", action="store_true",
+                    help="only the headline run (what the rocprofv3 summary profiles)")
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="requests in the serving stream (500 for the full stream)")
     ap.add_argument("--no-profile", action="store_true",
@@ -408,7 +516,8 @@ def main():
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
     args = ap.parse_args()
     if args.summarize_rocprof:
-        t = summarize_rocprof(args.summarize_rocprof, os.path.join(ROOT, "profiles"))
+        t = summarize_rocprof(args.summarize_rocprof, os.path.join(ROOT, "profiles"), args.steps,
+                              args.warmup)
         print(json.dumps({k: v["bytes_per_launch"] for k, v in t["kernels"].items()}))
         return
     if args.calibrate_copy:
@@ -425,92 +534,74 @@ def main():
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
               "(the multi-GPU decomposition is not part of this build)", file=sys.stderr)
         sys.exit(2)
+    if args.steps < 1 or args.warmup < 0:
+        print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
+        sys.exit(2)
 
     import torch
     from paper_1703_00879_amd import cola as C
 
-    p = workload_params(C)
-    if args.warmup + args.steps > p.n_steps:
-        print(f"warmup + steps must be <= {p.n_steps} (one run to z = 0)", file=sys.stderr)
-        sys.exit(2)
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
     torch.cuda.set_device(0)
+    p = workload_params(C)
     st = C.State(p, device="cuda:0")
-    stream = torch.cuda.current_stream()
-
-    torch.cuda.synchronize()
+    log(f"state {C.cola_query_sizes(p)['total_bytes'] / 2 ** 30:.1f} GiB allocated")
+    elapsed, prof, ic_ms = run_timed(C, torch, p, st, args.warmup, args.steps,
+                                     not args.no_profile, log)
+    log(f"{args.steps} timed steps: {elapsed:.3f} s")
     t0 = time.perf_counter()
-    C.cola_make_ic(p, st)
-    torch.cuda.synchronize()
-    ic_ms = (time.perf_counter() - t0) * 1e3
-    print(f"[bench] initial conditions {ic_ms:.1f} ms", file=sys.stderr, flush=True)
-
-    for i in range(args.warmup):
-        C.cola_step(p, st, i)
-    torch.cuda.synchronize()
-    print(f"[bench] {args.warmup} warmup steps done", file=sys.stderr, flush=True)
-
-    if not args.no_profile:
-        C.cola_profile_reset()
-        C.cola_profile_enable(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i in range(args.warmup, args.warmup + args.steps):
-        C.cola_step(p, st, i)
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
-    C.cola_profile_enable(False)
-    prof = {} if args.no_profile else C.cola_profile_read()
-    print(f"[bench] {args.steps} timed steps: {elapsed:.3f} s", file=sys.stderr, flush=True)
-
-    t0 = time.perf_counter()
-    k, P, nm = C.cola_power_spectrum(p, st)
+    C.cola_power_spectrum(p, st)
     pk_ms = (time.perf_counter() - t0) * 1e3
     ok = bool(torch.isfinite(st.disp_f).all().item())
-
-    N = p.np1d ** 3
-    value = N * args.steps / elapsed
-    ms_step = elapsed * 1e3 / args.steps
-    kernels = {name: {"ms_per_step": ms / args.steps, "launches_per_step": cnt / args.steps}
-               for name, (ms, cnt) in sorted(prof.items(), key=lambda kv: -kv[1][0])}
-    roofline = None
-    if prof:
-        dom, (dom_ms, dom_cnt) = max(prof.items(), key=lambda kv: kv[1][0])
-        by = algorithmic_bytes(dom, p)
-        avg_s = dom_ms / dom_cnt / 1e3
-        ach = by / avg_s / 1e9 if by else None
-        tr = traffic_for(dom)
-        roofline = {"bound": "hbm", "kernel": dom, "achieved": ach, "peak": HBM_PEAK_GBS,
-                    "unit": "GB/s", "frac": ach / HBM_PEAK_GBS if ach else None,
-                    "traffic": tr, "avg_launch_ms": avg_s * 1e3,
-                    "algorithmic_bytes_per_launch": by}
-    yard = yardstick_bytes_per_step(p)
-    out = {
-        "metric": METRIC, "value": value, "unit": "particle-steps/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
-        "data": "synthetic",
-        "config": {"workload": "nDGP rcH0=1 Vainshtein-screened (Gaussian R=1 Mpc/h), "
-                               "Np=512^3, Nmesh=1024^3, L=1024 Mpc/h, 2LPT at z=19, "
-                               "30 COLA steps", "gravity": "nDGP", "np1d": 512,
-                   "nmesh1d": 1024, "box_mpc_h": 1024.0, "n_steps": 30, "seed": 1,
-                   "parallelism": "single GPU"},
-        "roofline": roofline,
-        "hbm_frac_yardstick": yard / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
-        "yardstick_bytes_per_step": yard,
-        "ic_ms": ic_ms, "pk_ms": pk_ms, "finite": ok,
-        "kernels": kernels,
-    }
-    out["growth_triangles"] = bench_triangles(C, torch)
     del st
     torch.cuda.empty_cache()
-    if not args.no_models:
-        out["other_models_ms_per_step"] = bench_models(C, torch)
-    if not args.no_serving:
-        print("[bench] ensemble and serving", file=sys.stderr, flush=True)
-        out["ensemble"] = bench_ensemble(C, torch)
-        out["serving"] = bench_serving(C, torch, requests=args.serve_requests)
-    if not args.no_cpu_baseline:
-        print("[bench] timing the FP64 oracle on the host", file=sys.stderr, flush=True)
+
+    N = p.np1d ** 3
+    ms_step = elapsed * 1e3 / args.steps
+    yard = yardstick_bytes_for(p, C)
+    kernels = {name: {"ms_per_step": ms / args.steps, "launches_per_step": cnt / args.steps}
+               for name, (ms, cnt) in sorted(prof.items(), key=lambda kv: -kv[1][0])}
+    out = {
+        "metric": METRIC, "value": N * args.steps / elapsed, "unit": "particle-steps/s",
+        "n_gpus": 1, "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_step,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": WORKLOAD, "gravity": "f(R) Hu-Sawicki n=1", "fr0_abs": 1e-5,
+                   "growth": "scale-dependent", "np1d": p.np1d, "nmesh1d": p.nmesh1d,
+                   "box_mpc_h": p.box, "n_steps": p.n_steps, "seed": p.seed,
+                   "parallelism": "single GPU"},
+        "roofline": roofline_of(p, prof, traffic_for),
+        "hbm_frac_yardstick": yard / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
+        "yardstick_bytes_per_step": yard,
+        "ic_ms": ic_ms[-1], "pk_ms": pk_ms, "finite": ok,
+        "kernels": kernels,
+    }
+    if not args.headline_only:
+        q = secondary_params(C)
+        st = C.State(q, device="cuda:0")
+        e2, prof2, _ = run_timed(C, torch, q, st, 2, 10, not args.no_profile, log)
+        del st
+        torch.cuda.empty_cache()
+        ms2 = e2 * 1e3 / 10
+        out["secondary"] = {
+            "workload": SECONDARY, "steps": 10, "warmup": 2, "ms_per_step": ms2,
+            "particle_steps_per_s": q.np1d ** 3 * 10 / e2,
+            "hbm_frac_yardstick": yardstick_bytes_for(q, C) / (ms2 / 1e3) / 1e9 / HBM_PEAK_GBS,
+            "roofline": roofline_of(q, prof2),
+            "kernels": {name: {"ms_per_step": ms / 10, "launches_per_step": cnt / 10}
+                        for name, (ms, cnt) in sorted(prof2.items(), key=lambda kv: -kv[1][0])}}
+        log(f"secondary: {ms2:.2f} ms/step")
+        out["growth_triangles"] = bench_triangles(C, torch)
+        if not args.no_models:
+            out["other_models_ms_per_step"] = bench_models(C, torch)
+        if not args.no_serving:
+            log("ensemble and serving")
+            out["ensemble"] = bench_ensemble(C, torch)
+            out["serving"] = bench_serving(C, torch, requests=args.serve_requests)
+    if not args.no_cpu_baseline and not args.headline_only:
+        log("timing the FP64 oracle on the host")
         out["cpu_baseline"] = cpu_baseline()
     else:
         out["cpu_baseline"] = None

@@ -276,6 +276,8 @@ static void step_impl(const cola_params* p, cola_state* st, int32_t i, void* wor
   if (L.kdep) {
     // L''(q, a_i) and Psi_LPT(a_{i+1}) - Psi_LPT(a_i) from the stored k-space fields
     const FFTPlan pp = plan_part(b);
+    float2* coef = at<float2>(st->tables, L.off_lpt_coef);
+    launch_lpt_coef(L, b.growth, g.slice0, g.slice1, coef, s);
     for (int c = 0; c < 6; ++c) {
       KOp op;
       op.kf = (float)(2.0 * M_PI / p->box);
@@ -285,6 +287,7 @@ static void step_impl(const cola_params* p, cola_state* st, int32_t i, void* wor
       op.tab_slice0 = g.slice0;
       op.tab_slice1 = g.slice1;
       op.lpt_mode = c < 3 ? 0 : 1;
+      op.coef = coef + (c < 3 ? 0 : L.n_k);
       op.kdep = 1;
       op.comp = c % 3;
       op.scale = (float)(1.0 / (double)L.N);

@@ -215,6 +215,8 @@ Layout make_layout(const cola_params& p) {
   L.off_scratch = o;
   L.scratch_bytes = pk_scratch_bytes(L, 2048) + align_up(2048 * (sizeof(float4) + 8));
   o = align_up(o + L.scratch_bytes);
+  L.off_lpt_coef = o;
+  o = align_up(o + (L.kdep ? 2 * (size_t)L.n_k * sizeof(float2) : 0));
   L.tables_bytes = o;
   const size_t mesh_bytes = align_up(L.mesh_elems * sizeof(float2));
   const size_t pfield_bytes = align_up(L.pgrid_elems * sizeof(float2));

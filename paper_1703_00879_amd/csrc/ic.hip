@@ -280,6 +280,26 @@ void launch_growth_ode(const cola_params& p, const Layout& L, double* table, dou
   COLA_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------------------------ per-step LPT coefficients
+__global__ void k_lpt_coef(const double* __restrict__ table, int64_t slice0, int64_t slice1,
+                           int64_t n_k, float2* __restrict__ coef) {
+  for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_k;
+       k += (int64_t)gridDim.x * blockDim.x) {
+    const double* t0 = table + slice0 + 6 * k;
+    const double* t1 = table + slice1 + 6 * k;
+    coef[k] = make_float2((float)t0[2], (float)t0[5]);
+    coef[n_k + k] = make_float2((float)(t1[0] - t0[0]), (float)(t1[3] - t0[3]));
+  }
+}
+
+void launch_lpt_coef(const Layout& L, const double* table, int64_t slice0, int64_t slice1,
+                     float2* coef, hipStream_t s) {
+  ProfScope ps("lpt_coef", s);
+  const unsigned g = (unsigned)std::min<int64_t>((L.n_k + 255) / 256, 4096);
+  hipLaunchKernelGGL(k_lpt_coef, dim3(g), dim3(256), 0, s, table, slice0, slice1, L.n_k, coef);
+  COLA_LAUNCH_CHECK();
+}
+
 // ------------------------------------------------------------------ triangle growth
 // Exact second-order growth of a Fourier triangle k = k1 + k2 (Sec. 4.2) beside the
 // approximation the path uses, D2_hat(k)(1 - cos^2 theta), for checking it (Fig. 1):

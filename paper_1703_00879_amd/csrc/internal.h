@@ -70,7 +70,7 @@ struct Layout {
   int64_t n_k;              // entries per growth-table slice
   int n_steps;
   // offsets (bytes) inside `tables`
-  size_t off_growth, off_ref, off_tw_m, off_tw_p, off_scratch, tables_bytes;
+  size_t off_growth, off_ref, off_tw_m, off_tw_p, off_scratch, off_lpt_coef, tables_bytes;
   size_t scratch_bytes;
   // offsets (bytes) inside `work`: six mesh slots (padded half-complex / real meshes);
   // the interleaved force mesh [nm][nm][nm][3] spans slots 3-5, and the sorted CIC
@@ -135,6 +135,7 @@ struct KOp {
   const double* table = nullptr;   // growth table base (K_LPT)
   int64_t tab_slice0 = 0, tab_slice1 = 0;   // element offsets of two slices (K_LPT)
   int lpt_mode = 0;                // 0: X = D''(slice0); 1: X = D(slice1) - D(slice0); 2: X = D(slice0)
+  const float2* coef = nullptr;    // K_LPT: the step's (X1, X2) per |nu|^2 in FP32, if built
   int comp = 0, comp2 = 0;
   float scale = 1.f;
   float kf = 1.f;                  // 2 pi / L
@@ -207,6 +208,11 @@ void launch_unpad3(const Layout& L, const float* const f0[3], const float* const
                    float alpha, float beta, float* out, hipStream_t s);
 void launch_combine_u0(const Layout& L, const float* psi1, const float* psi2,
                        const double* table, float* disp, hipStream_t s);
+// The growth-table values the step's LPT transforms read, rounded once to FP32 per |nu|^2:
+// coef[k] = (D1''(a_i), D2''(a_i)) and coef[n_k + k] = (D1(a_i+1) - D1(a_i), D2(a_i+1) -
+// D2(a_i)) (differences taken in FP64), from table slices at element offsets slice0/slice1.
+void launch_lpt_coef(const Layout& L, const double* table, int64_t slice0, int64_t slice1,
+                     float2* coef, hipStream_t s);
 // CIC deposit into the padded real mesh.  `bins` is the work area at off_bins, `entries`
 // the packed per-particle CIC records sorted by home tile (float4 each).
 void launch_deposit(const Layout& L, const float* disp, float* rho_padded, void* bins,

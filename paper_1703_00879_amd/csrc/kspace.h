@@ -71,11 +71,15 @@ __device__ __forceinline__ float2 kspace_apply(const KOp& op, int ix, int iy, in
     return make_float2(f * a.x, f * a.y);
   } else if constexpr (KIND == K_LPT) {
     if (n2 == 0 || nyq_c) return make_float2(0.f, 0.f);
+    float x1, x2;
     const int64_t e = (int64_t)(op.kdep ? n2 : 0) * 6;
     const double* t0 = op.table + op.tab_slice0 + e;
     const double* t1 = op.table + op.tab_slice1 + e;
-    float x1, x2;
-    if (op.lpt_mode == 0) {          // second derivatives at slice 0
+    if (op.coef) {                   // the step's FP32 pairs: one 8-byte read per mode
+      const float2 cf = op.coef[op.kdep ? n2 : 0];
+      x1 = cf.x;
+      x2 = cf.y;
+    } else if (op.lpt_mode == 0) {   // second derivatives at slice 0
       x1 = (float)t0[2];
       x2 = (float)t0[5];
     } else if (op.lpt_mode == 1) {   // D(slice 1) - D(slice 0)

@@ -23,14 +23,16 @@ def bench():
 
 def test_yardstick_per_particle_step(bench):
     # 1300 B per screened scale-independent particle-step at M = 8N; LCDM 852 B; with the
-    # per-step LPT synthesis of scale-dependent growth 1428 B
+    # per-step LPT synthesis of scale-dependent growth 1428 B (the headline workload)
     p = bench.workload_params(C)
     N = p.np1d ** 3
-    assert bench.yardstick_bytes_per_step(p) == 1300 * N
-    assert bench.yardstick_bytes_for(p, C) == 1300 * N
+    assert p.nmesh1d ** 3 == 8 * N
+    assert bench.yardstick_bytes_for(p, C) == 1428 * N
     assert bench.yardstick_bytes_for(p.with_(model=C.LCDM), C) == 852 * N
-    assert bench.yardstick_bytes_for(p.with_(model=C.FR_HS1, growth_mode=0), C) == 1428 * N
+    assert bench.yardstick_bytes_for(p.with_(model=C.NDGP), C) == 1300 * N
     assert bench.yardstick_bytes_for(p.with_(model=C.FR_HS1, growth_mode=1), C) == 1300 * N
+    q = bench.secondary_params(C)
+    assert bench.yardstick_bytes_for(q, C) == 1300 * q.np1d ** 3
 
 
 def test_algorithmic_bytes(bench):
@@ -43,6 +45,9 @@ def test_algorithmic_bytes(bench):
     assert ab("fft_x_fwd_smooth") == 16 * H and ab("fft_x_fwd_pot") == 24 * H
     assert ab("fft_x_fwd_force_1src") == 24 * H and ab("fft_x_fwd_force") == 32 * H
     assert ab("deposit") == 16 * N + 4 * M
+    Hp = p.np1d ** 2 * (p.np1d // 2 + 1)
+    assert ab("fft_x_inv_lpt") == 24 * Hp and ab("lpt_fft_y_inv") == 16 * Hp
+    assert ab("lpt_fft_c2r_z") == 8 * Hp + 4 * N
     assert ab("no_such_kernel") is None
 
 
@@ -59,9 +64,12 @@ def test_algorithmic_bytes(bench):
     ("void cola::k_bin<0, true>(float const*)", "bin_count"),
     ("void cola::k_bin<1, true>(float const*)", "bin_scatter"),
     ("void cola::k_deposit_tiles<16>(float4 const*)", "deposit"),
+    ("void cola::k_fft_col<512, 1, 4, 8>(HIP_vector_type<float, 2u>*, long)", "fft_x_inv_lpt"),
+    ("void cola::k_fft_col<512, 1, 0, 16>(HIP_vector_type<float, 2u>*, long)", "lpt_fft_y_inv"),
+    ("void cola::k_fft_c2r_row<256>(float2 const*)", "lpt_fft_c2r_z"),
 ])
 def test_profile_names(bench, symbol, name):
-    assert bench._profile_name(symbol, 1024) == name
+    assert bench._profile_name(symbol, 1024, 512) == name
 
 
 def _write(path, header, rows):
@@ -73,9 +81,9 @@ def _write(path, header, rows):
 
 
 def test_summarize_rocprof_on_synthetic_runs(bench, tmp_path):
-    """Three steps (the first is the warm-up): the gather ends each step; the summary
-    covers the two steps after the first gather, scales FETCH_SIZE and WRITE_SIZE by the
-    factors that make a 1 GiB copy read 1 GiB, and writes both profile files."""
+    """Three timed steps: the gather ends each step; the summary covers the two steps
+    after the first gather, scales FETCH_SIZE and WRITE_SIZE by the factors that make a
+    1 GiB copy read 1 GiB, and writes both profile files."""
     d = tmp_path / "prof"
     gather = "void cola::k_gather<0>(cola::GatherDev, long)"
     c2r3 = "void cola::k_fft_c2r_row3<512>(float2 const*)"
@@ -103,14 +111,14 @@ def test_summarize_rocprof_on_synthetic_runs(bench, tmp_path):
            ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"],
            [[1, copy, "WRITE_SIZE", gib_kib]])
     out = tmp_path / "profiles"
-    t = bench.summarize_rocprof(str(d), str(out))
+    t = bench.summarize_rocprof(str(d), str(out), steps=3)
     assert t["fetch_scale"] == pytest.approx(2.0) and t["write_scale"] == pytest.approx(1.0)
     g, c = t["kernels"]["gather_kick_drift"], t["kernels"]["fft_c2r_z3"]
     assert g["launches_per_step"] == 1 and c["launches_per_step"] == 1
     assert g["avg_ms"] == pytest.approx(4.0) and c["ms_per_step"] == pytest.approx(5.0)
     assert g["bytes_per_launch"] == pytest.approx(1024 * (2 * 2000.0 + 500.0))
     assert c["bytes_per_launch"] == pytest.approx(1024 * (2 * 1000.0 + 3000.0))
-    saved = json.load(open(out / "traffic_ndgp_512_1024.json"))
+    saved = json.load(open(out / bench.TRAFFIC_FILE))
     assert saved["source_hash"] == bench.source_hash()
-    md = open(out / "pm_step_ndgp_512_1024.md").read()
+    md = open(out / bench.PROFILE_FILE).read()
     assert "| fft_c2r_z3 | 1 | 5.000 |" in md and "rocprofv3 --kernel-trace" in md

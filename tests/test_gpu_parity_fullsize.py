@@ -266,3 +266,130 @@ def test_maximum_size_planar_forces():
              fp_across=max(rms(F[1]), rms(F[2])) / rms(F[0]))
     record("maximum_size_planar_forces", **e)
     assert e["fp"] < 1e-5 and e["fp_across"] < 1e-5, e
+
+
+def _sparse_modes(n, box, rng):
+    """Five particle-grid modes (nu_x, nu_y, nu_z), 0 < nu_z < n/2: a low mode, an x- and a
+    y-Nyquist mode (their i k_x / i k_y factor is zero), the largest |nu|^2 with a
+    non-zero gradient, and a mode next to k = 0; amplitudes make each field O(1) Mpc/h."""
+    h = n // 2
+    nus = [(3, 5, 7), (-h, 2, 9), (h - 1, -(h - 1), h - 1), (0, -h, 3), (-1, 0, 1)]
+    out = []
+    for nu in nus:
+        k = 2 * np.pi * math.sqrt(sum(v * v for v in nu)) / box
+        a1, a2 = (rng.standard_normal(2) + 1j * rng.standard_normal(2)) * n ** 3 / k
+        out.append((nu, a1, a2))
+    return out
+
+
+@pytest.mark.parametrize("n_p", [512, 1024])
+def test_fullsize_scale_dependent_lpt_step(n_p):
+    """One cola_step of F5 with scale-dependent growth at 512^3 particles / 1024^3 cells and
+    at 1024^3 / 2048^3 (the headline size; skipped when the device lacks the memory) with
+    the particles on the lattice (u = v = 0, so the density is exactly uniform and the PM
+    force exactly zero) and phi1_k, phi2_k zero except at five modes.  The step then gives
+    v = -dtau_kick L''(q, a_i) and u = dtau_drift v + Delta_i(q): the per-step LPT synthesis
+    (App. A) through the particle-grid transforms and the gather, compared particle by
+    particle with the oracle's direct summation over the modes with its FP64 growth factors
+    (every particle at 512^3; every particle of every eighth lattice plane at 1024^3)."""
+    p = C.Params(model=C.FR_HS1, fr0_abs=1e-5, screening=1, growth_mode=0, np1d=n_p,
+                 nmesh1d=2 * n_p, box=2.0 * n_p, z_init=19.0, n_steps=20, seed=1)
+    N = n_p ** 3
+    sizes = C.cola_query_sizes(p)
+    gc.collect()
+    torch.cuda.empty_cache()
+    free, _ = torch.cuda.mem_get_info()
+    need = sizes["total_bytes"] + (4 << 30)
+    if free < need:
+        pytest.skip(f"needs {need / 1e9:.0f} GB of device memory, {free / 1e9:.0f} GB free")
+    st = C.State(p)
+    C.cola_prepare(p, st)
+    st.disp_f.zero_()
+    st.vel_f.zero_()
+    st.lpt.zero_()
+    # phi1_k at byte 0, phi2_k at half of lpt_bytes: padded half-complex particle-grid
+    # fields, element (ix, iy, iz) at ix * plane + iy * pitch + iz (complex values)
+    pitch = (n_p // 2 + 1 + 15) // 16 * 16
+    plane = n_p * pitch + 16
+    lptc = st.lpt.view(torch.float32).view(-1, 2)
+    off2 = sizes["lpt_bytes"] // 2 // 8
+    rng = np.random.default_rng(n_p)
+    modes = _sparse_modes(n_p, p.box, rng)
+    for nu, a1, a2 in modes:
+        e = (nu[0] % n_p) * plane + (nu[1] % n_p) * pitch + nu[2]
+        lptc[e] = torch.tensor([a1.real, a1.imag], dtype=torch.float32)
+        lptc[off2 + e] = torch.tensor([a2.real, a2.imag], dtype=torch.float32)
+    i = 7
+    st.c.next_step = i
+    C.cola_step(p, st, i)
+    torch.cuda.synchronize()
+    # oracle: growth factors at the modes' k, the time grid, direct summation
+    from oracle.cola import time_grid
+    from oracle.lpt import lpt_field_sparse
+    po = to_oracle(p)
+    model = Model(po)
+    a_grid, kick, drift = time_grid(po)
+    ks = np.array([2 * np.pi * math.sqrt(sum(v * v for v in nu)) / p.box for nu, _, _ in modes])
+    G = solve_growth(ks, a_grid[i:i + 2], po.omega_m, model.mu, model.gamma2_orth, po.a_ini)
+    G0, G1 = G[0], G[1]
+    lpp = [(nu, G0[m, 2] * complex(np.complex64(a1)) + G0[m, 5] * complex(np.complex64(a2)))
+           for m, (nu, a1, a2) in enumerate(modes)]
+    dlt = [(nu, (G1[m, 0] - G0[m, 0]) * complex(np.complex64(a1))
+            + (G1[m, 3] - G0[m, 3]) * complex(np.complex64(a2)))
+           for m, (nu, a1, a2) in enumerate(modes)]
+    step = 1 if n_p <= 512 else 8
+    chunk = 32 if n_p <= 512 else 8
+    num_u = den_u = num_v = den_v = 0.0
+    u3 = st.disp_f.view(3, n_p, n_p, n_p)
+    v3 = st.vel_f.view(3, n_p, n_p, n_p)
+    for x0 in range(0, n_p, chunk * step):
+        planes = np.arange(x0, min(n_p, x0 + chunk * step), step)
+        L2 = lpt_field_sparse(lpp, n_p, p.box, planes)
+        D = lpt_field_sparse(dlt, n_p, p.box, planes)
+        v_or = -kick[i] * L2
+        u_or = drift[i] * v_or + D
+        sel = torch.from_numpy(planes).cuda()
+        ug = u3[:, sel].cpu().numpy().astype(np.float64)
+        vg = v3[:, sel].cpu().numpy().astype(np.float64)
+        num_u += float(((ug - u_or) ** 2).sum())
+        den_u += float((u_or ** 2).sum())
+        num_v += float(((vg - v_or) ** 2).sum())
+        den_v += float((v_or ** 2).sum())
+    e = dict(u=math.sqrt(num_u / den_u), v=math.sqrt(num_v / den_v),
+             u_rms=math.sqrt(den_u / (3 * N / step)))
+    record(f"fullsize_scale_dependent_lpt_step_np{n_p}", **e)
+    assert e["u_rms"] > 1e-3   # the modes move the particles
+    assert e["u"] < 1e-5 and e["v"] < 1e-5, e
+
+
+def test_fullsize_initial_conditions_512():
+    """cola_make_ic of F5 with scale-dependent growth at 512^3 particles (the 8-column
+    particle-grid tiles of the Hessian, potential and LPT transforms) against the oracle's
+    2LPT fields on the same seeded white noise: u = Psi1 - (3/7) Psi2 at every particle."""
+    from oracle import fftlib
+    from oracle.lpt import initial_fields
+    from oracle.spectrum import InitialSpectrum
+    p = C.Params(model=C.FR_HS1, fr0_abs=1e-5, screening=1, growth_mode=0, np1d=512,
+                 nmesh1d=1024, box=1024.0, z_init=19.0, n_steps=20, seed=1)
+    st = C.State(p)
+    C.cola_make_ic(p, st)
+    torch.cuda.synchronize()
+    u = st.disp_f.cpu().numpy()
+    del st
+    gc.collect()
+    torch.cuda.empty_cache()
+    po = to_oracle(p)
+    fftlib.set_workers(min(16, len(__import__("os").sched_getaffinity(0))))
+    try:
+        f = initial_fields(po, InitialSpectrum(po))
+    finally:
+        fftlib.set_workers(1)
+    num = den = 0.0
+    for c in range(3):
+        ref = (f["psi1"][c] - (3.0 / 7.0) * f["psi2"][c]).reshape(-1)
+        d = u[c].astype(np.float64) - ref
+        num += float(d @ d)
+        den += float(ref @ ref)
+    e = dict(u=math.sqrt(num / den), u_rms=math.sqrt(den / u.size))
+    record("fullsize_initial_conditions_512", **e)
+    assert e["u"] < 1e-5, e
