@@ -173,6 +173,27 @@ cola_status cola_step(const cola_params* p, cola_state* st, int32_t i, hipStream
  * conditions still need cola_make_ic with a work buffer, which may be shared by runs. */
 cola_status cola_step_static(const cola_params* p, cola_state* st, int32_t i, hipStream_t stream);
 
+/* Ensembles (the mock catalogues the method is for, Sec. 1): runs stepped together.
+ * One step of every member with steps left is captured as one HIP graph, each member a
+ * branch on one of n_streams capture streams (default priority), and the graph is
+ * replayed while the same members have steps left; then a graph of the remaining members
+ * is captured, until every member reaches z = 0.  Every step is the same kernels with the
+ * same per-step values as cola_step (taken from the state's step table at the state's
+ * device step counter), so each member's result is bitwise that of stepping it alone.
+ * cola_ensemble_create: n >= 1 runs, params[j] and states[j] (host arrays; the states
+ *   are caller-owned and must outlive the ensemble, each with its own buffers).  The
+ *   handle holds host-side objects only (streams and events are made by the first run).
+ * cola_ensemble_run: every member needs its initial conditions (cola_make_ic) and may
+ *   start at any next_step; 1 <= n_streams <= 64; kernel profiling must be off.  Each
+ *   member's next_step ends at n_steps.  Enqueues on `stream` and returns.
+ * cola_ensemble_destroy: waits for the ensemble's work, then releases the handle and
+ *   the graphs it made (NULL is accepted). */
+typedef struct cola_ensemble cola_ensemble;
+cola_status cola_ensemble_create(int32_t n, const cola_params* params, cola_state* const* states,
+                                 cola_ensemble** out);
+cola_status cola_ensemble_run(cola_ensemble* e, int32_t n_streams, hipStream_t stream);
+cola_status cola_ensemble_destroy(cola_ensemble* e);
+
 /* Shell-averaged power spectrum of the current particles (the P(k) output of Sec. 8):
  * CIC on the PM mesh, FFT, P_b = < L^3 |delta_k|^2 / (M^2 W_CIC^2) > over shells
  * b = floor(|nu| + 1/2), modes weighted 2 for 0 < nu_z < n/2.  Host outputs k_out,

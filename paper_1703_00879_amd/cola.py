@@ -21,7 +21,8 @@ SMOOTH_GAUSS, SMOOTH_TOPHAT, SMOOTH_SHARPK = 0, 1, 2
 READ_X_TOTAL_DENSITY, READ_X_NO_A3, READ_D2_HALF_K = 1, 2, 4
 
 EXPORTED = ["cola_query_sizes", "cola_validate", "cola_prepare", "cola_make_ic", "cola_pm_force",
-            "cola_step", "cola_step_static", "cola_power_spectrum", "cola_positions", "cola_growth_table",
+            "cola_step", "cola_step_static", "cola_ensemble_create", "cola_ensemble_run",
+            "cola_ensemble_destroy", "cola_power_spectrum", "cola_positions", "cola_growth_table",
             "cola_white_noise", "cola_growth_triangles", "cola_profile_enable", "cola_profile_read",
             "cola_profile_reset",
             "cola_status_string", "cola_last_error"]
@@ -110,6 +111,8 @@ def load_library(path=LIB_PATH):
         "cola_query_sizes": [P, S], "cola_validate": [P], "cola_prepare": [P, St, vp],
         "cola_make_ic": [P, St, vp], "cola_pm_force": [P, St, d, vp, vp, vp],
         "cola_step": [P, St, i32, vp], "cola_step_static": [P, St, i32, vp],
+        "cola_ensemble_create": [i32, P, vp, vp], "cola_ensemble_run": [vp, i32, vp],
+        "cola_ensemble_destroy": [vp],
         "cola_power_spectrum": [P, St, i32, vp, vp, vp, vp],
         "cola_positions": [P, St, vp, vp],
         "cola_growth_table": [P, St, i32, vp, i64, vp, vp],
@@ -208,6 +211,33 @@ def cola_step(p, state, i, stream=None):
 def cola_step_static(p, state, i, stream=None):
     _check(load_library().cola_step_static(ctypes.byref(p._c()), ctypes.byref(state.c), int(i),
                                            _stream(stream)))
+
+
+class Ensemble:
+    """Runs stepped together as captured HIP graphs (cola_ensemble_*): the parameter and
+    state arrays are marshalled once; run() advances every member to z = 0."""
+
+    def __init__(self, params, states):
+        lib = load_library()
+        self.states = list(states)
+        self._p = (_Params * len(params))(*[q._c() for q in params])
+        self._st = (ctypes.POINTER(_State) * len(states))(*[ctypes.pointer(st.c) for st in states])
+        self.h = ctypes.c_void_p(0)
+        _check(lib.cola_ensemble_create(len(params), self._p, self._st, ctypes.byref(self.h)))
+
+    def run(self, n_streams=8, stream=None):
+        _check(load_library().cola_ensemble_run(self.h, int(n_streams), _stream(stream)))
+
+    def close(self):
+        if self.h:
+            _check(load_library().cola_ensemble_destroy(self.h))
+            self.h = ctypes.c_void_p(0)
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def cola_power_spectrum(p, state, nbins=None, stream=None):

@@ -7,6 +7,7 @@
 #include <cmath>
 #include <cstring>
 #include <map>
+#include <memory>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -116,6 +117,8 @@ struct Bufs {
   float* psi2;
   void* bins;
   float4* entries;
+  StepDev* steps;     // per-step scalars of every step
+  int* ctr;           // device step counter: the step the step kernels read
 };
 
 template <class T>
@@ -151,6 +154,8 @@ static Bufs carve(const cola_params& p, const cola_state* st, void* work = nullp
   b.pk_scratch = at<void>(st->tables, L.off_scratch);
   b.pk_out = at<float4>(st->tables, L.off_scratch + pk_scratch_bytes(L, 2048));
   b.pk_cnt = reinterpret_cast<unsigned long long*>(b.pk_out + 2048);
+  b.steps = at<StepDev>(st->tables, L.off_steps);
+  b.ctr = at<int>(st->tables, L.off_ctr);
   for (int i = 0; i < 6; ++i) b.mesh[i] = at<float2>(work, L.off_mesh[i]);
   b.force = at<float>(work, L.off_mesh[3]);
   for (int i = 0; i < 6; ++i) b.pf[i] = L.kdep ? at<float2>(work, L.off_pfield[i]) : nullptr;
@@ -195,6 +200,7 @@ static void do_prepare(const cola_params& p, cola_state* st, const Bufs& b, hipS
   COLA_HIP_CHECK(hipMemcpyAsync(b.tw_m, tm.data(), tm.size() * sizeof(float2), hipMemcpyHostToDevice, s));
   COLA_HIP_CHECK(hipMemcpyAsync(b.tw_p, tp.data(), tp.size() * sizeof(float2), hipMemcpyHostToDevice, s));
   launch_growth_ode(p, b.L, b.growth, b.ref, s);
+  for (int i = 0; i < p.n_steps; ++i) launch_write_step(b.steps, i, step_dev(p, b.L, i), s);
   st->prepared = 1;
 }
 
@@ -205,10 +211,12 @@ static void do_prepare(const cola_params& p, cola_state* st, const Bufs& b, hipS
 // the three complex force components then take slots 0-2.  If flat_out is given, rho and
 // S are copied there before being overwritten.
 static void pm_core(const cola_params& p, const Bufs& b, const float* disp, double a,
-                    float* flat_out, hipStream_t s) {
+                    float* flat_out, hipStream_t s, bool from_table = false) {
   const Layout& L = b.L;
   const FFTPlan pl = plan_mesh(b);
-  const StepScalars sc = step_scalars(p, a);
+  const PMScalars sc = pm_scalars(p, a);
+  const StepDev* steps = from_table ? b.steps : nullptr;
+  const int* ctr = from_table ? b.ctr : nullptr;
   float2* const* M = b.mesh;
   const float invM = (float)(1.0 / (double)L.M);
   launch_deposit(L, disp, R(M[0]), b.bins, b.entries, s);
@@ -218,18 +226,19 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
   float2* src = M[1];
   KOp base;
   base.kf = (float)(2.0 * M_PI / p.box);
+  base.steps = steps;
+  base.step_ctr = ctr;
   KOp op = base;
-  op.g_n = -sc.kappa;
-  op.g_5 = sc.fifth ? -sc.coupling * sc.kappa : 0.f;
+  op.g_n = sc.g_n;
+  op.g_5 = sc.g_5;
   op.a2m2 = sc.a2m2;
   op.scale = invM;
   if (sc.screen) {
     KOp sop = base;
     sop.scale = invM;
     int kind = K_SMOOTH;
-    float cn = 0.f, c5 = 1.f;   // the row pass forms (rho - 1)(cn + c5 eps)
-    if (p.model == COLA_FR_HS1 || p.model == COLA_SYMMETRON) {   // potential screening
-      sop.g_n = -sc.kappa;
+    if (sc.potential) {   // potential screening (f(R), symmetron): delta_k is kept
+      sop.g_n = sc.sop_g_n;
       kind = K_POT;
       dk = M[1];
     } else {
@@ -238,14 +247,16 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
       // one field and delta_k need not be kept
       sop.r_smooth = (float)p.r_smooth;
       sop.filter = p.filter;
-      cn = op.g_n;
-      c5 = op.g_5;
-      op.g_n = 1.f;
-      op.g_5 = 0.f;
-      op.a2m2 = 0.f;
     }
-    fft_screen(pl, kind, sop, M[1], M[2], R(M[0]), flat_out ? R(M[3]) : nullptr, p.model,
-               sc.cham_thr, sc.vx_pref, sc.vx_off, cn, c5, s);
+    ScreenArgs sa;
+    sa.thr = sc.thr;
+    sa.vx = sc.vx;
+    sa.vx0 = sc.vx0;
+    sa.cn = sc.cn;
+    sa.c5 = sc.c5;
+    sa.steps = steps;
+    sa.step_ctr = ctr;
+    fft_screen(pl, kind, sop, M[1], M[2], R(M[0]), flat_out ? R(M[3]) : nullptr, p.model, sa, s);
     if (flat_out) launch_unpad_mesh(L, R(M[3]), flat_out + L.M, s);
     src = M[2];
   } else if (flat_out) {
@@ -256,36 +267,33 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
 }
 
 // One COLA step on the given work area (st->work when null, else the library's scratch).
-static void step_impl(const cola_params* p, cola_state* st, int32_t i, void* work, hipStream_t s) {
+// Its step-dependent scalars come from the state's step table at the device step counter,
+// which the step sets to i first (unless `replay`: a captured step that relies on the
+// counter the previous step advanced) and advances at the end.
+static void step_impl(const cola_params* p, cola_state* st, int32_t i, void* work, hipStream_t s,
+                      bool replay = false) {
   if (!p) throw Error{COLA_E_ARG, "params is NULL"};
   const Bufs b = carve(*p, st, work);
   const Layout& L = b.L;
   if (!st->prepared || st->next_step < 0) throw Error{COLA_E_STATE, "no initial conditions"};
   if (i != st->next_step) throw Error{COLA_E_STATE, "step index out of order"};
   if (i < 0 || i >= p->n_steps) throw Error{COLA_E_STATE, "step index beyond n_steps"};
-  const Cosmo cz{p->omega_m, 1.0 - p->omega_m};
-  const double ai = a_of_step(*p, i), an = a_of_step(*p, i + 1);
-  const double a_lo = (i == 0) ? ai : 0.5 * (a_of_step(*p, i - 1) + ai);
-  const double a_hi = 0.5 * (ai + an);
+  if (!replay) launch_set_counter(b.ctr, i, s);
   GatherArgs g{};
-  g.dtk = tau_between(cz, a_lo, a_hi);
-  g.dtd = tau_between(cz, ai, an);
   g.table = b.growth;
-  g.slice0 = (int64_t)i * L.n_k * 6;
-  g.slice1 = (int64_t)(i + 1) * L.n_k * 6;
+  g.steps = b.steps;
+  g.step_ctr = b.ctr;
   if (L.kdep) {
     // L''(q, a_i) and Psi_LPT(a_{i+1}) - Psi_LPT(a_i) from the stored k-space fields
     const FFTPlan pp = plan_part(b);
     float2* coef = at<float2>(st->tables, L.off_lpt_coef);
-    launch_lpt_coef(L, b.growth, g.slice0, g.slice1, coef, s);
+    launch_lpt_coef(L, b.growth, 0, 0, b.steps, b.ctr, coef, s);
     for (int c = 0; c < 6; ++c) {
       KOp op;
       op.kf = (float)(2.0 * M_PI / p->box);
       op.a = b.phi1;
       op.b = b.phi2;
       op.table = b.growth;
-      op.tab_slice0 = g.slice0;
-      op.tab_slice1 = g.slice1;
       op.lpt_mode = c < 3 ? 0 : 1;
       op.coef = coef + (c < 3 ? 0 : L.n_k);
       op.kdep = 1;
@@ -301,12 +309,106 @@ static void step_impl(const cola_params* p, cola_state* st, int32_t i, void* wor
     g.psi1 = b.psi1;
     g.psi2 = b.psi2;
   }
-  pm_core(*p, b, st->disp, ai, nullptr, s);
+  pm_core(*p, b, st->disp, a_of_step(*p, i), nullptr, s, true);
   g.F3 = b.force;
   g.disp = st->disp;
   g.vel = st->vel;
   launch_gather(L, g, s);
+  launch_step_advance(b.ctr, s);
   st->next_step = i + 1;
+}
+
+// ------------------------------------------------------------------ ensembles
+// Runs stepped together: one step of every member with steps left is captured as one HIP
+// graph, one stream branch per member (members spread over the capture streams), and the
+// graph is replayed while the set of members with steps left stays the same.
+struct Ensemble {
+  std::vector<cola_params> p;
+  std::vector<cola_state*> st;
+  std::vector<hipStream_t> streams;   // capture branches 1.. (branch 0 is the caller's stream)
+  std::vector<hipEvent_t> events;     // fork event, one join event per branch, hand-over
+  // graphs launched and not known to be finished: kept until the ensemble is destroyed
+  std::vector<std::pair<hipGraph_t, hipGraphExec_t>> graphs;
+  ~Ensemble() {
+    if (!streams.empty()) (void)hipStreamSynchronize(streams[0]);
+    for (auto& g : graphs) {
+      (void)hipGraphExecDestroy(g.second);
+      (void)hipGraphDestroy(g.first);
+    }
+    for (auto e : events) (void)hipEventDestroy(e);
+    for (auto x : streams) (void)hipStreamDestroy(x);
+  }
+};
+
+static void ensemble_run(Ensemble& E, int n_streams, hipStream_t s) {
+  if (prof().on) throw Error{COLA_E_STATE, "kernel profiling must be off while a graph is captured"};
+  const int nb = std::max(1, std::min<int>(n_streams, (int)E.st.size()));
+  // streams[0] captures and replays (the caller's stream may be the null stream, which
+  // cannot be captured); streams[1 ..] are the other branches
+  while ((int)E.streams.size() < nb) {
+    hipStream_t x;
+    COLA_HIP_CHECK(hipStreamCreateWithFlags(&x, hipStreamNonBlocking));
+    E.streams.push_back(x);
+  }
+  while ((int)E.events.size() < nb + 1) {
+    hipEvent_t e;
+    COLA_HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    E.events.push_back(e);
+  }
+  hipStream_t c0 = E.streams[0];
+  for (;;) {
+    std::vector<int> act;
+    int reps = 1 << 30;
+    for (int j = 0; j < (int)E.st.size(); ++j) {
+      const int left = E.p[j].n_steps - E.st[j]->next_step;
+      if (left > 0) {
+        act.push_back(j);
+        reps = std::min(reps, left);
+      }
+    }
+    if (act.empty()) break;
+    std::vector<int32_t> first(act.size());
+    for (size_t m = 0; m < act.size(); ++m) {   // the counters the captured steps start from
+      cola_state* st = E.st[act[m]];
+      first[m] = st->next_step;
+      const Bufs b = carve(E.p[act[m]], st);
+      launch_set_counter(b.ctr, st->next_step, s);
+    }
+    COLA_HIP_CHECK(hipEventRecord(E.events[nb], s));   // c0 starts after the caller's work
+    COLA_HIP_CHECK(hipStreamWaitEvent(c0, E.events[nb], 0));
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    COLA_HIP_CHECK(hipStreamBeginCapture(c0, hipStreamCaptureModeThreadLocal));
+    try {
+      COLA_HIP_CHECK(hipEventRecord(E.events[0], c0));
+      for (int k = 1; k < nb; ++k) COLA_HIP_CHECK(hipStreamWaitEvent(E.streams[k], E.events[0], 0));
+      for (size_t m = 0; m < act.size(); ++m)
+        step_impl(&E.p[act[m]], E.st[act[m]], first[m], nullptr, E.streams[m % nb], true);
+      for (int k = 1; k < nb; ++k) {
+        COLA_HIP_CHECK(hipEventRecord(E.events[k], E.streams[k]));
+        COLA_HIP_CHECK(hipStreamWaitEvent(c0, E.events[k], 0));
+      }
+    } catch (...) {
+      (void)hipStreamEndCapture(c0, &graph);
+      if (graph) (void)hipGraphDestroy(graph);
+      for (size_t m = 0; m < act.size(); ++m) E.st[act[m]]->next_step = first[m];
+      throw;
+    }
+    COLA_HIP_CHECK(hipStreamEndCapture(c0, &graph));
+    const hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    if (ie != hipSuccess) {
+      (void)hipGraphDestroy(graph);
+      for (size_t m = 0; m < act.size(); ++m) E.st[act[m]]->next_step = first[m];
+      throw Error{COLA_E_HIP, std::string("hipGraphInstantiate: ") + hipGetErrorString(ie)};
+    }
+    E.graphs.emplace_back(graph, exec);
+    hipError_t le = hipSuccess;
+    for (int r = 0; r < reps && le == hipSuccess; ++r) le = hipGraphLaunch(exec, c0);
+    if (le != hipSuccess) throw Error{COLA_E_HIP, std::string("hipGraphLaunch: ") + hipGetErrorString(le)};
+    for (size_t m = 0; m < act.size(); ++m) E.st[act[m]]->next_step = first[m] + reps;
+    COLA_HIP_CHECK(hipEventRecord(E.events[nb], c0));   // the caller's stream waits for the steps
+    COLA_HIP_CHECK(hipStreamWaitEvent(s, E.events[nb], 0));
+  }
 }
 
 }  // namespace cola
@@ -473,6 +575,41 @@ cola_status cola_step_static(const cola_params* p, cola_state* st, int32_t i, hi
     const Layout L = make_layout(*p);
     step_impl(p, st, i, static_work(L.work_bytes), s);
   });
+}
+
+cola_status cola_ensemble_create(int32_t n, const cola_params* params, cola_state* const* states,
+                                 cola_ensemble** out) {
+  return guarded([&] {
+    if (!out) throw Error{COLA_E_ARG, "out is NULL"};
+    *out = nullptr;
+    if (n < 1 || !params || !states) throw Error{COLA_E_ARG, "need n >= 1 runs"};
+    auto E = std::make_unique<Ensemble>();
+    for (int j = 0; j < n; ++j) {
+      const Bufs b = carve(params[j], states[j]);   // validates the run and its buffers
+      (void)b;
+      for (int i = 0; i < j; ++i)
+        if (states[i] == states[j]) throw Error{COLA_E_ARG, "a state appears twice"};
+      E->p.push_back(params[j]);
+      E->st.push_back(states[j]);
+    }
+    *out = reinterpret_cast<cola_ensemble*>(E.release());
+  });
+}
+
+cola_status cola_ensemble_run(cola_ensemble* e, int32_t n_streams, hipStream_t s) {
+  return guarded([&] {
+    if (!e) throw Error{COLA_E_ARG, "ensemble is NULL"};
+    if (n_streams < 1 || n_streams > 64) throw Error{COLA_E_ARG, "n_streams must be in [1, 64]"};
+    Ensemble& E = *reinterpret_cast<Ensemble*>(e);
+    for (size_t j = 0; j < E.st.size(); ++j)
+      if (!E.st[j]->prepared || E.st[j]->next_step < 0)
+        throw Error{COLA_E_STATE, "every member needs its initial conditions"};
+    ensemble_run(E, n_streams, s);
+  });
+}
+
+cola_status cola_ensemble_destroy(cola_ensemble* e) {
+  return guarded([&] { delete reinterpret_cast<Ensemble*>(e); });
 }
 
 cola_status cola_power_spectrum(const cola_params* p, cola_state* st, int32_t nbins, double* k_out,

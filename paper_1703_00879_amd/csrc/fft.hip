@@ -365,6 +365,7 @@ __global__ void __launch_bounds__(OpCfg<N>::T)
 k_fft_col_fwd_op(float2* __restrict__ data, float2* __restrict__ out, int64_t elemStride,
                  const float2* __restrict__ tw_g, KOp op) {
   constexpr int B = OpCfg<N>::B, E = OpCfg<N>::E, T = OpCfg<N>::T;
+  if (op.steps) op.g_n = op.steps[*op.step_ctr].sop_g_n;
   static_assert(T % B == 0, "a thread's butterflies must share one column");
   __shared__ float2 lds[N * B];
   __shared__ float2 tw[N];
@@ -416,6 +417,12 @@ __global__ void __launch_bounds__(ColCfg<N>::T)
 k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
                     int64_t elemStride, const float2* __restrict__ tw_g, KOp op) {
   constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
+  if (op.steps) {
+    const StepDev& sd = op.steps[*op.step_ctr];
+    op.g_n = sd.g_n;
+    op.g_5 = sd.g_5;
+    op.a2m2 = sd.a2m2;
+  }
   constexpr int R0 = Plan<N>::rad[0], NB0 = E / R0;
   static_assert(T % B == 0, "a thread's butterflies must share one column");
   __shared__ float2 lds[N * B];
@@ -758,8 +765,17 @@ template <int NC, int MODEL>
 __global__ void __launch_bounds__(RowCfg<NC>::T)
 k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float* __restrict__ s_out,
                  int64_t nrows, int /*n*/, int pitch, int64_t plane, const float2* __restrict__ tw_g,
-                 float thr, float vx, float vx0, float cn, float c5) {
+                 ScreenArgs sa) {
   constexpr int B = RowCfg<NC>::B, E = RowCfg<NC>::E, T = RowCfg<NC>::T, LS = RowCfg<NC>::LS;
+  if (sa.steps) {
+    const StepDev& sd = sa.steps[*sa.step_ctr];
+    sa.thr = sd.thr;
+    sa.vx = sd.vx;
+    sa.vx0 = sd.vx0;
+    sa.cn = sd.cn;
+    sa.c5 = sd.c5;
+  }
+  const float thr = sa.thr, vx = sa.vx, vx0 = sa.vx0, cn = sa.cn, c5 = sa.c5;
   __shared__ float2 lds[NC * LS];
   __shared__ float2 tw[2 * NC];   // twiddles exp(-2 pi i t / n), staged in LDS
   const int tid = threadIdx.x;
@@ -1008,8 +1024,8 @@ static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, c
 
 template <int N>
 static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* dk, float2* data,
-                        const float* rho, float* s_out, int model, float thr, float vx, float vx0,
-                        float cn, float c5, hipStream_t s) {
+                        const float* rho, float* s_out, int model, const ScreenArgs& sa,
+                        hipStream_t s) {
   const int n = pl.n, P = pl.pitch;
   const int64_t rows = (int64_t)n * n;
   constexpr int B = ColCfg<N>::B;
@@ -1036,10 +1052,10 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
     const dim3 g((unsigned)((rows + BR - 1) / BR)), b(RowCfg<N / 2>::T);
     if (model == COLA_FR_HS1 || model == COLA_SYMMETRON)   // eps = min(1, thr/|Phi|)
       hipLaunchKernelGGL((k_fft_screen_row<N / 2, COLA_FR_HS1>), g, b, 0, s, data, rho, s_out, rows, n,
-                         P, pl.plane, pl.tw, thr, vx, vx0, cn, c5);
+                         P, pl.plane, pl.tw, sa);
     else
       hipLaunchKernelGGL((k_fft_screen_row<N / 2, COLA_NDGP>), g, b, 0, s, data, rho, s_out, rows, n, P,
-                         pl.plane, pl.tw, thr, vx, vx0, cn, c5);
+                         pl.plane, pl.tw, sa);
     COLA_LAUNCH_CHECK();
   }
   col_pass<N, -1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s, "fft_y_fwd");
@@ -1057,10 +1073,9 @@ void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const fl
 }
 
 void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* dk, float2* data, const float* rho,
-                float* s_out, int model, float thr, float vx, float vx0, float cn, float c5,
-                hipStream_t s) {
+                float* s_out, int model, const ScreenArgs& sa, hipStream_t s) {
   switch (pl.n) {
-#define CASE(N_) case N_: screen_impl<N_>(pl, kind, op, dk, data, rho, s_out, model, thr, vx, vx0, cn, c5, s); return;
+#define CASE(N_) case N_: screen_impl<N_>(pl, kind, op, dk, data, rho, s_out, model, sa, s); return;
     CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
     CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
 #undef CASE

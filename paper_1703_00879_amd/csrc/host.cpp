@@ -150,6 +150,57 @@ StepScalars step_scalars(const cola_params& p, double a) {
   return s;
 }
 
+PMScalars pm_scalars(const cola_params& p, double a) {
+  const StepScalars sc = step_scalars(p, a);
+  PMScalars s{};
+  s.g_n = -sc.kappa;
+  s.g_5 = sc.fifth ? -sc.coupling * sc.kappa : 0.f;
+  s.a2m2 = sc.a2m2;
+  s.sop_g_n = 0.f;
+  s.thr = sc.cham_thr;
+  s.vx = sc.vx_pref;
+  s.vx0 = sc.vx_off;
+  s.cn = 0.f;
+  s.c5 = 1.f;
+  s.screen = sc.screen;
+  s.potential = (p.model == COLA_FR_HS1 || p.model == COLA_SYMMETRON) ? 1 : 0;
+  if (s.screen) {
+    if (s.potential) {
+      s.sop_g_n = -sc.kappa;
+    } else {   // one source: (rho - 1)(g_n + g_5 eps) over k^2
+      s.cn = s.g_n;
+      s.c5 = s.g_5;
+      s.g_n = 1.f;
+      s.g_5 = 0.f;
+      s.a2m2 = 0.f;
+    }
+  }
+  return s;
+}
+
+StepDev step_dev(const cola_params& p, const Layout& L, int i) {
+  const Cosmo cz{p.omega_m, 1.0 - p.omega_m};
+  const double ai = a_of_step(p, i), an = a_of_step(p, i + 1);
+  const double a_lo = (i == 0) ? ai : 0.5 * (a_of_step(p, i - 1) + ai);
+  const double a_hi = 0.5 * (ai + an);
+  const PMScalars m = pm_scalars(p, ai);
+  StepDev d{};
+  d.g_n = m.g_n;
+  d.g_5 = m.g_5;
+  d.a2m2 = m.a2m2;
+  d.sop_g_n = m.sop_g_n;
+  d.thr = m.thr;
+  d.vx = m.vx;
+  d.vx0 = m.vx0;
+  d.cn = m.cn;
+  d.c5 = m.c5;
+  d.dtk = (float)tau_between(cz, a_lo, a_hi);
+  d.dtd = (float)tau_between(cz, ai, an);
+  d.slice0 = (int64_t)i * L.n_k * 6;
+  d.slice1 = (int64_t)(i + 1) * L.n_k * 6;
+  return d;
+}
+
 // ------------------------------------------------------------------ validation / layout
 static bool is_2a3b(int n) {
   if (n < 2 || n % 2) return false;
@@ -217,6 +268,10 @@ Layout make_layout(const cola_params& p) {
   o = align_up(o + L.scratch_bytes);
   L.off_lpt_coef = o;
   o = align_up(o + (L.kdep ? 2 * (size_t)L.n_k * sizeof(float2) : 0));
+  L.off_steps = o;
+  o = align_up(o + (size_t)p.n_steps * sizeof(StepDev));
+  L.off_ctr = o;
+  o = align_up(o + sizeof(int));
   L.tables_bytes = o;
   const size_t mesh_bytes = align_up(L.mesh_elems * sizeof(float2));
   const size_t pfield_bytes = align_up(L.pgrid_elems * sizeof(float2));

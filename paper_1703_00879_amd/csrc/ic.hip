@@ -282,7 +282,12 @@ void launch_growth_ode(const cola_params& p, const Layout& L, double* table, dou
 
 // ------------------------------------------------------------------ per-step LPT coefficients
 __global__ void k_lpt_coef(const double* __restrict__ table, int64_t slice0, int64_t slice1,
+                           const StepDev* __restrict__ steps, const int* __restrict__ ctr,
                            int64_t n_k, float2* __restrict__ coef) {
+  if (steps) {
+    slice0 = steps[*ctr].slice0;
+    slice1 = steps[*ctr].slice1;
+  }
   for (int64_t k = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; k < n_k;
        k += (int64_t)gridDim.x * blockDim.x) {
     const double* t0 = table + slice0 + 6 * k;
@@ -293,10 +298,11 @@ __global__ void k_lpt_coef(const double* __restrict__ table, int64_t slice0, int
 }
 
 void launch_lpt_coef(const Layout& L, const double* table, int64_t slice0, int64_t slice1,
-                     float2* coef, hipStream_t s) {
+                     const StepDev* steps, const int* ctr, float2* coef, hipStream_t s) {
   ProfScope ps("lpt_coef", s);
   const unsigned g = (unsigned)std::min<int64_t>((L.n_k + 255) / 256, 4096);
-  hipLaunchKernelGGL(k_lpt_coef, dim3(g), dim3(256), 0, s, table, slice0, slice1, L.n_k, coef);
+  hipLaunchKernelGGL(k_lpt_coef, dim3(g), dim3(256), 0, s, table, slice0, slice1, steps, ctr,
+                     L.n_k, coef);
   COLA_LAUNCH_CHECK();
 }
 

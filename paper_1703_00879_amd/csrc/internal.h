@@ -70,7 +70,8 @@ struct Layout {
   int64_t n_k;              // entries per growth-table slice
   int n_steps;
   // offsets (bytes) inside `tables`
-  size_t off_growth, off_ref, off_tw_m, off_tw_p, off_scratch, off_lpt_coef, tables_bytes;
+  size_t off_growth, off_ref, off_tw_m, off_tw_p, off_scratch, off_lpt_coef, off_steps,
+      off_ctr, tables_bytes;
   size_t scratch_bytes;
   // offsets (bytes) inside `work`: six mesh slots (padded half-complex / real meshes);
   // the interleaved force mesh [nm][nm][nm][3] spans slots 3-5, and the sorted CIC
@@ -117,6 +118,32 @@ struct StepScalars {         // PM-force scalars at scale factor a
 StepScalars step_scalars(const cola_params& p, double a);
 double a_of_step(const cola_params& p, int i);
 
+// The PM force's scalars at scale factor a in the form the kernels take them: the force
+// pass's Green's-function coefficients g_n, g_5 and a^2 m^2, the potential-screening X
+// pass's -kappa, and the screening row pass's threshold, Vainshtein prefactor and offset
+// and source weights (cn + c5 eps).  For nDGP (massless fifth force, Sec. 5.2) the row
+// pass folds both sources into (rho - 1)(cn + c5 eps) and the force pass takes that one
+// field with g_n = 1.
+struct PMScalars {
+  float g_n, g_5, a2m2, sop_g_n;
+  float thr, vx, vx0, cn, c5;
+  int screen;      // screening on
+  int potential;   // potential screening (f(R), symmetron); else density (nDGP)
+};
+PMScalars pm_scalars(const cola_params& p, double a);
+
+// Per-step scalars of cola_step i (a_i -> a_{i+1}), built once per run into the tables
+// buffer; the step's kernels read entry [*step counter], so one captured step can be
+// replayed for every step.  Values equal what the same step computes on the host.
+struct StepDev {
+  float g_n, g_5, a2m2, sop_g_n;   // PMScalars at a_i
+  float thr, vx, vx0, cn, c5;
+  float dtk, dtd;                  // kick tau(a_{i+1/2}) - tau(a_{i-1/2}), drift tau(a_{i+1}) - tau(a_i)
+  int32_t pad;
+  int64_t slice0, slice1;          // growth-table element offsets of slices i and i + 1
+};
+StepDev step_dev(const cola_params& p, const Layout& L, int i);
+
 // ------------------------------------------------------------------ k-space operators
 enum KKind : int {
   K_COPY = 0,      // out = scale * a
@@ -136,6 +163,9 @@ struct KOp {
   int64_t tab_slice0 = 0, tab_slice1 = 0;   // element offsets of two slices (K_LPT)
   int lpt_mode = 0;                // 0: X = D''(slice0); 1: X = D(slice1) - D(slice0); 2: X = D(slice0)
   const float2* coef = nullptr;    // K_LPT: the step's (X1, X2) per |nu|^2 in FP32, if built
+  // when set, the step-dependent coefficients (g_n, g_5, a2m2) come from steps[*step_ctr]
+  const StepDev* steps = nullptr;
+  const int* step_ctr = nullptr;
   int comp = 0, comp2 = 0;
   float scale = 1.f;
   float kf = 1.f;                  // 2 pi / L
@@ -184,9 +214,13 @@ void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const fl
 // give S = delta eps; for a massless fifth force (nDGP) cn = g_n and c5 = g_5 fold the
 // Newtonian and fifth-force sources into one field with one Green's function 1/k^2.
 // s_out (optional, padded real) receives S = delta eps.
+struct ScreenArgs {
+  float thr, vx, vx0, cn, c5;      // see PMScalars
+  const StepDev* steps = nullptr;  // when set, the five come from steps[*step_ctr]
+  const int* step_ctr = nullptr;
+};
 void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* dk, float2* data,
-                const float* rho, float* s_out, int model, float thr, float vx, float vx0,
-                float cn, float c5, hipStream_t s);
+                const float* rho, float* s_out, int model, const ScreenArgs& sa, hipStream_t s);
 
 // ------------------------------------------------------------------ kernels (launchers)
 void launch_fill(float* p, size_t n, float v, hipStream_t s);
@@ -212,7 +246,11 @@ void launch_combine_u0(const Layout& L, const float* psi1, const float* psi2,
 // coef[k] = (D1''(a_i), D2''(a_i)) and coef[n_k + k] = (D1(a_i+1) - D1(a_i), D2(a_i+1) -
 // D2(a_i)) (differences taken in FP64), from table slices at element offsets slice0/slice1.
 void launch_lpt_coef(const Layout& L, const double* table, int64_t slice0, int64_t slice1,
-                     float2* coef, hipStream_t s);
+                     const StepDev* steps, const int* ctr, float2* coef, hipStream_t s);
+// step table and counter: steps[i] = v; *ctr = v; *ctr += 1 (single-thread kernels)
+void launch_write_step(StepDev* steps, int i, const StepDev& v, hipStream_t s);
+void launch_set_counter(int* ctr, int v, hipStream_t s);
+void launch_step_advance(int* ctr, hipStream_t s);
 // CIC deposit into the padded real mesh.  `bins` is the work area at off_bins, `entries`
 // the packed per-particle CIC records sorted by home tile (float4 each).
 void launch_deposit(const Layout& L, const float* disp, float* rho_padded, void* bins,
@@ -230,6 +268,8 @@ struct GatherArgs {
   int64_t slice0, slice1;     // element offsets of slices i and i+1
   double dtk, dtd;
   float* force_out;           // cola_pm_force: write F_p instead of updating
+  const StepDev* steps;       // when set, dtk, dtd, slice0, slice1 come from steps[*step_ctr]
+  const int* step_ctr;
 };
 void launch_gather(const Layout& L, const GatherArgs& g, hipStream_t s);
 // the three components of the interleaved force mesh into flat [3][nm^3]

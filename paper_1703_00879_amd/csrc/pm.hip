@@ -507,6 +507,7 @@ struct GatherDev {
   const double* table; int64_t slice0, slice1;
   float dtk, dtd;
   float* force_out;
+  const StepDev* steps; const int* step_ctr;
 };
 
 // F_p = sum_corners W F_j (same CIC weights as the deposit); then
@@ -529,6 +530,13 @@ template <int MODE>
 __global__ void __launch_bounds__(256)
 k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int ppitch,
          int64_t pplane, int bricks) {
+  if (MODE != 2 && g.steps) {
+    const StepDev& sd = g.steps[*g.step_ctr];
+    g.dtk = sd.dtk;
+    g.dtd = sd.dtd;
+    g.slice0 = sd.slice0;
+    g.slice1 = sd.slice1;
+  }
   const unsigned blk = xcd_block(blockIdx.x, gridDim.x);
   int64_t p;
   if (bricks) {
@@ -606,6 +614,8 @@ void launch_gather(const Layout& L, const GatherArgs& a, hipStream_t s) {
   g.table = a.table; g.slice0 = a.slice0; g.slice1 = a.slice1;
   g.dtk = (float)a.dtk; g.dtd = (float)a.dtd;
   g.force_out = a.force_out;
+  g.steps = a.steps;
+  g.step_ctr = a.step_ctr;
   const int ratio = L.nm / L.np;
   const dim3 grid((unsigned)((L.N + 255) / 256)), block(256);
   const int bricks = (L.np % 64 == 0 && L.np % kGatherBrick == 0) ? 1 : 0;
@@ -622,6 +632,24 @@ void launch_gather(const Layout& L, const GatherArgs& a, hipStream_t s) {
     hipLaunchKernelGGL(k_gather<1>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
                        2 * L.pitch_p, 2 * L.plane_p, bricks);
   }
+  COLA_LAUNCH_CHECK();
+}
+
+// ------------------------------------------------------------------ step table and counter
+__global__ void k_write_step(StepDev* steps, int i, StepDev v) { steps[i] = v; }
+__global__ void k_set_counter(int* ctr, int v) { *ctr = v; }
+__global__ void k_step_advance(int* ctr) { *ctr += 1; }
+
+void launch_write_step(StepDev* steps, int i, const StepDev& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_write_step, dim3(1), dim3(1), 0, s, steps, i, v);
+  COLA_LAUNCH_CHECK();
+}
+void launch_set_counter(int* ctr, int v, hipStream_t s) {
+  hipLaunchKernelGGL(k_set_counter, dim3(1), dim3(1), 0, s, ctr, v);
+  COLA_LAUNCH_CHECK();
+}
+void launch_step_advance(int* ctr, hipStream_t s) {
+  hipLaunchKernelGGL(k_step_advance, dim3(1), dim3(1), 0, s, ctr);
   COLA_LAUNCH_CHECK();
 }
 
