@@ -17,7 +17,8 @@ Each model supplies, as functions of wavenumber k [h/Mpc] and scale factor a:
 import numpy as np
 
 from .background import E, omega_m_of_a
-from .params import (MODEL_LCDM, MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, FILTER_GAUSS,
+from .params import (MODEL_LCDM, MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, MODEL_MBETA,
+                     MODEL_KMOUFLAGE, FILTER_GAUSS,
                      FILTER_TOPHAT, FILTER_SHARPK, H0_OVER_C, READ_X_TOTAL_DENSITY, READ_X_NO_A3)
 
 
@@ -151,6 +152,99 @@ def sym_phi_crit(p):
     return 3.0 * p.omega_m / (p.sym_astar ** 3 * p.sym_mass ** 2)
 
 
+# ----------------------------------------------------------------------------- general {m, beta}
+class MBetaTables:
+    """A general {m(a), beta(a)} model (App. C) given as beta and m^2/H0^2 at knots in ln a,
+    interpolated by natural cubic splines of beta(ln a) and ln(m^2/H0^2)(ln a) (scipy's
+    CubicSpline as the library step).  mu = 1 + 2 beta^2 k^2/(k^2 + a^2 m^2);
+    gamma_2^E = m^2 (dm^2/da) beta^2 Om / (2 H0^4 Pi Pi Pi) k^2/(a^4 H^2) with
+    Pi(q) = (q/(a H0))^2 + m^2/H0^2; field equation with C = 2 beta^2 and potential screening
+    by Phi_crit(a) = (9 Om / (2 beta(a))) int_{a_0}^a beta/((m^2/H0^2) a'^4) da', a_0 the first
+    knot with Phi_crit(a_0) = 0 (the App. C integral)."""
+
+    def __init__(self, p):
+        from scipy.interpolate import CubicSpline
+        lna = np.asarray(p.mb_lna, dtype=np.float64)
+        self.om = p.omega_m
+        self.a0 = float(np.exp(lna[0]))
+        self.sb = CubicSpline(lna, np.asarray(p.mb_beta, dtype=np.float64), bc_type="natural")
+        self.sm = CubicSpline(lna, np.log(np.asarray(p.mb_m2, dtype=np.float64)), bc_type="natural")
+        self.dsm = self.sm.derivative()
+
+    def beta(self, a):
+        return self.sb(np.log(a))
+
+    def m2(self, a):
+        """m^2(a)/H0^2."""
+        return np.exp(self.sm(np.log(a)))
+
+    def dm2_da(self, a):
+        return self.m2(a) * self.dsm(np.log(a)) / a
+
+    def a2m2(self, a):
+        return a * a * H0_OVER_C ** 2 * self.m2(a)
+
+    def mu(self, k, a):
+        k2 = np.asarray(k, dtype=np.float64) ** 2
+        b = self.beta(a)
+        return 1.0 + 2.0 * b * b * k2 / (k2 + self.a2m2(a))
+
+    def gamma2E(self, k, k1, k2, a):
+        m2 = self.m2(a)
+        Pi = lambda q: (np.asarray(q, dtype=np.float64) / (a * H0_OVER_C)) ** 2 + m2  # noqa: E731
+        H = E(a, self.om) * H0_OVER_C
+        b = self.beta(a)
+        k = np.asarray(k, dtype=np.float64)
+        return (m2 * self.dm2_da(a) * b * b * self.om / (2.0 * Pi(k) * Pi(k1) * Pi(k2))
+                * k * k / (a ** 4 * H * H))
+
+    def phi_crit(self, a):
+        from scipy import integrate
+        f = lambda x: float(self.beta(x)) / (float(self.m2(x)) * x ** 4)  # noqa: E731
+        I, _ = integrate.quad(f, self.a0, a, epsabs=0.0, epsrel=1e-12, limit=200)
+        return 4.5 * self.om / float(self.beta(a)) * I
+
+
+# ----------------------------------------------------------------------------- k-Mouflage
+# Gradient screening (App. B) for a kinetic function P(X) = -1 + X + K0 X^m (the form is
+# this reading's choice; the paper leaves X*(|grad Phi_N|) to the user):
+# P_X(X*)^2 X* = (lambda |grad Phi_N|)^2, eps = min(1, 1/P_X(X*)); C = 2 beta^2, m(a) = 0;
+# linear growth mu = 1 + 2 beta^2 / P_X(X(a)) with the cosmological X(a) = x0 a^xn, and
+# gamma_2 = 0 (none is given).
+def km_px(X, k0, m):
+    return 1.0 + m * k0 * np.asarray(X, dtype=np.float64) ** (m - 1)
+
+
+def km_xstar(R, k0, m):
+    """X* >= 0 solving P_X(X*)^2 X* = R (R >= 0), by bisection on ln X (the left side
+    increases monotonically); X* = 0 where R = 0."""
+    R = np.asarray(R, dtype=np.float64)
+    out = np.zeros_like(R)
+    pos = R > 0
+    r = R[pos]
+    lo = np.log(r) - 2.0 * np.log(km_px(r, k0, m)) - 1.0    # P_X(X) >= 1: X <= R
+    hi = np.log(r) + 1.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        x = np.exp(mid)
+        f = km_px(x, k0, m) ** 2 * x - r
+        lo = np.where(f < 0, mid, lo)
+        hi = np.where(f < 0, hi, mid)
+    out[pos] = np.exp(0.5 * (lo + hi))
+    return out
+
+
+def eps_kmouflage(grad_phi_n, k0, m, lam):
+    """eps = min(1, 1/P_X(X*)) (App. B) from |grad Phi_N| (h/Mpc)."""
+    R = (lam * np.asarray(grad_phi_n, dtype=np.float64)) ** 2
+    return np.minimum(1.0, 1.0 / km_px(km_xstar(R, k0, m), k0, m))
+
+
+def km_mu(a, p):
+    X = p.km_x0 * a ** p.km_xn
+    return 1.0 + 2.0 * p.km_beta ** 2 / km_px(X, p.km_k0, p.km_m)
+
+
 # ----------------------------------------------------------------------------- dispatch
 class Model:
     """Model functions of a run (bound to its cosmology and model parameters)."""
@@ -160,6 +254,7 @@ class Model:
         self.om = p.omega_m
         self.kind = p.model
         self.lcdm_growth = force_lcdm_growth or (p.growth_mode == 1)
+        self.mb = MBetaTables(p) if p.model == MODEL_MBETA else None
 
     # --- linear growth inputs (App. B: the user supplies mu and gamma_2)
     def mu(self, k, a):
@@ -172,6 +267,10 @@ class Model:
             return np.full_like(k, dgp_mu(a, self.om, self.p.rc_h0))
         if self.kind == MODEL_SYMMETRON:
             return sym_mu(k, a, self.p)
+        if self.kind == MODEL_MBETA:
+            return self.mb.mu(k, a)
+        if self.kind == MODEL_KMOUFLAGE:
+            return np.full_like(k, km_mu(a, self.p))
         raise ValueError(self.kind)
 
     def gamma2_orth(self, k, a):
@@ -186,18 +285,25 @@ class Model:
         if self.kind == MODEL_SYMMETRON:
             kk = k / np.sqrt(2.0)
             return sym_gamma2E(k, kk, kk, a, self.p)
+        if self.kind == MODEL_MBETA:
+            kk = k / np.sqrt(2.0)
+            return self.mb.gamma2E(k, kk, kk, a)
+        if self.kind == MODEL_KMOUFLAGE:
+            return np.zeros_like(k)
         raise ValueError(self.kind)
 
     # --- N-body field equation (Sec. 6, App. B)
     @property
     def has_fifth_force(self):
-        return self.kind in (MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON)
+        return self.kind in (MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, MODEL_MBETA, MODEL_KMOUFLAGE)
 
     def a2m2(self, a):
         if self.kind == MODEL_FR:
             return float(fr_a2m2(a, self.om, self.p.fr0_abs))
         if self.kind == MODEL_SYMMETRON:
             return float(sym_a2m2(a, self.p))
+        if self.kind == MODEL_MBETA:
+            return float(self.mb.a2m2(a))
         return 0.0
 
     def coupling(self, a):
@@ -209,7 +315,22 @@ class Model:
             return float(1.0 / (3.0 * dgp_beta(a, self.om, self.p.rc_h0)))
         if self.kind == MODEL_SYMMETRON:
             return float(2.0 * sym_beta2(a, self.p))   # C = 2 beta^2 (App. B, C)
+        if self.kind == MODEL_MBETA:
+            return float(2.0 * self.mb.beta(a) ** 2)
+        if self.kind == MODEL_KMOUFLAGE:
+            return 2.0 * self.p.km_beta ** 2
         return 0.0
+
+    def phi_crit(self, a):
+        """Critical potential of potential screening (App. C): (3/2)|f_R(a)| for f(R), the
+        App. C integral for the symmetron and for the tabulated {m, beta} model."""
+        if self.kind == MODEL_FR:
+            return 1.5 * float(fr_fR_abs(a, self.om, self.p.fr0_abs))
+        if self.kind == MODEL_SYMMETRON:
+            return sym_phi_crit(self.p)
+        if self.kind == MODEL_MBETA:
+            return self.mb.phi_crit(a)
+        raise ValueError(self.kind)
 
 
 # ----------------------------------------------------------------------------- screening

@@ -15,6 +15,9 @@ MODEL_LCDM = 0
 MODEL_FR = 1      # Hu-Sawicki f(R), n = 1 (Sec. 5.1)
 MODEL_NDGP = 2    # normal-branch DGP (Sec. 5.2)
 MODEL_SYMMETRON = 3   # symmetron, a {m(a), beta(a)} model with potential screening (App. C)
+MODEL_MBETA = 4       # general {m(a), beta(a)} model given as tables (App. C)
+MODEL_KMOUFLAGE = 5   # k-Mouflage: gradient screening (App. B)
+MBETA_MAX_KNOTS = 64
 
 FILTER_GAUSS = 0
 FILTER_TOPHAT = 1
@@ -46,6 +49,21 @@ class Params:
     sym_beta: float = 1.0         # beta_* of the symmetron (App. C)
     sym_mass: float = 2997.92458  # m_*/H0 (m_* = 1 h/Mpc: a 1 Mpc/h range)
     sym_astar: float = 0.5        # a_*: beta = m = 0 before it
+    # general {m(a), beta(a)} model: beta and m^2/H0^2 at knots ln a (ascending, 4 to 64
+    # knots spanning [a_ini, 1]); both sides interpolate with natural cubic splines of
+    # beta and of ln(m^2/H0^2) in ln a
+    mb_lna: tuple = ()
+    mb_beta: tuple = ()
+    mb_m2: tuple = ()
+    # k-Mouflage (App. B) with the kinetic function P(X) = -1 + X + K0 X^m: coupling beta,
+    # K0 and m, the scale lambda (Mpc/h) of P_X(X*)^2 X* = (lambda |grad Phi_N|)^2 with
+    # Phi_N the dimensionless Newtonian potential, and the cosmological X(a) = x0 a^xn
+    km_beta: float = 0.5
+    km_k0: float = 1.0
+    km_m: int = 3
+    km_lambda: float = 1e6
+    km_x0: float = 0.0
+    km_xn: float = 0.0
     screening: int = 1
     filter: int = FILTER_GAUSS
     r_smooth: float = 1.0
@@ -76,11 +94,11 @@ class Params:
 
     @property
     def scale_dependent(self):
-        """True when the LPT growth factors depend on k (Sec. 4): f(R) and the
-        symmetron run with their own growth factors.  LCDM and nDGP have
+        """True when the LPT growth factors depend on k (Sec. 4): f(R), the symmetron and
+        the general {m, beta} model run with their own growth factors.  LCDM and nDGP have
         k-independent D1, D2 (Sec. 5.2), and growth_mode 1 forces the LCDM factors
         (Sec. 7.1)."""
-        return self.model in (MODEL_FR, MODEL_SYMMETRON) and self.growth_mode == 0
+        return self.model in (MODEL_FR, MODEL_SYMMETRON, MODEL_MBETA) and self.growth_mode == 0
 
     def with_(self, **kw):
         return replace(self, **kw)

@@ -27,8 +27,8 @@ from .background import kappa
 from .cola import time_grid
 from .growth import growth_table
 from .models import (Model, eps_chameleon, eps_potential, eps_vainshtein, vainshtein_x, window,
-                     fr_fR_abs, dgp_beta, sym_phi_crit)
-from .params import MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, H0_OVER_C
+                     fr_fR_abs, dgp_beta)
+from .params import MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, MODEL_MBETA, H0_OVER_C
 
 
 def _cic_1d(s, n):
@@ -66,12 +66,12 @@ def planar_pm(u1, p, a, model=None):
     S = delta
     if model.has_fifth_force:
         if p.screening:
-            if p.model in (MODEL_FR, MODEL_SYMMETRON):
+            if p.model in (MODEL_FR, MODEL_SYMMETRON, MODEL_MBETA):
                 phi_n = np.fft.ifft(-kap * dk * inv_k2).real * H0_OVER_C ** 2 / (a * a)
                 if p.model == MODEL_FR:
                     eps = eps_chameleon(phi_n, fr_fR_abs(a, p.omega_m, p.fr0_abs))
                 else:
-                    eps = eps_potential(phi_n, sym_phi_crit(p))
+                    eps = eps_potential(phi_n, model.phi_crit(a))
             elif p.model == MODEL_NDGP:
                 dR = np.fft.ifft(dk * window(np.abs(k) * p.r_smooth, p.filter)).real
                 beta = dgp_beta(a, p.omega_m, p.rc_h0)

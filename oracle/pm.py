@@ -25,9 +25,10 @@ from . import fftlib
 
 from .background import kappa
 from .lpt import grad_factor, inv_laplacian, kvec
-from .models import (Model, eps_chameleon, eps_potential, eps_vainshtein, vainshtein_x, window,
-                     fr_fR_abs, dgp_beta, sym_phi_crit)
-from .params import MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, H0_OVER_C
+from .models import (Model, eps_chameleon, eps_potential, eps_vainshtein, eps_kmouflage,
+                     vainshtein_x, window,
+                     fr_fR_abs, dgp_beta)
+from .params import MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, MODEL_MBETA, MODEL_KMOUFLAGE, H0_OVER_C
 
 
 def lagrangian_index(n_p):
@@ -97,13 +98,18 @@ def screened_source(delta, delta_k, p, a, model):
     n, L = p.nmesh1d, p.box
     if not p.screening or not model.has_fifth_force:
         return delta.copy()
-    if p.model in (MODEL_FR, MODEL_SYMMETRON):
+    if p.model in (MODEL_FR, MODEL_SYMMETRON, MODEL_MBETA):
         Phi = fftlib.irfftn(-kappa(a, p.omega_m) * delta_k * inv_laplacian(n, L), n)
         phi_n = Phi * H0_OVER_C ** 2 / (a * a)
         if p.model == MODEL_FR:
             eps = eps_chameleon(phi_n, fr_fR_abs(a, p.omega_m, p.fr0_abs))
         else:
-            eps = eps_potential(phi_n, sym_phi_crit(p))
+            eps = eps_potential(phi_n, model.phi_crit(a))
+    elif p.model == MODEL_KMOUFLAGE:
+        # gradient screening (App. B): |grad Phi_N| of the dimensionless Newtonian potential
+        Phi_k = -kappa(a, p.omega_m) * delta_k * inv_laplacian(n, L)
+        g2 = sum(fftlib.irfftn(grad_factor(n, L, ax) * Phi_k, n) ** 2 for ax in range(3))
+        eps = eps_kmouflage(np.sqrt(g2) * H0_OVER_C ** 2 / (a * a), p.km_k0, p.km_m, p.km_lambda)
     elif p.model == MODEL_NDGP:
         (kx, ky, kz), _ = kvec(n, L)
         k = np.sqrt(kx * kx + ky * ky + kz * kz)

@@ -29,7 +29,7 @@ import numpy as np
 from .background import E, kappa, dlna_dtau, omega_m_of_a
 from .growth import _integrate_pieces, growth_breaks, solve_growth
 from .models import Model, fr_gamma2E, dgp_gamma2E_orth, sym_gamma2E
-from .params import MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON
+from .params import MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, MODEL_MBETA
 
 
 def cos_theta(k, k1, k2):
@@ -40,8 +40,10 @@ def gamma2E(model, k, k1, k2, a):
     """gamma_2^E of the model at the triangle (Secs. 5.1-5.2, App. C); zero for LCDM and
     for runs with LCDM growth factors."""
     k, k1, k2 = (np.asarray(x, dtype=np.float64) for x in (k, k1, k2))
-    if model.lcdm_growth or model.kind not in (MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON):
+    if model.lcdm_growth or model.kind not in (MODEL_FR, MODEL_NDGP, MODEL_SYMMETRON, MODEL_MBETA):
         return np.zeros_like(k)
+    if model.kind == MODEL_MBETA:
+        return model.mb.gamma2E(k, k1, k2, a)
     if model.kind == MODEL_FR:
         return fr_gamma2E(k, k1, k2, a, model.om, model.p.fr0_abs)
     if model.kind == MODEL_SYMMETRON:
@@ -88,13 +90,13 @@ def solve_d2_triangle(k, k1, k2, a_out, p, rtol=1e-12, atol=1e-14):
     return out
 
 
-def approx_d2_triangle(k, k1, k2, a_out, p):
+def approx_d2_triangle(k, k1, k2, a_out, p, rtol=1e-12, atol=1e-14):
     """The approximation D2_hat(k, a)(1 - cos^2 theta), shape (len(a_out), n)."""
     model = Model(p)
     k, k1, k2 = (np.atleast_1d(np.asarray(x, dtype=np.float64)) for x in (k, k1, k2))
     c = cos_theta(k, k1, k2)
     G = solve_growth(k, np.atleast_1d(a_out), p.omega_m, model.mu, model.gamma2_orth, p.a_ini,
-                     breaks=growth_breaks(p, model))
+                     rtol=rtol, atol=atol, breaks=growth_breaks(p, model))
     return G[:, :, 3] * (1.0 - c * c)
 
 
