@@ -125,7 +125,12 @@ def _mock_params(C, rng, j, sizes, seed0, n_steps):
 def bench_ensemble(C, torch, boxes=64, budget=160 << 30):
     """A mixed ensemble of small boxes (seeded draw, seed 4: n_p in {64, 96, 128, 192,
     256}, 10 steps) run one at a time on one stream, then all resident at once and
-    interleaved on eight streams; aggregate particle-steps/s and yardstick HBM fraction."""
+    interleaved on eight streams, then all resident and stepped as captured HIP graphs
+    (cola_ensemble_run: one step of every box per graph, a branch per box over eight
+    capture streams, replayed for the ten steps); aggregate particle-steps/s and
+    yardstick HBM fraction.  Every leg's time runs from the first allocation to the end
+    of the last step, initial conditions included; the graph leg also reports its steps
+    alone."""
     import numpy as np
     from paper_1703_00879_amd.serve import GpuEngine, Request, Server, summarize
     rng = np.random.default_rng(4)
@@ -139,32 +144,68 @@ def bench_ensemble(C, torch, boxes=64, budget=160 << 30):
         out[name] = {"seconds": sm["span_s"], "particle_steps_per_s": sm["particle_steps_per_s"],
                      "hbm_frac_yardstick": yard / sm["span_s"] / 1e9 / HBM_PEAK_GBS}
         torch.cuda.empty_cache()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    states = [C.State(p, device="cuda:0") for p in ps]
+    ic_streams = [torch.cuda.Stream() for _ in range(8)]
+    for j, (p, st) in enumerate(zip(ps, states)):   # initial conditions overlap on 8 streams
+        C.cola_make_ic(p, st, stream=ic_streams[j % 8].cuda_stream)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    ens = C.Ensemble(ps, states)
+    ens.run(n_streams=8)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    ens.close()
+    ps_total = out["particle_steps"]
+    out["graph_8_streams"] = {"seconds": t2 - t0, "particle_steps_per_s": ps_total / (t2 - t0),
+                              "hbm_frac_yardstick": yard / (t2 - t0) / 1e9 / HBM_PEAK_GBS,
+                              "steps_seconds": t2 - t1,
+                              "steps_particle_steps_per_s": ps_total / (t2 - t1),
+                              "steps_hbm_frac_yardstick": yard / (t2 - t1) / 1e9 / HBM_PEAK_GBS}
+    del states, ens
+    torch.cuda.empty_cache()
     return out
 
 
-def bench_serving(C, torch, requests=96, budget=96 << 30):
+def bench_serving(C, torch, requests=96, budget=96 << 30, rates=(0.5, 0.8, 1.0)):
     """A Poisson stream of mock requests (n_p in {128, 256, 384}, 10-30 steps, models and
     parameters as the ensemble, seed = 100000 + j) through the serving loop: first all at
-    once to measure the saturation rate, then arriving at 0.8 of it (arrival RNG seed 5).
-    Reports runs/hour and p50 / p99 time to z = 0."""
+    once to measure the saturation rate, then arriving at 0.5, 0.8 and 1.0 of it (arrival
+    RNG seed 5).  Reports runs/hour and p50 / p99 time to z = 0 at each rate."""
     import numpy as np
     from paper_1703_00879_amd.serve import GpuEngine, Request, Server, summarize
     rng = np.random.default_rng(5)
     ps = [_mock_params(C, rng, j, (128, 256, 384), 100000, rng.integers(10, 31))
           for j in range(requests)]
     srv = Server(GpuEngine(n_streams=4), budget, max_active=16)
-    sat = summarize(srv.run([Request(p, 0.0, j) for j, p in enumerate(ps)]))
+
+    def progress(done, total):
+        if done % 50 == 0 or done == total:
+            print(f"[bench] serving: {done}/{total} runs done", file=sys.stderr, flush=True)
+
+    sat = summarize(srv.run([Request(p, 0.0, j) for j, p in enumerate(ps)], on_result=progress))
     torch.cuda.empty_cache()
-    lam = 0.8 * sat["runs"] / sat["span_s"]
-    t = np.cumsum(rng.exponential(1.0 / lam, size=requests))
-    t -= t[0]
-    st = summarize(srv.run([Request(p, float(a), j) for j, (p, a) in enumerate(zip(ps, t))]))
-    torch.cuda.empty_cache()
-    return {"requests": requests, "saturation_runs_per_hour": sat["runs_per_hour"],
-            "arrival_rate_per_s": lam, "runs_per_hour": st["runs_per_hour"],
-            "p50_time_to_z0_s": st["p50_s"], "p99_time_to_z0_s": st["p99_s"],
-            "particle_steps_per_s": st["particle_steps_per_s"],
-            "saturation_p99_time_to_z0_s": sat["p99_s"]}
+    gaps = rng.exponential(1.0, size=requests)   # unit-rate Poisson gaps, scaled per rate
+    out = {"requests": requests, "saturation_runs_per_hour": sat["runs_per_hour"],
+           "saturation_p50_time_to_z0_s": sat["p50_s"], "saturation_p99_time_to_z0_s": sat["p99_s"],
+           "rates": {}}
+    for f in rates:
+        lam = f * sat["runs"] / sat["span_s"]
+        t = np.cumsum(gaps / lam)
+        t -= t[0]
+        st = summarize(srv.run([Request(p, float(a), j) for j, (p, a) in enumerate(zip(ps, t))],
+                               on_result=progress))
+        torch.cuda.empty_cache()
+        out["rates"][f"{f:g}"] = {"arrival_rate_per_s": lam, "runs_per_hour": st["runs_per_hour"],
+                                  "p50_time_to_z0_s": st["p50_s"], "p99_time_to_z0_s": st["p99_s"],
+                                  "particle_steps_per_s": st["particle_steps_per_s"]}
+    # the headline serving figures: 0.8 of saturation
+    r8 = out["rates"].get("0.8")
+    if r8:
+        out.update(runs_per_hour=r8["runs_per_hour"], p50_time_to_z0_s=r8["p50_time_to_z0_s"],
+                   p99_time_to_z0_s=r8["p99_time_to_z0_s"])
+    return out
 
 
 def source_hash():
@@ -330,7 +371,26 @@ def summarize_rocprof(d, out_dir, steps, warmup=0):
     return traffic
 
 
-def cpu_baseline(steps=2):
+def host_cpu_model():
+    """Host CPU as /proc/cpuinfo names it (model name, family, model, stepping) and the
+    logical CPUs the process may use / the host has."""
+    info = {}
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                k, _, v = line.partition(":")
+                k = k.strip()
+                if k in ("model name", "cpu family", "model", "stepping") and k not in info:
+                    info[k] = v.strip()
+    except OSError:
+        pass
+    name = info.get("model name", "unknown host CPU")
+    return (f"{name} (family {info.get('cpu family', '?')}, model {info.get('model', '?')}, "
+            f"stepping {info.get('stepping', '?')}); {len(os.sched_getaffinity(0))} of "
+            f"{os.cpu_count()} logical CPUs available")
+
+
+def cpu_baseline(steps=6):
     """The FP64 oracle on the host, on a bounded sample of the headline workload: F5 with
     scale-dependent growth, screened, on a 128^3-particle / 256^3-mesh / 256 Mpc/h sub-box
     (the workload's 2 Mpc/h particle spacing and 1 Mpc/h cells, its 20-step time grid and
@@ -342,12 +402,7 @@ def cpu_baseline(steps=2):
     from oracle.cola import Run
     p = oracle.Params(model=oracle.MODEL_FR, fr0_abs=1e-5, screening=1, growth_mode=0,
                       np1d=128, nmesh1d=256, box=256.0, z_init=19.0, n_steps=20, seed=1)
-    host = "unknown host CPU"
-    try:
-        with open("/proc/cpuinfo") as f:
-            host = next(l.split(":", 1)[1].strip() for l in f if l.startswith("model name"))
-    except (OSError, StopIteration):
-        pass
+    host = host_cpu_model()
     cores = len(os.sched_getaffinity(0))
     res = {}
     for w in (1, cores):
@@ -507,6 +562,8 @@ def main():
                     help="only the headline run (what the rocprofv3 summary profiles)")
     ap.add_argument("--serve-requests", type=int, default=96,
                     help="requests in the serving stream (500 for the full stream)")
+    ap.add_argument("--serving-only", action="store_true",
+                    help="only the serving sweep (with --serve-requests), printed as JSON")
     ap.add_argument("--no-profile", action="store_true",
                     help="do not record per-kernel HIP events in the timed region")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
@@ -543,6 +600,11 @@ def main():
 
     def log(msg):
         print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+    if args.serving_only:
+        torch.cuda.set_device(0)
+        print(json.dumps({"serving": bench_serving(C, torch, requests=args.serve_requests)}))
+        return
 
     torch.cuda.set_device(0)
     p = workload_params(C)

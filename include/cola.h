@@ -41,11 +41,15 @@ typedef int32_t cola_status;
 #define COLA_E_UNSUPPORTED (-5)  /* valid request this build does not implement */
 
 /* Gravity models (Sec. 5, App. C): LCDM, Hu-Sawicki f(R) with n = 1, normal-branch DGP,
- * and the symmetron, a {m(a), beta(a)} model with potential screening. */
+ * the symmetron, and the general {m(a), beta(a)} model given by tables, both of the
+ * latter with potential screening. */
 #define COLA_LCDM 0
 #define COLA_FR_HS1 1
 #define COLA_NDGP 2
 #define COLA_SYMMETRON 3
+#define COLA_MBETA 4        /* general {m(a), beta(a)} model given as tables (App. C) */
+#define COLA_KMOUFLAGE 5    /* k-Mouflage: gradient screening (App. B) */
+#define COLA_MBETA_MAX_KNOTS 64
 
 /* Fourier-space smoothing windows for density (Vainshtein) screening (App. B). */
 #define COLA_SMOOTH_GAUSS 0
@@ -75,7 +79,10 @@ typedef int32_t cola_status;
  * box > 0, z_init > 0,
  * 1 <= n_steps <= 4096, fr0_abs > 0 for f(R), rc_h0 > 0 for nDGP, sym_beta >= 0,
  * sym_mass > 0 and 0 < sym_astar < 1 for the symmetron, r_smooth >= 0, filter in 0..2,
- * model in 0..3, growth_mode in 0..1, screening in 0..1, readings & ~COLA_READ_ALL = 0. */
+ * model in 0..5, growth_mode in 0..1, screening in 0..1, readings & ~COLA_READ_ALL = 0;
+ * for COLA_KMOUFLAGE km_beta >= 0, km_k0 > 0, 2 <= km_m <= 8, km_lambda >= 0, km_x0 >= 0;
+ * for COLA_MBETA 4 <= mb_n <= COLA_MBETA_MAX_KNOTS, mb_lna strictly ascending with
+ * mb_lna[0] <= ln a_ini and mb_lna[mb_n - 1] >= 0, mb_beta >= 0, mb_m2 > 0, all finite. */
 typedef struct cola_params {
   double omega_m, omega_b, h, n_s, sigma8, t_cmb;
   double fr0_abs;     /* |f_R0| of Hu-Sawicki f(R) (Sec. 5.1) */
@@ -94,6 +101,23 @@ typedef struct cola_params {
   double sym_beta;    /* beta_star */
   double sym_mass;    /* m_star / H0 (dimensionless; 2997.92458 is a 1 Mpc/h range) */
   double sym_astar;   /* a_star */
+  /* general {m(a), beta(a)} model (App. C): beta(a) and m^2(a)/H0^2 at mb_n knots ln a;
+   * interpolated by natural cubic splines of beta and of ln(m^2/H0^2) in ln a.  mu =
+   * 1 + 2 beta^2 k^2/(k^2 + a^2 m^2), gamma_2^E from m^2, dm^2/da and beta (App. C), the
+   * field equation couples with C = 2 beta^2 and screens with eps = min(1, |Phi_crit/Phi_N|),
+   * Phi_crit(a) = (9 Omega_m / (2 beta(a))) int_{a_0}^{a} beta / ((m^2/H0^2) a'^4) da' from the
+   * first knot a_0 (where Phi_crit = 0), by quadrature */
+  int32_t mb_n, mb_reserved;
+  double mb_lna[COLA_MBETA_MAX_KNOTS];
+  double mb_beta[COLA_MBETA_MAX_KNOTS];
+  double mb_m2[COLA_MBETA_MAX_KNOTS];
+  /* k-Mouflage (App. B) with the kinetic function P(X) = -1 + X + km_k0 X^km_m: the fifth
+   * force is massless with C = 2 km_beta^2 and screened by eps = min(1, 1/P_X(X*)), where
+   * P_X(X*)^2 X* = (km_lambda |grad Phi_N|)^2, Phi_N the dimensionless Newtonian potential
+   * and km_lambda in Mpc/h; linear growth mu = 1 + 2 km_beta^2 / P_X(X(a)) with the
+   * cosmological X(a) = km_x0 a^km_xn, gamma_2 = 0 */
+  double km_beta, km_k0, km_lambda, km_x0, km_xn;
+  int32_t km_m, km_reserved;
 } cola_params;
 
 /* Byte sizes of the caller-owned device buffers of one state. */

@@ -16,7 +16,8 @@ _PKG = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.environ.get("COLA_LIBRARY") or os.path.join(_PKG, "_lib", "libcola.so")
 
 COLA_OK = 0
-LCDM, FR_HS1, NDGP, SYMMETRON = 0, 1, 2, 3
+LCDM, FR_HS1, NDGP, SYMMETRON, MBETA, KMOUFLAGE = 0, 1, 2, 3, 4, 5
+MBETA_MAX_KNOTS = 64
 SMOOTH_GAUSS, SMOOTH_TOPHAT, SMOOTH_SHARPK = 0, 1, 2
 READ_X_TOTAL_DENSITY, READ_X_NO_A3, READ_D2_HALF_K = 1, 2, 4
 
@@ -45,7 +46,15 @@ class _Params(ctypes.Structure):
                 ("np1d", ctypes.c_int32), ("nmesh1d", ctypes.c_int32),
                 ("n_steps", ctypes.c_int32), ("readings", ctypes.c_int32),
                 ("sym_beta", ctypes.c_double), ("sym_mass", ctypes.c_double),
-                ("sym_astar", ctypes.c_double)]
+                ("sym_astar", ctypes.c_double),
+                ("mb_n", ctypes.c_int32), ("mb_reserved", ctypes.c_int32),
+                ("mb_lna", ctypes.c_double * MBETA_MAX_KNOTS),
+                ("mb_beta", ctypes.c_double * MBETA_MAX_KNOTS),
+                ("mb_m2", ctypes.c_double * MBETA_MAX_KNOTS),
+                ("km_beta", ctypes.c_double), ("km_k0", ctypes.c_double),
+                ("km_lambda", ctypes.c_double), ("km_x0", ctypes.c_double),
+                ("km_xn", ctypes.c_double), ("km_m", ctypes.c_int32),
+                ("km_reserved", ctypes.c_int32)]
 
 
 class _Sizes(ctypes.Structure):
@@ -86,12 +95,31 @@ class Params:
     nmesh1d: int = 64
     n_steps: int = 10
     readings: int = 0
+    # general {m(a), beta(a)} model: knots ln a, beta and m^2/H0^2 there (tuples)
+    mb_lna: tuple = ()
+    mb_beta: tuple = ()
+    mb_m2: tuple = ()
+    # k-Mouflage: P(X) = -1 + X + km_k0 X^km_m, coupling, lambda (Mpc/h), X(a) = km_x0 a^km_xn
+    km_beta: float = 0.5
+    km_k0: float = 1.0
+    km_m: int = 3
+    km_lambda: float = 1e6
+    km_x0: float = 0.0
+    km_xn: float = 0.0
 
     def with_(self, **kw):
         return replace(self, **kw)
 
     def _c(self):
-        return _Params(**{f.name: getattr(self, f.name) for f in fields(self)})
+        kw = {f.name: getattr(self, f.name) for f in fields(self) if not f.name.startswith("mb_")}
+        c = _Params(**kw)
+        n = len(self.mb_lna)
+        if not (len(self.mb_beta) == n and len(self.mb_m2) == n and n <= MBETA_MAX_KNOTS):
+            raise ValueError("mb_lna, mb_beta and mb_m2 need equal lengths <= MBETA_MAX_KNOTS")
+        c.mb_n = n
+        for i in range(n):
+            c.mb_lna[i], c.mb_beta[i], c.mb_m2[i] = self.mb_lna[i], self.mb_beta[i], self.mb_m2[i]
+        return c
 
 
 _lib = None

@@ -233,7 +233,30 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
   op.g_5 = sc.g_5;
   op.a2m2 = sc.a2m2;
   op.scale = invM;
-  if (sc.screen) {
+  if (sc.screen && sc.gradient) {
+    // gradient screening (k-Mouflage, App. B): the Newtonian force mesh gives
+    // |grad Phi_N|; the density is deposited again (bitwise the same) and the row kernel
+    // forms (rho - 1)(cn + c5 eps); the massless fifth force then shares 1/k^2
+    KOp nop = base;
+    nop.g_n = sc.cn;
+    nop.scale = invM;
+    nop.step_newton = 1;
+    float2* const w0[3] = {M[0], M[1], M[2]};
+    fft_c2r_force3(pl, nop, nullptr, M[1], w0, b.force, s);
+    launch_deposit(L, disp, R(M[0]), b.bins, b.entries, s);
+    KmArgs ka;
+    ka.km_r = sc.km_r;
+    ka.k0 = (float)p.km_k0;
+    ka.m = p.km_m;
+    ka.cn = sc.cn;
+    ka.c5 = sc.c5;
+    ka.steps = steps;
+    ka.step_ctr = ctr;
+    launch_kmouflage_source(L, R(M[0]), b.force, R(M[1]), flat_out ? R(M[2]) : nullptr, ka, s);
+    if (flat_out) launch_unpad_mesh(L, R(M[2]), flat_out + L.M, s);
+    fft_r2c_zy(pl, R(M[1]), M[1], s);
+    src = M[1];
+  } else if (sc.screen) {
     KOp sop = base;
     sop.scale = invM;
     int kind = K_SMOOTH;

@@ -419,9 +419,9 @@ k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
   constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
   if (op.steps) {
     const StepDev& sd = op.steps[*op.step_ctr];
-    op.g_n = sd.g_n;
-    op.g_5 = sd.g_5;
-    op.a2m2 = sd.a2m2;
+    op.g_n = op.step_newton ? sd.cn : sd.g_n;
+    op.g_5 = op.step_newton ? 0.f : sd.g_5;
+    op.a2m2 = op.step_newton ? 0.f : sd.a2m2;
   }
   constexpr int R0 = Plan<N>::rad[0], NB0 = E / R0;
   static_assert(T % B == 0, "a thread's butterflies must share one column");
@@ -1050,7 +1050,7 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
     ProfScope ps("fft_z_screen", s);
     constexpr int BR = RowCfg<N / 2>::B;
     const dim3 g((unsigned)((rows + BR - 1) / BR)), b(RowCfg<N / 2>::T);
-    if (model == COLA_FR_HS1 || model == COLA_SYMMETRON)   // eps = min(1, thr/|Phi|)
+    if (model == COLA_FR_HS1 || model == COLA_SYMMETRON || model == COLA_MBETA)   // eps = min(1, thr/|Phi|)
       hipLaunchKernelGGL((k_fft_screen_row<N / 2, COLA_FR_HS1>), g, b, 0, s, data, rho, s_out, rows, n,
                          P, pl.plane, pl.tw, sa);
     else

@@ -113,6 +113,55 @@ double sigma8_norm(const cola_params& p) {
   return p.sigma8 * p.sigma8 / I;
 }
 
+// ------------------------------------------------------------------ general {m, beta} tables
+// Natural cubic spline through (x_i, y_i): second derivatives M with M_0 = M_{n-1} = 0 from
+// the tridiagonal continuity equations, by the Thomas algorithm.
+static void natural_spline(int n, const double* x, const double* y, double* M) {
+  std::vector<double> c(n, 0.0), d(n, 0.0);
+  M[0] = M[n - 1] = 0.0;
+  for (int i = 1; i < n - 1; ++i) {
+    const double h0 = x[i] - x[i - 1], h1 = x[i + 1] - x[i];
+    const double a = h0, b = 2.0 * (h0 + h1), cc = h1;
+    const double r = 6.0 * ((y[i + 1] - y[i]) / h1 - (y[i] - y[i - 1]) / h0);
+    const double den = b - a * (i > 1 ? c[i - 1] : 0.0);
+    c[i] = cc / den;
+    d[i] = (r - a * (i > 1 ? d[i - 1] : 0.0)) / den;
+  }
+  for (int i = n - 2; i >= 1; --i) M[i] = d[i] - c[i] * (i + 1 < n - 1 ? M[i + 1] : 0.0);
+}
+
+MBSpline mb_spline(const cola_params& p) {
+  MBSpline s{};
+  if (p.model != COLA_MBETA) return s;
+  s.n = p.mb_n;
+  for (int i = 0; i < s.n; ++i) {
+    s.x[i] = p.mb_lna[i];
+    s.yb[i] = p.mb_beta[i];
+    s.ym[i] = std::log(p.mb_m2[i]);
+  }
+  natural_spline(s.n, s.x, s.yb, s.Mb);
+  natural_spline(s.n, s.x, s.ym, s.Mm);
+  return s;
+}
+
+// Phi_crit(a) of App. C, (9 Om / (2 beta(a))) int_{a_0}^{a} beta / ((m^2/H0^2) a'^4) da',
+// by Gauss-Legendre panels of width <= 0.01 in ln a' (the integrand there is
+// beta / ((m^2/H0^2) a'^3))
+static double mb_phi_crit(const cola_params& p, const MBSpline& s, double a) {
+  const double l0 = s.x[0], l1 = std::log(a);
+  if (!(l1 > l0)) return 0.0;
+  const int panels = std::max(1, (int)std::ceil((l1 - l0) / 0.01));
+  const double I = integrate([&](double lna) {
+    const double x = std::exp(lna);
+    double b, m2, dm2;
+    mb_eval(s, x, b, m2, dm2);
+    return b / (m2 * x * x * x);
+  }, l0, l1, panels);
+  double b, m2, dm2;
+  mb_eval(s, a, b, m2, dm2);
+  return 4.5 * p.omega_m / b * I;
+}
+
 // ------------------------------------------------------------------ model scalars
 StepScalars step_scalars(const cola_params& p, double a) {
   StepScalars s{};
@@ -120,7 +169,8 @@ StepScalars step_scalars(const cola_params& p, double a) {
   const double E = std::sqrt(om / (a * a * a) + ol);
   s.a = a;
   s.kappa = (float)(1.5 * om * a);
-  s.fifth = (p.model == COLA_FR_HS1 || p.model == COLA_NDGP || p.model == COLA_SYMMETRON) ? 1 : 0;
+  s.fifth = (p.model == COLA_FR_HS1 || p.model == COLA_NDGP || p.model == COLA_SYMMETRON ||
+             p.model == COLA_MBETA || p.model == COLA_KMOUFLAGE) ? 1 : 0;
   s.screen = s.fifth && p.screening;
   if (p.model == COLA_FR_HS1) {
     const double X = om / (a * a * a) + 4.0 * ol, Y = om + 4.0 * ol;
@@ -138,6 +188,17 @@ StepScalars step_scalars(const cola_params& p, double a) {
     s.coupling = (float)(2.0 * p.sym_beta * p.sym_beta * sv);
     const double phi_crit = 3.0 * om / (p.sym_astar * p.sym_astar * p.sym_astar * p.sym_mass * p.sym_mass);
     s.cham_thr = (float)(phi_crit * a * a / (kH0c * kH0c));
+  } else if (p.model == COLA_MBETA) {
+    // App. C: C = 2 beta^2, a^2 m^2, and the threshold Phi_crit a^2/(H0/c)^2 on the code
+    // potential with Phi_crit from the App. C integral
+    const MBSpline sp = mb_spline(p);
+    double b, m2, dm2;
+    mb_eval(sp, a, b, m2, dm2);
+    s.a2m2 = (float)(a * a * kH0c * kH0c * m2);
+    s.coupling = (float)(2.0 * b * b);
+    s.cham_thr = (float)(mb_phi_crit(p, sp, a) * a * a / (kH0c * kH0c));
+  } else if (p.model == COLA_KMOUFLAGE) {   // App. B: massless, C = 2 beta^2
+    s.coupling = (float)(2.0 * p.km_beta * p.km_beta);
   } else if (p.model == COLA_NDGP) {
     const double oma = om / (a * a * a) / (E * E);
     const double beta = 1.0 + 2.0 * p.rc_h0 * E * (1.0 - 0.5 * oma);
@@ -163,7 +224,12 @@ PMScalars pm_scalars(const cola_params& p, double a) {
   s.cn = 0.f;
   s.c5 = 1.f;
   s.screen = sc.screen;
-  s.potential = (p.model == COLA_FR_HS1 || p.model == COLA_SYMMETRON) ? 1 : 0;
+  s.potential = (p.model == COLA_FR_HS1 || p.model == COLA_SYMMETRON || p.model == COLA_MBETA) ? 1 : 0;
+  s.gradient = p.model == COLA_KMOUFLAGE ? 1 : 0;
+  {
+    const double f = p.km_lambda * kH0c * kH0c / (a * a);
+    s.km_r = s.gradient ? (float)(f * f) : 0.f;
+  }
   if (s.screen) {
     if (s.potential) {
       s.sop_g_n = -sc.kappa;
@@ -194,6 +260,7 @@ StepDev step_dev(const cola_params& p, const Layout& L, int i) {
   d.vx0 = m.vx0;
   d.cn = m.cn;
   d.c5 = m.c5;
+  d.km_r = m.km_r;
   d.dtk = (float)tau_between(cz, a_lo, a_hi);
   d.dtd = (float)tau_between(cz, ai, an);
   d.slice0 = (int64_t)i * L.n_k * 6;
@@ -215,7 +282,25 @@ void validate(const cola_params& p) {
   if (!(p.omega_b >= 0 && p.omega_b < p.omega_m)) bad("omega_b must be in [0, omega_m)");
   if (!(p.h > 0) || !(p.sigma8 > 0) || !(p.t_cmb > 0)) bad("h, sigma8 and t_cmb must be > 0");
   if (!std::isfinite(p.n_s)) bad("n_s must be finite");
-  if (p.model < 0 || p.model > 3) bad("model must be 0 (LCDM), 1 (f(R)), 2 (nDGP) or 3 (symmetron)");
+  if (p.model < 0 || p.model > 5)
+    bad("model must be 0 (LCDM), 1 (f(R)), 2 (nDGP), 3 (symmetron), 4 (tabulated {m, beta}) or "
+        "5 (k-Mouflage)");
+  if (p.model == COLA_KMOUFLAGE &&
+      !(p.km_beta >= 0 && p.km_k0 > 0 && p.km_m >= 2 && p.km_m <= 8 && p.km_lambda >= 0 &&
+        p.km_x0 >= 0 && std::isfinite(p.km_xn) && std::isfinite(p.km_beta) &&
+        std::isfinite(p.km_k0) && std::isfinite(p.km_lambda) && std::isfinite(p.km_x0)))
+    bad("k-Mouflage needs km_beta >= 0, km_k0 > 0, 2 <= km_m <= 8, km_lambda >= 0, km_x0 >= 0");
+  if (p.model == COLA_MBETA) {
+    if (p.mb_n < 4 || p.mb_n > COLA_MBETA_MAX_KNOTS) bad("mb_n must be in [4, COLA_MBETA_MAX_KNOTS]");
+    for (int i = 0; i < p.mb_n; ++i) {
+      if (!std::isfinite(p.mb_lna[i]) || !std::isfinite(p.mb_beta[i]) || !std::isfinite(p.mb_m2[i]))
+        bad("mb tables must be finite");
+      if (i > 0 && !(p.mb_lna[i] > p.mb_lna[i - 1])) bad("mb_lna must be strictly ascending");
+      if (!(p.mb_beta[i] >= 0) || !(p.mb_m2[i] > 0)) bad("mb_beta must be >= 0 and mb_m2 > 0");
+    }
+    if (!(p.mb_lna[0] <= -std::log1p(p.z_init) + 1e-12) || !(p.mb_lna[p.mb_n - 1] >= 0))
+      bad("mb_lna must span [ln a_ini, 0]");
+  }
   if (p.model == COLA_SYMMETRON &&
       !(p.sym_beta >= 0 && p.sym_mass > 0 && p.sym_astar > 0 && p.sym_astar < 1))
     bad("symmetron needs sym_beta >= 0, sym_mass > 0, 0 < sym_astar < 1");
@@ -251,7 +336,8 @@ Layout make_layout(const cola_params& p) {
   L.plane_m = plane_stride(L.nm);
   L.pgrid_elems = (size_t)L.np * L.plane_p;
   L.mesh_elems = (size_t)L.nm * L.plane_m;
-  L.kdep = ((p.model == COLA_FR_HS1 || p.model == COLA_SYMMETRON) && p.growth_mode == 0);
+  L.kdep = ((p.model == COLA_FR_HS1 || p.model == COLA_SYMMETRON || p.model == COLA_MBETA) &&
+            p.growth_mode == 0);
   L.n_k = L.kdep ? 3 * (int64_t)(L.np / 2) * (L.np / 2) + 1 : 1;
   L.n_steps = p.n_steps;
   size_t o = 0;
@@ -290,7 +376,9 @@ Layout make_layout(const cola_params& p) {
   L.off_bins = o;
   o += bins_bytes(L.ntiles);
   const size_t entries_bytes = align_up((size_t)L.N * sizeof(float4));
-  if (entries_bytes <= mesh_bytes) {
+  // k-Mouflage deposits a second time while the Newtonian force mesh (over slots 3-5) is
+  // still needed, so its records get their own area
+  if (entries_bytes <= mesh_bytes && p.model != COLA_KMOUFLAGE) {
     L.off_entries = L.off_mesh[5];   // dead before the force mesh is written
   } else {
     L.off_entries = o;

@@ -26,6 +26,8 @@ constexpr double kH0c = 1.0 / 2997.92458;   // H0/c in h/Mpc
 struct GrowthDev {
   double om, fr0, rc, a_ini, kf;
   double sb, sm, sa;  // symmetron beta_*, m_*/H0, a_*
+  double kb, kk0, kx0, kxn;   // k-Mouflage beta, K0, X(a) = kx0 a^kxn
+  int km;                     // k-Mouflage exponent m
   int model;          // effective model for the growth (LCDM when growth_mode = 1)
   int kdep;           // table indexed by |nu|^2
   int n_steps;
@@ -85,12 +87,25 @@ __device__ __forceinline__ void rk4_to(double* y, double& lna, double l1, double
   rk4_segment<NV>(y, lna, l1, rhs);
 }
 
+// RK4 from lna to l1 (as rk4_to) with a step boundary on every knot of a tabulated
+// {m, beta} model in between: the splines' third derivatives jump there, which a step
+// across a knot would integrate at lower order.
+template <int NV, class Rhs>
+__device__ __forceinline__ void rk4_to_knots(double* y, double& lna, double l1, double l_kink,
+                                             const GrowthDev& g, const MBSpline& mb, const Rhs& rhs) {
+  if (g.model == COLA_MBETA) {
+    for (int j = 0; j < mb.n; ++j)
+      if (mb.x[j] > lna && mb.x[j] < l1) rk4_to<NV>(y, lna, mb.x[j], l_kink, rhs);
+  }
+  rk4_to<NV>(y, lna, l1, l_kink, rhs);
+}
+
 __device__ __forceinline__ double growth_kink(const GrowthDev& g) {
   return g.model == COLA_SYMMETRON ? log(g.sa) : -1e300;
 }
 
 // mu(k, a) of the model (Secs. 5.1, 5.2, App. C)
-__device__ __forceinline__ double growth_mu(const GrowthDev& g, double k, double a) {
+__device__ __forceinline__ double growth_mu(const GrowthDev& g, const MBSpline& mb, double k, double a) {
   if (g.model == COLA_FR_HS1) {
     const double ol = 1.0 - g.om;
     const double X = g.om / (a * a * a) + 4.0 * ol, Y = g.om + 4.0 * ol;
@@ -103,6 +118,16 @@ __device__ __forceinline__ double growth_mu(const GrowthDev& g, double k, double
     const double oma = g.om / (a * a * a) / (E * E);
     return 1.0 + 1.0 / (3.0 * (1.0 + 2.0 * g.rc * E * (1.0 - 0.5 * oma)));
   }
+  if (g.model == COLA_KMOUFLAGE) {   // App. B: 1 + 2 beta^2 / P_X(X(a)), P_X = 1 + m K0 X^(m-1)
+    const double X = g.kx0 * pow(a, g.kxn);
+    return 1.0 + 2.0 * g.kb * g.kb / (1.0 + g.km * g.kk0 * pow(X, (double)(g.km - 1)));
+  }
+  if (g.model == COLA_MBETA) {   // App. C: 1 + 2 beta^2 k^2/(k^2 + a^2 m^2), tabulated
+    double b, m2, dm2;
+    mb_eval(mb, a, b, m2, dm2);
+    const double a2m2 = a * a * kH0c * kH0c * m2;
+    return 1.0 + 2.0 * b * b * k * k / (k * k + a2m2);
+  }
   if (g.model == COLA_SYMMETRON) {   // App. C: 1 + 2 beta^2 k^2/(k^2 + a^2 m^2)
     if (a <= g.sa) return 1.0;
     const double r = g.sa / a, s = 1.0 - r * r * r;
@@ -113,8 +138,8 @@ __device__ __forceinline__ double growth_mu(const GrowthDev& g, double k, double
 }
 
 // 2 a^4 H^2 gamma_2^E(k, k1, k2, a) (Secs. 5.1, 5.2); c2 = cos^2 theta
-__device__ __forceinline__ double gamma2E_term(const GrowthDev& g, double k, double k1, double k2,
-                                               double c2, double a) {
+__device__ __forceinline__ double gamma2E_term(const GrowthDev& g, const MBSpline& mb, double k, double k1,
+                                               double k2, double c2, double a) {
   const double E = dE(a, g.om);
   const double a6 = (a * a * a) * (a * a * a);
   double g2 = 0.0;
@@ -131,6 +156,14 @@ __device__ __forceinline__ double gamma2E_term(const GrowthDev& g, double k, dou
     const double oma = g.om / (a * a * a) / (E * E);
     const double beta = 1.0 + 2.0 * g.rc * E * (1.0 - 0.5 * oma);
     g2 = -(g.rc * g.rc * g.om * g.om) / (6.0 * E * E * beta * beta * beta * a6) * (1.0 - c2);
+  } else if (g.model == COLA_MBETA) {
+    // App. C with the tabulated beta, m^2/H0^2 and d(m^2/H0^2)/da
+    double b, m2, dm2;
+    mb_eval(mb, a, b, m2, dm2);
+    const double ah = a * kH0c;
+    const double P = k * k / (ah * ah) + m2, P1 = k1 * k1 / (ah * ah) + m2, P2 = k2 * k2 / (ah * ah) + m2;
+    const double H = E * kH0c;
+    g2 = m2 * dm2 * b * b * g.om / (2.0 * P * P1 * P2) * k * k / (a * a * a * a * H * H);
   } else if (g.model == COLA_SYMMETRON && a > g.sa) {
     // App. C: m^2 (dm^2/da) beta^2 Om / (2 H0^4 Pi Pi Pi) k^2/(a^4 H^2), Pi(q) = (q/(aH0))^2 + m^2/H0^2
     const double r = g.sa / a, s = 1.0 - r * r * r;
@@ -144,8 +177,8 @@ __device__ __forceinline__ double gamma2E_term(const GrowthDev& g, double k, dou
 }
 
 // mu(k, a) and 2 a^4 H^2 gamma_2(k, k/sqrt2, k/sqrt2, a) for the growth equations
-__device__ __forceinline__ void growth_model(const GrowthDev& g, double k, double a, double& mu,
-                                             double& g2term) {
+__device__ __forceinline__ void growth_model(const GrowthDev& g, const MBSpline& mb, double k, double a,
+                                             double& mu, double& g2term) {
   const double E = dE(a, g.om);
   if (g.model == COLA_FR_HS1) {
     const double ol = 1.0 - g.om;
@@ -170,9 +203,12 @@ __device__ __forceinline__ void growth_model(const GrowthDev& g, double k, doubl
     mu = 1.0 + 1.0 / (3.0 * beta);
     const double g2 = -(g.rc * g.rc * g.om * g.om) / (6.0 * E * E * beta * beta * beta * ((a * a * a) * (a * a * a)));
     g2term = 2.0 * a * a * a * a * E * E * g2;
-  } else if (g.model == COLA_SYMMETRON) {
-    mu = growth_mu(g, k, a);
-    g2term = gamma2E_term(g, k, k * M_SQRT1_2, k * M_SQRT1_2, 0.0, a);
+  } else if (g.model == COLA_KMOUFLAGE) {   // gamma_2 = 0
+    mu = growth_mu(g, mb, k, a);
+    g2term = 0.0;
+  } else if (g.model == COLA_SYMMETRON || g.model == COLA_MBETA) {
+    mu = growth_mu(g, mb, k, a);
+    g2term = gamma2E_term(g, mb, k, k * M_SQRT1_2, k * M_SQRT1_2, 0.0, a);
   } else {
     mu = 1.0;
     g2term = 0.0;
@@ -183,11 +219,11 @@ __device__ __forceinline__ void growth_model(const GrowthDev& g, double k, doubl
 // HALF (the COLA_READ_D2_HALF_K reading): y also carries (D1, D1') at k/sqrt2, and the D2
 // source takes that D1 squared in place of D1(k)^2.
 template <bool HALF>
-__device__ __forceinline__ void growth_rhs(const GrowthDev& g, double k, double lna, const double* y,
-                                           double* dy) {
+__device__ __forceinline__ void growth_rhs(const GrowthDev& g, const MBSpline& mb, double k, double lna,
+                                           const double* y, double* dy) {
   const double a = exp(lna);
   double mu, g2t;
-  growth_model(g, k, a, mu, g2t);
+  growth_model(g, mb, k, a, mu, g2t);
   const double kap = 1.5 * g.om * a;
   const double f = 1.0 / (a * a * dE(a, g.om));
   const double ds = HALF ? y[4] : y[0];
@@ -197,15 +233,15 @@ __device__ __forceinline__ void growth_rhs(const GrowthDev& g, double k, double 
   dy[3] = (kap * mu * y[2] - kap * mu * ds * ds - g2t * ds * ds) * f;
   if constexpr (HALF) {
     dy[4] = y[5] * f;
-    dy[5] = kap * growth_mu(g, k * M_SQRT1_2, a) * y[4] * f;
+    dy[5] = kap * growth_mu(g, mb, k * M_SQRT1_2, a) * y[4] * f;
   }
 }
 
 template <bool HALF>
-__device__ __forceinline__ void store_slice(const GrowthDev& g, double k, double a, const double* y,
-                                            double* out) {
+__device__ __forceinline__ void store_slice(const GrowthDev& g, const MBSpline& mb, double k, double a,
+                                            const double* y, double* out) {
   double mu, g2t;
-  growth_model(g, k, a, mu, g2t);
+  growth_model(g, mb, k, a, mu, g2t);
   const double kap = 1.5 * g.om * a;
   const double ds = HALF ? y[4] : y[0];
   out[0] = y[0];
@@ -217,7 +253,8 @@ __device__ __forceinline__ void store_slice(const GrowthDev& g, double k, double
 }
 
 template <bool HALF>
-__global__ void __launch_bounds__(64) k_growth_ode(GrowthDev g, double* __restrict__ table, double* __restrict__ ref) {
+__global__ void __launch_bounds__(64) k_growth_ode(GrowthDev g, MBSpline mb, double* __restrict__ table,
+                                                   double* __restrict__ ref) {
   const int64_t t = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
   if (t > g.n_k) return;
   GrowthDev gg = g;
@@ -245,12 +282,12 @@ __global__ void __launch_bounds__(64) k_growth_ode(GrowthDev g, double* __restri
   for (int i = 0; i < nsl; ++i) {
     const double a_target = (t == g.n_k) ? 1.0 : ai + i * (1.0 - ai) / g.n_steps;
     const double l1 = log(a_target);
-    rk4_to<NV>(y, lna, l1, growth_kink(gg),
-               [&](double l, const double* yy, double* dy) { growth_rhs<HALF>(gg, k, l, yy, dy); });
+    rk4_to_knots<NV>(y, lna, l1, growth_kink(gg), gg, mb,
+                     [&](double l, const double* yy, double* dy) { growth_rhs<HALF>(gg, mb, k, l, yy, dy); });
     if (t == g.n_k)
-      store_slice<HALF>(gg, k, a_target, y, ref);
+      store_slice<HALF>(gg, mb, k, a_target, y, ref);
     else
-      store_slice<HALF>(gg, k, a_target, y, table + ((int64_t)i * g.n_k + t) * 6);
+      store_slice<HALF>(gg, mb, k, a_target, y, table + ((int64_t)i * g.n_k + t) * 6);
   }
 }
 
@@ -267,16 +304,22 @@ void launch_growth_ode(const cola_params& p, const Layout& L, double* table, dou
   g.sb = p.sym_beta;
   g.sm = p.sym_mass;
   g.sa = p.sym_astar;
+  g.kb = p.km_beta;
+  g.kk0 = p.km_k0;
+  g.kx0 = p.km_x0;
+  g.kxn = p.km_xn;
+  g.km = p.km_m;
   g.kdep = L.kdep ? 1 : 0;
   g.n_steps = p.n_steps;
   g.n_k = L.n_k;
   const int64_t threads = L.n_k + 1;
+  const MBSpline mb = mb_spline(p);
   if (p.readings & COLA_READ_D2_HALF_K)
     hipLaunchKernelGGL(k_growth_ode<true>, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, s, g,
-                       table, ref);
+                       mb, table, ref);
   else
     hipLaunchKernelGGL(k_growth_ode<false>, dim3((unsigned)((threads + 63) / 64)), dim3(64), 0, s, g,
-                       table, ref);
+                       mb, table, ref);
   COLA_LAUNCH_CHECK();
 }
 
@@ -320,19 +363,19 @@ struct Triangle {
   double k, k1, k2, c, c2;
 };
 
-__device__ __forceinline__ void triangle_rhs(const GrowthDev& g, const Triangle& t, double lna,
-                                             const double* y, double* dy) {
+__device__ __forceinline__ void triangle_rhs(const GrowthDev& g, const MBSpline& mb, const Triangle& t,
+                                             double lna, const double* y, double* dy) {
   const double a = exp(lna);
   const double E = dE(a, g.om);
   const double kap = 1.5 * g.om * a;
   const double f = 1.0 / (a * a * E);
-  const double mu = growth_mu(g, t.k, a), mu1 = growth_mu(g, t.k1, a), mu2 = growth_mu(g, t.k2, a);
+  const double mu = growth_mu(g, mb, t.k, a), mu1 = growth_mu(g, mb, t.k1, a), mu2 = growth_mu(g, mb, t.k2, a);
   const double oma = g.om / (a * a * a) / (E * E);
-  const double g2t = gamma2E_term(g, t.k, t.k1, t.k2, t.c2, a)
+  const double g2t = gamma2E_term(g, mb, t.k, t.k1, t.k2, t.c2, a)
                      + 2.0 * a * a * a * a * E * E * 1.5 * oma * (mu - mu1) * (t.k1 / t.k2) * t.c;
   const double src = 1.0 - (2.0 * mu1 - mu) / mu * t.c2 + g2t / (kap * mu);
   double muh, g2h;
-  growth_model(g, t.k, a, muh, g2h);   // the approximate equation at k
+  growth_model(g, mb, t.k, a, muh, g2h);   // the approximate equation at k
   dy[0] = y[1] * f;
   dy[1] = kap * mu1 * y[0] * f;
   dy[2] = y[3] * f;
@@ -345,7 +388,7 @@ __device__ __forceinline__ void triangle_rhs(const GrowthDev& g, const Triangle&
   dy[9] = (kap * muh * y[8] - kap * muh * y[4] * y[4] - g2h * y[4] * y[4]) * f;
 }
 
-__global__ void __launch_bounds__(64) k_growth_triangle(GrowthDev g, int n, const double* __restrict__ tri, double a_end,
+__global__ void __launch_bounds__(64) k_growth_triangle(GrowthDev g, MBSpline mb, int n, const double* __restrict__ tri, double a_end,
                                   double* __restrict__ out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
@@ -366,8 +409,8 @@ __global__ void __launch_bounds__(64) k_growth_triangle(GrowthDev g, int n, cons
   double y[10] = {1.0, g0, 1.0, g0, 1.0, g0, -3.0 / 7.0 * s2, -6.0 / 7.0 * s2 * g0, -3.0 / 7.0,
                   -6.0 / 7.0 * g0};
   double lna = log(ai);
-  rk4_to<10>(y, lna, log(a_end), growth_kink(g),
-             [&](double l, const double* yy, double* dy) { triangle_rhs(g, t, l, yy, dy); });
+  rk4_to_knots<10>(y, lna, log(a_end), growth_kink(g), g, mb,
+                   [&](double l, const double* yy, double* dy) { triangle_rhs(g, mb, t, l, yy, dy); });
   out[2 * i] = y[6];
   out[2 * i + 1] = y[8] * s2;
 }
@@ -384,8 +427,14 @@ void launch_growth_triangles(const cola_params& p, int n, const double* tri, dou
   g.sb = p.sym_beta;
   g.sm = p.sym_mass;
   g.sa = p.sym_astar;
-  hipLaunchKernelGGL(k_growth_triangle, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, g, n, tri, a,
-                     out);
+  g.kb = p.km_beta;
+  g.kk0 = p.km_k0;
+  g.kx0 = p.km_x0;
+  g.kxn = p.km_xn;
+  g.km = p.km_m;
+  const MBSpline mb = mb_spline(p);
+  hipLaunchKernelGGL(k_growth_triangle, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, s, g, mb, n, tri,
+                     a, out);
   COLA_LAUNCH_CHECK();
 }
 

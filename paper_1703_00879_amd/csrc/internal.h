@@ -2,6 +2,7 @@
 #pragma once
 
 #include <hip/hip_runtime.h>
+#include <cmath>
 #include <cstddef>
 #include <cstdint>
 #include <string>
@@ -96,6 +97,44 @@ constexpr int kMaxDevices = 64;
 // Error{COLA_E_SIZE} when `need` exceeds it.
 void* static_work(size_t need);
 
+// ------------------------------------------------------------------ general {m, beta} tables
+// Natural cubic splines of beta and of ln(m^2/H0^2) over the knots x = ln a of a
+// COLA_MBETA run: values and second derivatives at the knots (the second derivatives
+// vanish at both ends).  Evaluated the same way on the host and in the growth kernels.
+struct MBSpline {
+  int n;
+  double x[COLA_MBETA_MAX_KNOTS];
+  double yb[COLA_MBETA_MAX_KNOTS], Mb[COLA_MBETA_MAX_KNOTS];
+  double ym[COLA_MBETA_MAX_KNOTS], Mm[COLA_MBETA_MAX_KNOTS];
+};
+MBSpline mb_spline(const cola_params& p);   // zero n unless p.model == COLA_MBETA
+
+// beta, m^2/H0^2 and d(m^2/H0^2)/da at scale factor a (the end cubics continue outside
+// the knots)
+__host__ __device__ inline void mb_eval(const MBSpline& s, double a, double& beta, double& m2,
+                                        double& dm2_da) {
+  const double x = log(a);
+  int lo = 0, hi = s.n - 1;   // interval [x_lo, x_lo+1] holding x, clamped to the ends
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (x < s.x[mid])
+      hi = mid;
+    else
+      lo = mid;
+  }
+  const double h = s.x[lo + 1] - s.x[lo], t = x - s.x[lo], u = s.x[lo + 1] - x;
+  auto val = [&](const double* y, const double* M, double& d) {
+    const double c0 = y[lo] / h - M[lo] * h / 6.0, c1 = y[lo + 1] / h - M[lo + 1] * h / 6.0;
+    d = -M[lo] * u * u / (2.0 * h) + M[lo + 1] * t * t / (2.0 * h) - c0 + c1;
+    return M[lo] * u * u * u / (6.0 * h) + M[lo + 1] * t * t * t / (6.0 * h) + c0 * u + c1 * t;
+  };
+  double db, dl;
+  beta = val(s.yb, s.Mb, db);
+  const double lm = val(s.ym, s.Mm, dl);
+  m2 = exp(lm);
+  dm2_da = m2 * dl / a;
+}
+
 // ------------------------------------------------------------------ host physics (FP64)
 struct Cosmo {
   double om, ol;
@@ -127,8 +166,10 @@ double a_of_step(const cola_params& p, int i);
 struct PMScalars {
   float g_n, g_5, a2m2, sop_g_n;
   float thr, vx, vx0, cn, c5;
+  float km_r;      // k-Mouflage: (lambda (H0/c)^2 / a^2)^2, turning |F_Newton|^2 into R
   int screen;      // screening on
-  int potential;   // potential screening (f(R), symmetron); else density (nDGP)
+  int potential;   // potential screening (f(R), symmetron, tabulated {m, beta})
+  int gradient;    // gradient screening (k-Mouflage); neither: density screening (nDGP)
 };
 PMScalars pm_scalars(const cola_params& p, double a);
 
@@ -139,7 +180,7 @@ struct StepDev {
   float g_n, g_5, a2m2, sop_g_n;   // PMScalars at a_i
   float thr, vx, vx0, cn, c5;
   float dtk, dtd;                  // kick tau(a_{i+1/2}) - tau(a_{i-1/2}), drift tau(a_{i+1}) - tau(a_i)
-  int32_t pad;
+  float km_r;
   int64_t slice0, slice1;          // growth-table element offsets of slices i and i + 1
 };
 StepDev step_dev(const cola_params& p, const Layout& L, int i);
@@ -163,9 +204,11 @@ struct KOp {
   int64_t tab_slice0 = 0, tab_slice1 = 0;   // element offsets of two slices (K_LPT)
   int lpt_mode = 0;                // 0: X = D''(slice0); 1: X = D(slice1) - D(slice0); 2: X = D(slice0)
   const float2* coef = nullptr;    // K_LPT: the step's (X1, X2) per |nu|^2 in FP32, if built
-  // when set, the step-dependent coefficients (g_n, g_5, a2m2) come from steps[*step_ctr]
+  // when set, the step-dependent coefficients (g_n, g_5, a2m2) come from steps[*step_ctr];
+  // with step_newton the force pass takes the Newtonian part alone (g_n = the step's cn)
   const StepDev* steps = nullptr;
   const int* step_ctr = nullptr;
+  int step_newton = 0;
   int comp = 0, comp2 = 0;
   float scale = 1.f;
   float kf = 1.f;                  // 2 pi / L
@@ -251,6 +294,18 @@ void launch_lpt_coef(const Layout& L, const double* table, int64_t slice0, int64
 void launch_write_step(StepDev* steps, int i, const StepDev& v, hipStream_t s);
 void launch_set_counter(int* ctr, int v, hipStream_t s);
 void launch_step_advance(int* ctr, hipStream_t s);
+// k-Mouflage source (App. B): out = (rho - 1)(cn + c5 eps) in the padded real layout, with
+// eps = min(1, 1/P_X(X*)), P_X(X*)^2 X* = km_r |F|^2 from the interleaved Newtonian force
+// mesh f3; s_out (optional, padded real) gets S = (rho - 1) eps.  With steps set, km_r, cn
+// and c5 come from steps[*step_ctr].
+struct KmArgs {
+  float km_r, k0, cn, c5;
+  int m;
+  const StepDev* steps = nullptr;
+  const int* step_ctr = nullptr;
+};
+void launch_kmouflage_source(const Layout& L, const float* rho, const float* f3, float* out,
+                             float* s_out, const KmArgs& k, hipStream_t s);
 // CIC deposit into the padded real mesh.  `bins` is the work area at off_bins, `entries`
 // the packed per-particle CIC records sorted by home tile (float4 each).
 void launch_deposit(const Layout& L, const float* disp, float* rho_padded, void* bins,

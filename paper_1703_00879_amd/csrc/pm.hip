@@ -635,6 +635,56 @@ void launch_gather(const Layout& L, const GatherArgs& a, hipStream_t s) {
   COLA_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------------------------ k-Mouflage source
+// X* >= 0 with P_X(X*)^2 X* = R, P_X = 1 + m K0 X^(m-1): Newton on y = ln X of
+// f(y) = y + 2 ln P_X(e^y) - ln R, which rises with slope between 1 and 2m - 1, from the
+// smaller of the two asymptotic roots; returns P_X(X*)
+__device__ __forceinline__ float km_px_at_root(float R, float k0, int m) {
+  if (!(R > 0.f)) return 1.f;
+  const float mk = (float)m * k0, lr = __logf(R);
+  float y = fminf(lr, (lr - 2.f * __logf(mk)) / (float)(2 * m - 1));
+  float px = 1.f;
+  for (int it = 0; it < 24; ++it) {
+    const float t = mk * __expf((float)(m - 1) * y);   // m K0 X^(m-1)
+    px = 1.f + t;
+    const float f = y + 2.f * __logf(px) - lr;
+    const float fp = 1.f + 2.f * (float)(m - 1) * t / px;
+    y -= f / fp;
+  }
+  return 1.f + mk * __expf((float)(m - 1) * y);
+}
+
+__global__ void k_kmouflage_source(const float* __restrict__ rho, const float* __restrict__ f3,
+                                   float* __restrict__ out, float* __restrict__ s_out, int n,
+                                   int rpitch, int64_t rplane, KmArgs k) {
+  if (k.steps) {
+    const StepDev& sd = k.steps[*k.step_ctr];
+    k.km_r = sd.km_r;
+    k.cn = sd.cn;
+    k.c5 = sd.c5;
+  }
+  const int64_t total = (int64_t)n * n * n;
+  for (int64_t e = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; e < total;
+       e += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t r = e / n;
+    const int64_t pe = (r / n) * rplane + (r % n) * rpitch + (e - r * n);
+    const float fx = f3[3 * e], fy = f3[3 * e + 1], fz = f3[3 * e + 2];
+    const float px = km_px_at_root(k.km_r * (fx * fx + fy * fy + fz * fz), k.k0, k.m);
+    const float eps = fminf(1.f, 1.f / px);
+    const float dl = rho[pe] - 1.f;
+    out[pe] = dl * (k.cn + k.c5 * eps);
+    if (s_out) s_out[pe] = dl * eps;
+  }
+}
+
+void launch_kmouflage_source(const Layout& L, const float* rho, const float* f3, float* out,
+                             float* s_out, const KmArgs& k, hipStream_t s) {
+  ProfScope ps("kmouflage_source", s);
+  hipLaunchKernelGGL(k_kmouflage_source, dim3(grid_for(L.M, 256)), dim3(256), 0, s, rho, f3, out,
+                     s_out, L.nm, 2 * L.pitch_m, 2 * L.plane_m, k);
+  COLA_LAUNCH_CHECK();
+}
+
 // ------------------------------------------------------------------ step table and counter
 __global__ void k_write_step(StepDev* steps, int i, StepDev v) { steps[i] = v; }
 __global__ void k_set_counter(int* ctr, int v) { *ctr = v; }

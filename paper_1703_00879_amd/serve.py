@@ -129,7 +129,7 @@ class Server:
         self.depth = depth
         self.keep = keep_states
 
-    def run(self, requests):
+    def run(self, requests, on_result=None):
         eng = self.engine
         order = sorted(range(len(requests)), key=lambda j: (requests[j].arrival, j))
         fps = {j: eng.footprint(requests[j].params) for j in order}
@@ -166,6 +166,8 @@ class Server:
                         state=eng.release(run.handle, self.keep))
                     if not self.keep:   # a kept state stays resident and keeps its footprint
                         used -= run.footprint
+                    if on_result:
+                        on_result(len(results), len(requests))
                     progressed = True
                 else:
                     still.append(run)

@@ -46,3 +46,40 @@ def test_results_identical_alone_and_in_the_mix():
         assert torch.equal(r.state.disp_f, d0), p
         assert torch.equal(r.state.vel_f, v0), p
         assert torch.isfinite(d0).all()
+
+
+def test_sixteen_requests_with_overlapping_arrivals():
+    """Sixteen requests drawn like the serving workload (n_p in {128, 256, 384} with
+    n_mesh = 2 n_p and L = 2 n_p Mpc/h, 10-30 steps, LCDM / f(R) / nDGP), arriving every
+    50 ms while earlier ones run: at most six admitted at once on four streams, later
+    ones admitted as slots free up.  Every result equals the same run alone, bit for bit."""
+    import numpy as np
+    rng = np.random.default_rng(77)
+    params = []
+    for j in range(16):
+        n = int(rng.choice([128, 256, 384]))
+        m = int(rng.integers(6))
+        kw = dict(np1d=n, nmesh1d=2 * n, box=2.0 * n, z_init=19.0, n_steps=int(rng.integers(10, 31)),
+                  seed=5000 + j, screening=1)
+        if m == 0:
+            kw.update(model=C.LCDM)
+        elif m <= 3:
+            kw.update(model=C.FR_HS1, fr0_abs=(1e-6, 1e-5, 1e-4)[m - 1])
+        else:
+            kw.update(model=C.NDGP, rc_h0=(0.5, 1.0)[m - 4])
+        params.append(C.Params(**kw))
+    reqs = [Request(p, arrival=0.05 * j, rid=j) for j, p in enumerate(params)]
+    eng = GpuEngine(n_streams=4)
+    res = Server(eng, hbm_budget=200 << 30, max_active=6, keep_states=True).run(reqs)
+    torch.cuda.synchronize()
+    admitted_late = sum(1 for r in res if r.admitted > r.arrival + 1e-3)
+    overlapped = sum(1 for a in res for b in res if a is not b and a.admitted < b.finished
+                     and b.admitted < a.finished)
+    assert overlapped > 0   # runs shared the device
+    for p, r in zip(params, res):
+        d0, v0 = _alone(p)
+        assert r.state.next_step == p.n_steps
+        assert torch.equal(r.state.disp_f, d0), p
+        assert torch.equal(r.state.vel_f, v0), p
+        del d0, v0
+    print(f"16 requests: {admitted_late} waited for a slot; {overlapped // 2} overlapping pairs")
