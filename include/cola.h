@@ -257,6 +257,25 @@ cola_status cola_white_noise(const cola_params* p, int32_t grid, float* dst,
 cola_status cola_growth_triangles(const cola_params* p, int32_t n, const double* tri, double a,
                                   double* out, hipStream_t stream);
 
+/* FFT tuning.  The Y passes of the 3D transforms (element stride one row pitch) run in
+ * tiles of 4, 8 or 16 columns per work-group; each column gets the same butterflies in the
+ * same order whatever the width, so every result is bitwise independent of it, and only
+ * the speed changes.  The widths are process-wide, per transform size and direction; the
+ * default is the widest tile whose 8-byte elements fit 128 KB of LDS.  A graph captured
+ * (cola_ensemble_run) keeps the widths in use when it was captured.
+ * cola_fft_tiles: n = a supported transform size (8 ... 2048, 2^a 3^b as the mesh);
+ *   fwd / inv = 4, 8 or 16 sets the width of the forward / inverse pass, 0 restores the
+ *   default, -1 leaves it; COLA_E_ARG if a width does not fit n (N * width / radix-group
+ *   threads above 1024, or LDS above 160 KB).  cur_out (host int32 [2], may be NULL)
+ *   receives the widths now in use (forward, inverse).
+ * cola_autotune: times every valid width of both directions for the PM mesh and the
+ *   particle grid of p on the state's work buffer (its contents are overwritten; the
+ *   state must be prepared, and no step of it may be in flight), keeps the fastest and
+ *   writes them to out (host int32 [4]: mesh forward, mesh inverse, particle-grid forward,
+ *   particle-grid inverse; 0 where the grid was not tuned).  Synchronises the stream. */
+cola_status cola_fft_tiles(int32_t n, int32_t fwd, int32_t inv, int32_t* cur_out);
+cola_status cola_autotune(const cola_params* p, cola_state* st, int32_t* out, hipStream_t stream);
+
 /* Kernel timing by HIP events on the launch stream: enable (1) / disable (0)
  * recording; read accumulated milliseconds and launch counts per kernel name
  * (synchronises the last recorded stream).  names/ms/counts are host arrays of

@@ -662,6 +662,38 @@ cola_status cola_power_spectrum(const cola_params* p, cola_state* st, int32_t nb
   });
 }
 
+cola_status cola_fft_tiles(int32_t n, int32_t fwd, int32_t inv, int32_t* cur_out) {
+  return guarded([&] {
+    if (!fft_size_supported(n)) throw Error{COLA_E_ARG, "transform size not supported"};
+    fft_set_tiles(n, fwd, inv);
+    if (cur_out) {
+      int t[2];
+      fft_get_tiles(n, t);
+      cur_out[0] = t[0];
+      cur_out[1] = t[1];
+    }
+  });
+}
+
+cola_status cola_autotune(const cola_params* p, cola_state* st, int32_t* out, hipStream_t s) {
+  return guarded([&] {
+    if (!p || !out) throw Error{COLA_E_ARG, "NULL argument"};
+    const Bufs b = carve(*p, st);
+    if (!st->prepared) throw Error{COLA_E_STATE, "state not prepared"};
+    int t[2];
+    fft_autotune(plan_mesh(b), b.mesh[0], s, t);
+    out[0] = t[0];
+    out[1] = t[1];
+    out[2] = out[3] = 0;
+    // the particle-grid transforms run only when their field fits the work area
+    if (b.L.pgrid_elems * sizeof(float2) <= b.L.work_bytes) {
+      fft_autotune(plan_part(b), b.mesh[0], s, t);
+      out[2] = t[0];
+      out[3] = t[1];
+    }
+  });
+}
+
 cola_status cola_positions(const cola_params* p, const cola_state* st, float* xyz, hipStream_t s) {
   return guarded([&] {
     if (!p || !xyz) throw Error{COLA_E_ARG, "NULL argument"};

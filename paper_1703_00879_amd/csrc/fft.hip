@@ -19,6 +19,7 @@
 // Conventions: forward e^{-i k x}, inverse e^{+i k x}, both unnormalised.  Twiddles come
 // from a table exp(-2 pi i t / n) built on the host in double precision.
 
+#include <atomic>
 #include <type_traits>
 
 #include "internal.h"
@@ -892,6 +893,110 @@ static void col_pass(float2* data, int64_t elemStride, int64_t tiles, int64_t ti
   COLA_LAUNCH_CHECK();
 }
 
+// ------------------------------------------------------------------ Y-pass tile widths
+// The Y passes (stride one row pitch) can run with 4, 8 or 16 columns per tile where the
+// tile fits LDS and the work-group limit; every choice computes the same butterflies on
+// each column, so results are bitwise independent of it.  The width per transform size
+// and direction comes from a process-wide table: the LDS-limited default, or what
+// fft_autotune measured fastest, or what the caller set.
+template <int N, int B>
+constexpr bool kTileOk = (N * B / ColCfg<N>::E) <= 1024 && (N * B / ColCfg<N>::E) % B == 0 &&
+                         (size_t)N * B * 8 + (size_t)N * 8 <= 163840;
+
+static constexpr int kSizes[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768,
+                                 1024, 1536, 2048};
+static int size_index(int n) {
+  for (int i = 0; i < (int)(sizeof(kSizes) / sizeof(int)); ++i)
+    if (kSizes[i] == n) return i;
+  return -1;
+}
+static std::atomic<int> g_ytile[sizeof(kSizes) / sizeof(int)][2];   // 0 = default
+
+template <int N>
+static int y_tile(int dir) {
+  const int i = size_index(N);
+  const int t = g_ytile[i][dir > 0 ? 1 : 0].load(std::memory_order_relaxed);
+  return t ? t : ColCfg<N>::B;
+}
+
+template <int N, int DIR, int B>
+static void y_pass_b(float2* data, const FFTPlan& pl, const KOp& op, hipStream_t s, const char* name) {
+  if constexpr (kTileOk<N, B>) {
+    const int P = pl.pitch;
+    col_pass<N, DIR, K_COPY, B>(data, P, (int64_t)pl.n * (P / B), P / B, pl.plane, pl.tw, op, s, name);
+  } else {
+    throw Error{COLA_E_ARG, "Y-pass tile width not valid for this size"};
+  }
+}
+
+template <int N, int DIR>
+static void y_pass(float2* data, const FFTPlan& pl, const KOp& op, hipStream_t s, const char* name) {
+  switch (y_tile<N>(DIR)) {
+    case 4: y_pass_b<N, DIR, 4>(data, pl, op, s, name); break;
+    case 8: y_pass_b<N, DIR, 8>(data, pl, op, s, name); break;
+    default: y_pass_b<N, DIR, 16>(data, pl, op, s, name); break;
+  }
+}
+
+template <int N>
+static bool tile_valid(int b) {
+  return (b == 4 && kTileOk<N, 4>) || (b == 8 && kTileOk<N, 8>) || (b == 16 && kTileOk<N, 16>);
+}
+
+// fwd, inv: 4, 8 or 16 sets the width, 0 restores the default, -1 leaves it
+template <int N>
+static void set_tiles_impl(int fwd, int inv) {
+  for (int w : {fwd, inv})
+    if (w != -1 && w != 0 && !tile_valid<N>(w))
+      throw Error{COLA_E_ARG, "tile width must be 4, 8 or 16 and fit this transform size"};
+  const int i = size_index(N);
+  if (fwd >= 0) g_ytile[i][0].store(fwd);
+  if (inv >= 0) g_ytile[i][1].store(inv);
+}
+
+// Times every valid width of the forward and inverse Y passes of an N-point transform on
+// `data` (a work field laid out by pl; its contents are overwritten) and keeps the fastest.
+template <int N>
+static void autotune_impl(const FFTPlan& pl, float2* data, hipStream_t s, int out[2]) {
+  hipEvent_t e0, e1;
+  COLA_HIP_CHECK(hipEventCreate(&e0));
+  COLA_HIP_CHECK(hipEventCreate(&e1));
+  KOp none;
+  for (int d = 0; d < 2; ++d) {
+    float best = 1e30f;
+    int best_b = ColCfg<N>::B;
+    for (int b : {4, 8, 16}) {
+      if (!tile_valid<N>(b)) continue;
+      auto run = [&] {
+        if (d == 0) {
+          if (b == 4) y_pass_b<N, -1, 4>(data, pl, none, s, "fft_y_tune");
+          else if (b == 8) y_pass_b<N, -1, 8>(data, pl, none, s, "fft_y_tune");
+          else y_pass_b<N, -1, 16>(data, pl, none, s, "fft_y_tune");
+        } else {
+          if (b == 4) y_pass_b<N, 1, 4>(data, pl, none, s, "fft_y_tune");
+          else if (b == 8) y_pass_b<N, 1, 8>(data, pl, none, s, "fft_y_tune");
+          else y_pass_b<N, 1, 16>(data, pl, none, s, "fft_y_tune");
+        }
+      };
+      run();   // warm-up
+      COLA_HIP_CHECK(hipEventRecord(e0, s));
+      for (int r = 0; r < 3; ++r) run();
+      COLA_HIP_CHECK(hipEventRecord(e1, s));
+      COLA_HIP_CHECK(hipEventSynchronize(e1));
+      float ms = 0.f;
+      COLA_HIP_CHECK(hipEventElapsedTime(&ms, e0, e1));
+      if (ms < best) {
+        best = ms;
+        best_b = b;
+      }
+    }
+    g_ytile[size_index(N)][d].store(best_b);
+    out[d] = best_b;
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+}
+
 template <int N>
 static void r2c_impl(const FFTPlan& pl, const float* in, float2* out, bool x_pass, hipStream_t s) {
   const int n = pl.n, P = pl.pitch;
@@ -904,10 +1009,8 @@ static void r2c_impl(const FFTPlan& pl, const float* in, float2* out, bool x_pas
     COLA_LAUNCH_CHECK();
   }
   KOp op;
-  constexpr int B = ColCfg<N>::B;
   // Y pass: per x-plane, tiles of B z-columns, element stride = pitch
-  col_pass<N, -1, K_COPY>(out, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, op, s,
-                          "fft_y_fwd");
+  y_pass<N, -1>(out, pl, op, s, "fft_y_fwd");
   // X pass: tiles of XCfg B (y, z) columns, element stride = plane
   constexpr int BX = XCfg<N>::B;
   if (x_pass)
@@ -920,7 +1023,6 @@ static void c2r_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* data
                      hipStream_t s) {
   const int n = pl.n, P = pl.pitch;
   const int64_t rows = (int64_t)n * n;
-  constexpr int B = ColCfg<N>::B;
   KOp op = op_in;
   op.n = n;
   op.pitch = P;
@@ -941,8 +1043,7 @@ static void c2r_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* data
   // the particle-grid transforms of the LPT terms are timed under names of their own
   const bool lpt = kind == K_LPT;
   KOp none;
-  col_pass<N, 1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s,
-                         lpt ? "lpt_fft_y_inv" : "fft_y_inv");
+  y_pass<N, 1>(data, pl, none, s, lpt ? "lpt_fft_y_inv" : "fft_y_inv");
   {
     ProfScope ps(lpt ? "lpt_fft_c2r_z" : "fft_c2r_z", s);
     constexpr int BR = RowCfg<N / 2>::B;
@@ -1005,7 +1106,7 @@ static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, c
   }
   KOp none;
   const int64_t ytiles = (int64_t)n * (P / B);
-  col_pass<N, 1, K_COPY>(work[0], P, ytiles, P / B, pl.plane, pl.tw, none, s, "fft_y_inv");
+  y_pass<N, 1>(work[0], pl, none, s, "fft_y_inv");
   {
     ProfScope ps("fft_y_inv_yz", s);
     hipLaunchKernelGGL((k_fft_col_inv_yz<N>), dim3((unsigned)ytiles), dim3(ColCfg<N>::T), 0, s,
@@ -1028,7 +1129,6 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
                         hipStream_t s) {
   const int n = pl.n, P = pl.pitch;
   const int64_t rows = (int64_t)n * n;
-  constexpr int B = ColCfg<N>::B;
   KOp op = op_in;
   op.n = n;
   op.pitch = P;
@@ -1045,7 +1145,7 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
     COLA_LAUNCH_CHECK();
   }
   KOp none;
-  col_pass<N, 1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s, "fft_y_inv");
+  y_pass<N, 1>(data, pl, none, s, "fft_y_inv");
   {
     ProfScope ps("fft_z_screen", s);
     constexpr int BR = RowCfg<N / 2>::B;
@@ -1058,13 +1158,43 @@ static void screen_impl(const FFTPlan& pl, int kind, const KOp& op_in, float2* d
                          pl.plane, pl.tw, sa);
     COLA_LAUNCH_CHECK();
   }
-  col_pass<N, -1, K_COPY>(data, P, (int64_t)n * (P / B), P / B, pl.plane, pl.tw, none, s, "fft_y_fwd");
+  y_pass<N, -1>(data, pl, none, s, "fft_y_fwd");
 }
 
 void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* src,
                     float2* const work[3], float* f3, hipStream_t s) {
   switch (pl.n) {
 #define CASE(N_) case N_: force3_impl<N_>(pl, op, dk, src, work, f3, s); return;
+    CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
+    CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
+#undef CASE
+    default: throw Error{COLA_E_UNSUPPORTED, "FFT size not supported"};
+  }
+}
+
+void fft_set_tiles(int n, int fwd, int inv) {
+  switch (n) {
+#define CASE(N_) case N_: set_tiles_impl<N_>(fwd, inv); return;
+    CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
+    CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
+#undef CASE
+    default: throw Error{COLA_E_ARG, "transform size not supported"};
+  }
+}
+
+void fft_get_tiles(int n, int out[2]) {
+  switch (n) {
+#define CASE(N_) case N_: out[0] = y_tile<N_>(-1); out[1] = y_tile<N_>(1); return;
+    CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
+    CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
+#undef CASE
+    default: throw Error{COLA_E_ARG, "transform size not supported"};
+  }
+}
+
+void fft_autotune(const FFTPlan& pl, float2* data, hipStream_t s, int out[2]) {
+  switch (pl.n) {
+#define CASE(N_) case N_: autotune_impl<N_>(pl, data, s, out); return;
     CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
     CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
 #undef CASE

@@ -265,6 +265,15 @@ struct ScreenArgs {
 void fft_screen(const FFTPlan& pl, int kind, const KOp& op, float2* dk, float2* data,
                 const float* rho, float* s_out, int model, const ScreenArgs& sa, hipStream_t s);
 
+// Tile widths (columns per work-group) of the Y passes of n-point transforms, per
+// direction: fwd / inv = 4, 8 or 16 sets one (COLA_E_ARG if it does not fit LDS or the
+// work-group limit at n), 0 restores the default, -1 leaves it.  fft_get_tiles gives the
+// widths in use.  fft_autotune times every valid width of both directions on `data` (a
+// field of pl's layout; overwritten), keeps the fastest and returns them in out[2].
+void fft_set_tiles(int n, int fwd, int inv);
+void fft_get_tiles(int n, int out[2]);
+void fft_autotune(const FFTPlan& pl, float2* data, hipStream_t s, int out[2]);
+
 // ------------------------------------------------------------------ kernels (launchers)
 void launch_fill(float* p, size_t n, float v, hipStream_t s);
 void launch_growth_ode(const cola_params& p, const Layout& L, double* table, double* ref,
