@@ -8,10 +8,11 @@ initial conditions (Eisenstein-Hu no-wiggle spectrum, Om = 0.3, h = 0.7, ns = 0.
 sigma8 = 0.8), 2LPT at z = 19, 20 COLA steps to z = 0.  FP64 only in the growth tables and
 the step coefficients.
 
-A step is one cola_step: the per-step LPT synthesis (six particle-grid inverse FFTs), CIC
-deposit, forward FFT, potential screening (inverse FFT of the Newtonian potential, the
-real-space factor, forward FFT of S), the fused Green's-function / fifth-force / gradient
-inverse FFTs, and the CIC gather fused with the kick and drift.  Warm-up steps run from
+A step is one cola_step: CIC deposit, forward FFT, potential screening (inverse FFT of
+the Newtonian potential, the real-space factor, forward FFT of S), the fused
+Green's-function / fifth-force / gradient inverse FFTs, the per-step LPT synthesis (two
+fused particle-grid inverse FFTs, each giving the three components of L'' or Delta), and
+the CIC gather fused with the kick and drift.  Warm-up steps run from
 their own initial conditions; the K timed steps start from new ones, so the default
 K = 20 times one whole run to z = 0 (initial conditions, made before each run, are never
 inside a timed interval).
@@ -80,9 +81,12 @@ def algorithmic_bytes(name, p):
         "fft_y_inv_yz": 8 * H + 16 * H,              # read G; write the y and z components
         "fft_c2r_z3": 24 * H + 12 * M,               # read 3 force passes, write (Fx, Fy, Fz)
         "gather_kick_drift": 12 * M + 72 * N,        # force mesh; u, v and the LPT terms in; u, v out
-        "fft_x_inv_lpt": 16 * Hp + 8 * Hp,           # read phi1_k, phi2_k; write one component
+        "lpt_fft_x_inv": 16 * Hp + 16 * Hp,          # read phi1_k, phi2_k; write G0 and G
         "lpt_fft_y_inv": 16 * Hp,
-        "lpt_fft_c2r_z": 8 * Hp + 4 * N,             # write one real particle-grid field
+        "lpt_fft_y_inv_yz": 8 * Hp + 16 * Hp,
+        "lpt_fft_c2r_z3": 24 * Hp + 12 * N,          # write (x, y, z) of L'' or Delta
+        "fft_x_inv_lpt": 16 * Hp + 8 * Hp,           # initial conditions: one component
+        "lpt_fft_c2r_z": 8 * Hp + 4 * N,
         "fill": 0,
     }
     return table.get(name)
@@ -239,6 +243,8 @@ def traffic_for(kernel):
 # particle grid's real transforms); the first pattern that matches wins
 _SYMBOLS = [("k_fft_col_fwd_force<{n}, true>", "fft_x_fwd_force"),
             ("k_fft_col_fwd_force<{n}, false>", "fft_x_fwd_force_1src"),
+            ("k_fft_col_lpt<{np}>", "lpt_fft_x_inv"), ("k_fft_col_inv_yz<{np}>", "lpt_fft_y_inv_yz"),
+            ("k_fft_c2r_row3<{nph}>", "lpt_fft_c2r_z3"),
             ("k_fft_col_inv_yz", "fft_y_inv_yz"), ("k_fft_col_fwd_op<{n}, 3,", "fft_x_fwd_smooth"),
             ("k_fft_col_fwd_op<{n}, 2,", "fft_x_fwd_pot"), ("k_fft_col<{n}, -1, 0,", "fft_y_fwd"),
             ("k_fft_col<{n}, 1, 0,", "fft_y_inv"), ("k_fft_col<{np}, 1, 4,", "fft_x_inv_lpt"),

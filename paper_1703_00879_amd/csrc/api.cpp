@@ -110,7 +110,9 @@ struct Bufs {
   unsigned long long* pk_cnt;
   float2* mesh[6];
   float* force;       // interleaved force mesh over slots 3-5
-  float2* pf[6];
+  float2* lptw[3];    // scale-dependent LPT: particle-grid work fields
+  float* lpp3;        // and the interleaved L'' and Delta arrays
+  float* dlt3;
   float2* phi1;
   float2* phi2;
   float* psi1;
@@ -158,7 +160,9 @@ static Bufs carve(const cola_params& p, const cola_state* st, void* work = nullp
   b.ctr = at<int>(st->tables, L.off_ctr);
   for (int i = 0; i < 6; ++i) b.mesh[i] = at<float2>(work, L.off_mesh[i]);
   b.force = at<float>(work, L.off_mesh[3]);
-  for (int i = 0; i < 6; ++i) b.pf[i] = L.kdep ? at<float2>(work, L.off_pfield[i]) : nullptr;
+  for (int i = 0; i < 3; ++i) b.lptw[i] = L.kdep ? at<float2>(work, L.off_lptw[i]) : nullptr;
+  b.lpp3 = L.kdep ? at<float>(work, L.off_lpp3) : nullptr;
+  b.dlt3 = L.kdep ? at<float>(work, L.off_dlt3) : nullptr;
   b.bins = at<void>(work, L.off_bins);
   b.entries = at<float4>(work, L.off_entries);
   if (L.kdep) {
@@ -306,33 +310,26 @@ static void step_impl(const cola_params* p, cola_state* st, int32_t i, void* wor
   g.table = b.growth;
   g.steps = b.steps;
   g.step_ctr = b.ctr;
+  pm_core(*p, b, st->disp, a_of_step(*p, i), nullptr, s, true);
   if (L.kdep) {
-    // L''(q, a_i) and Psi_LPT(a_{i+1}) - Psi_LPT(a_i) from the stored k-space fields
+    // L''(q, a_i) and Psi_LPT(a_{i+1}) - Psi_LPT(a_i) from the stored k-space fields,
+    // after the force (their work fields and outputs may lie over mesh slots 0-2)
     const FFTPlan pp = plan_part(b);
     float2* coef = at<float2>(st->tables, L.off_lpt_coef);
     launch_lpt_coef(L, b.growth, 0, 0, b.steps, b.ctr, coef, s);
-    for (int c = 0; c < 6; ++c) {
+    for (int t = 0; t < 2; ++t) {
       KOp op;
       op.kf = (float)(2.0 * M_PI / p->box);
-      op.a = b.phi1;
-      op.b = b.phi2;
-      op.table = b.growth;
-      op.lpt_mode = c < 3 ? 0 : 1;
-      op.coef = coef + (c < 3 ? 0 : L.n_k);
-      op.kdep = 1;
-      op.comp = c % 3;
+      op.coef = coef + (t == 0 ? 0 : L.n_k);
       op.scale = (float)(1.0 / (double)L.N);
-      fft_c2r(pp, K_LPT, op, b.pf[c], R(b.pf[c]), s);
-      if (c < 3)
-        g.lpp[c] = R(b.pf[c]);
-      else
-        g.dlt[c - 3] = R(b.pf[c]);
+      fft_c2r_lpt3(pp, op, b.phi1, b.phi2, b.lptw, t == 0 ? b.lpp3 : b.dlt3, s);
     }
+    g.lpp3 = b.lpp3;
+    g.dlt3 = b.dlt3;
   } else {
     g.psi1 = b.psi1;
     g.psi2 = b.psi2;
   }
-  pm_core(*p, b, st->disp, a_of_step(*p, i), nullptr, s, true);
   g.F3 = b.force;
   g.disp = st->disp;
   g.vel = st->vel;

@@ -354,11 +354,25 @@ k_fft_col(float2* __restrict__ data, int64_t elemStride, int64_t tilesPerBlock,
 // field instead of two reads and two writes.
 // Tile of the forward-operator-inverse X pass: the X-pass tile (for 1024-point columns 8
 // to a 64 KB tile, two work-groups per CU, 25 % faster than one 16-column tile per CU).
+// Elements per thread of the fused kernels that keep a column (or the Green's function)
+// in registers across two transforms of a tile.  With the plan's 16 elements a 2048-point
+// tile of 8 columns needs 1024 threads, whose 128-register budget per lane spills 150-180
+// bytes per lane to scratch memory (through the L2 to HBM); 32 elements per thread on 512
+// threads get 256 registers and spill 0-64 bytes, and measured 12-30 % faster.  At 1024
+// points the larger E spilled more and ran slower, so there the plan's E stays.  Each
+// butterfly is computed the same way whatever E is.
+template <int N, int B>
+struct FusedCfg {
+  static constexpr int E = (N >= 2048 && N * B / ColCfg<N>::E >= 1024) ? 2 * ColCfg<N>::E
+                                                                      : ColCfg<N>::E;
+  static constexpr int T = N * B / E;
+};
+
 template <int N>
 struct OpCfg {
   static constexpr int B = XCfg<N>::B;
-  static constexpr int E = ColCfg<N>::E;
-  static constexpr int T = N * B / E;
+  static constexpr int E = FusedCfg<N, B>::E;
+  static constexpr int T = FusedCfg<N, B>::T;
 };
 
 template <int N, int KIND, bool KEEP>
@@ -414,10 +428,10 @@ k_fft_col_fwd_op(float2* __restrict__ data, float2* __restrict__ out, int64_t el
 // data is touched once, so it streams past the caches and leaves the L2 to the register
 // spills of the two inverse transforms.
 template <int N, bool DK>
-__global__ void __launch_bounds__(ColCfg<N>::T)
+__global__ void __launch_bounds__((FusedCfg<N, ColCfg<N>::B>::T))
 k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
                     int64_t elemStride, const float2* __restrict__ tw_g, KOp op) {
-  constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
+  constexpr int B = ColCfg<N>::B, E = FusedCfg<N, B>::E, T = FusedCfg<N, B>::T;
   if (op.steps) {
     const StepDev& sd = op.steps[*op.step_ctr];
     op.g_n = op.step_newton ? sd.cn : sd.g_n;
@@ -476,11 +490,11 @@ k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
 // transforms; outA (F_y, may alias data) and outB (F_z) take the results.  Tile t covers
 // columns [col0, col0 + B) of x-plane t / tilesPerBlock, as in k_fft_col.
 template <int N>
-__global__ void __launch_bounds__(ColCfg<N>::T)
+__global__ void __launch_bounds__((FusedCfg<N, ColCfg<N>::B>::T))
 k_fft_col_inv_yz(const float2* data, float2* outA, float2* __restrict__ outB, int64_t elemStride,
                  int64_t tilesPerBlock, int64_t blockStride, const float2* __restrict__ tw_g,
                  KOp op) {
-  constexpr int B = ColCfg<N>::B, E = ColCfg<N>::E, T = ColCfg<N>::T;
+  constexpr int B = ColCfg<N>::B, E = FusedCfg<N, B>::E, T = FusedCfg<N, B>::T;
   constexpr int R0 = Plan<N>::rad[0], NB0 = E / R0;
   static_assert(T % B == 0, "a thread's butterflies must share one column");
   __shared__ float2 lds[N * B];
@@ -516,6 +530,71 @@ k_fft_col_inv_yz(const float2* data, float2* outA, float2* __restrict__ outB, in
       outB[base + (O)j * es + c] = grad_minus_i(op, 0, j, iz, 2, v);
     };
     GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load, store);
+  }
+}
+
+// Inverse X pass of a scale-dependent LPT term (App. A): the displacement-like field
+// IDFT[i k (c1 phi1_k + c2 phi2_k)], c1 and c2 the step's FP32 growth coefficients of
+// |nu|^2 (one 8-byte table read per mode).  A = -(c1 phi1_k + c2 phi2_k) / N is formed in
+// registers from one read of each potential, and two X transforms go out through the LDS
+// tile, as in k_fft_col_fwd_force: G0 = X^-1[-i k_x A] (= X^-1[i k_x (c1 phi1 + c2 phi2)]/N)
+// into o0 and G = X^-1[A] into o1, from which the Y passes of the force transforms give
+// the three components.  Columns past z = n/2 (row padding) get zeros.
+template <int N>
+struct LptXCfg {
+  static constexpr int B = XCfg<N>::B;
+  static constexpr int E = FusedCfg<N, B>::E;
+  static constexpr int T = FusedCfg<N, B>::T;
+};
+
+template <int N>
+__global__ void __launch_bounds__(LptXCfg<N>::T)
+k_fft_col_lpt(const float2* __restrict__ phi1, const float2* __restrict__ phi2,
+              float2* __restrict__ o0, float2* __restrict__ o1, int64_t elemStride,
+              const float2* __restrict__ tw_g, KOp op) {
+  constexpr int B = LptXCfg<N>::B, E = LptXCfg<N>::E, T = LptXCfg<N>::T;
+  constexpr int R0 = Plan<N>::rad[0], NB0 = E / R0;
+  static_assert(T % B == 0, "a thread's butterflies must share one column");
+  __shared__ float2 lds[N * B];
+  __shared__ float2 tw[N];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < N; i += T) tw[i] = tw_g[i];   // first read after stage 0's barrier
+  using O = Off<N>;
+  const O base = (O)xcd_block(blockIdx.x, gridDim.x) * B, es = (O)elemStride;
+  const int c0 = tid % B;
+  const int col = (int)base + c0;
+  const int iy = col / op.pitch, iz = col % op.pitch;
+  const int n = op.n, h = n >> 1;
+  const int ny = iy < h ? iy : iy - n;
+  const int n2yz = ny * ny + iz * iz;
+  const float ms = -op.scale;
+  float2 g[NB0][R0];
+#pragma unroll
+  for (int i = 0; i < NB0; ++i) {
+    const int j = (tid + i * T) / B;
+#pragma unroll
+    for (int r = 0; r < R0; ++r) {
+      const int jj = j + r * (N / R0);
+      const O idx = base + (O)jj * es + c0;
+      const float2 a = load_stream(phi1 + idx), b = load_stream(phi2 + idx);
+      const int nx = jj < h ? jj : jj - n;
+      const int n2 = nx * nx + n2yz;
+      g[i][r] = make_float2(0.f, 0.f);
+      if (iz <= h && n2 != 0) {
+        const float2 cf = op.coef[n2];
+        g[i][r] = make_float2(ms * (cf.x * a.x + cf.y * b.x), ms * (cf.x * a.y + cf.y * b.y));
+      }
+    }
+  }
+#pragma unroll
+  for (int t = 0; t < 2; ++t) {
+    float2* out = t == 0 ? o0 : o1;
+    auto load = [&](int i, int r, int jj, int) -> float2 {
+      return t == 0 ? grad_minus_i(op, jj, iy, iz, 0, g[i][r]) : g[i][r];
+    };
+    auto store = [&](int j, int c, float2 v) { store_stream(out + base + (O)j * es + c, v); };
+    GStages<N, +1, E, B, B, 1, 0, 1>::run(lds, tid, T, tw, load, store);
+    __syncthreads();   // the second transform reuses the LDS tile
   }
 }
 
@@ -692,14 +771,17 @@ k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nr
 // thread groups, one per component, each transforming the same B rows through its own
 // LDS tile as in k_fft_c2r_row; the last stage writes the interleaved rows into LDS over
 // the three tiles, and all threads copy them out -- one contiguous block -- with 16-byte
-// stores.
+// stores.  Rows of 1024 complex values go one to a work-group with unpadded tiles (a
+// single column has no transposed reads to pad against): 41 KB of LDS lets three
+// work-groups share a CU, so one group's loads overlap another's transforms and stores
+// (two rows with padded tiles took 90 KB, one work-group per CU, and ran 45 % slower).
 template <int NC>
 struct Row3Cfg {
   static constexpr int E = kRowE<NC>;
-  static constexpr int B = RowCfg<NC>::B >= 2 ? RowCfg<NC>::B / 2 : 1;
+  static constexpr int B = NC == 1024 ? 1 : (RowCfg<NC>::B >= 2 ? RowCfg<NC>::B / 2 : 1);
   static constexpr int TC = NC * B / E;   // threads per component
   static constexpr int T = 3 * TC;
-  static constexpr int LS = B + 1;
+  static constexpr int LS = B == 1 ? 1 : B + 1;
 };
 
 template <int NC>
@@ -1081,18 +1163,46 @@ void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* ou
   }
 }
 
+// Y and Z passes shared by the force and LPT transforms: work[0] holds G0 after its X
+// pass (the x component), work[1] G; the inverse Y pass of G0, the two-component Y pass
+// of G into work[1] (y) and work[2] (z), and one real Z pass of all three writing the
+// interleaved rows out3[((x n + y) n + z) 3 + c].
+template <int N>
+static void grad3_tail(const FFTPlan& pl, const KOp& op, float2* const work[3], float* out3,
+                       bool lpt, hipStream_t s) {
+  const int n = pl.n, P = pl.pitch;
+  const int64_t rows = (int64_t)n * n;
+  constexpr int B = ColCfg<N>::B;
+  KOp none;
+  const int64_t ytiles = (int64_t)n * (P / B);
+  y_pass<N, 1>(work[0], pl, none, s, lpt ? "lpt_fft_y_inv" : "fft_y_inv");
+  {
+    ProfScope ps(lpt ? "lpt_fft_y_inv_yz" : "fft_y_inv_yz", s);
+    hipLaunchKernelGGL((k_fft_col_inv_yz<N>), dim3((unsigned)ytiles), dim3(FusedCfg<N, B>::T), 0, s,
+                       work[1], work[1], work[2], (int64_t)P, (int64_t)(P / B), pl.plane, pl.tw, op);
+    COLA_LAUNCH_CHECK();
+  }
+  {
+    ProfScope ps(lpt ? "lpt_fft_c2r_z3" : "fft_c2r_z3", s);
+    constexpr int BR = Row3Cfg<N / 2>::B;
+    hipLaunchKernelGGL((k_fft_c2r_row3<N / 2>), dim3((unsigned)((rows + BR - 1) / BR)),
+                       dim3(Row3Cfg<N / 2>::T), 0, s, work[0], work[1], work[2], out3, rows, P,
+                       pl.plane, pl.tw);
+    COLA_LAUNCH_CHECK();
+  }
+}
+
 template <int N>
 static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, const float2* src,
                         float2* const work[3], float* f3, hipStream_t s) {
   const int n = pl.n, P = pl.pitch;
-  const int64_t rows = (int64_t)n * n;
   constexpr int B = ColCfg<N>::B;
   KOp op = op_in;
   op.n = n;
   op.pitch = P;
   op.plane = pl.plane;
   {
-    const dim3 g((unsigned)((int64_t)n * P / B)), b(ColCfg<N>::T);
+    const dim3 g((unsigned)((int64_t)n * P / B)), b(FusedCfg<N, B>::T);
     if (dk) {
       ProfScope ps("fft_x_fwd_force", s);
       hipLaunchKernelGGL((k_fft_col_fwd_force<N, true>), g, b, 0, s, dk, src, work[0], work[1],
@@ -1104,23 +1214,25 @@ static void force3_impl(const FFTPlan& pl, const KOp& op_in, const float2* dk, c
     }
     COLA_LAUNCH_CHECK();
   }
-  KOp none;
-  const int64_t ytiles = (int64_t)n * (P / B);
-  y_pass<N, 1>(work[0], pl, none, s, "fft_y_inv");
+  grad3_tail<N>(pl, op, work, f3, false, s);
+}
+
+template <int N>
+static void lpt3_impl(const FFTPlan& pl, const KOp& op_in, const float2* phi1, const float2* phi2,
+                      float2* const work[3], float* out3, hipStream_t s) {
+  const int n = pl.n, P = pl.pitch;
+  KOp op = op_in;
+  op.n = n;
+  op.pitch = P;
+  op.plane = pl.plane;
   {
-    ProfScope ps("fft_y_inv_yz", s);
-    hipLaunchKernelGGL((k_fft_col_inv_yz<N>), dim3((unsigned)ytiles), dim3(ColCfg<N>::T), 0, s,
-                       work[1], work[1], work[2], (int64_t)P, (int64_t)(P / B), pl.plane, pl.tw, op);
+    ProfScope ps("lpt_fft_x_inv", s);
+    constexpr int B = LptXCfg<N>::B;
+    hipLaunchKernelGGL((k_fft_col_lpt<N>), dim3((unsigned)((int64_t)n * P / B)),
+                       dim3(LptXCfg<N>::T), 0, s, phi1, phi2, work[0], work[1], pl.plane, pl.tw, op);
     COLA_LAUNCH_CHECK();
   }
-  {
-    ProfScope ps("fft_c2r_z3", s);
-    constexpr int BR = Row3Cfg<N / 2>::B;
-    hipLaunchKernelGGL((k_fft_c2r_row3<N / 2>), dim3((unsigned)((rows + BR - 1) / BR)),
-                       dim3(Row3Cfg<N / 2>::T), 0, s, work[0], work[1], work[2], f3, rows, P,
-                       pl.plane, pl.tw);
-    COLA_LAUNCH_CHECK();
-  }
+  grad3_tail<N>(pl, op, work, out3, true, s);
 }
 
 template <int N>
@@ -1165,6 +1277,17 @@ void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const fl
                     float2* const work[3], float* f3, hipStream_t s) {
   switch (pl.n) {
 #define CASE(N_) case N_: force3_impl<N_>(pl, op, dk, src, work, f3, s); return;
+    CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
+    CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
+#undef CASE
+    default: throw Error{COLA_E_UNSUPPORTED, "FFT size not supported"};
+  }
+}
+
+void fft_c2r_lpt3(const FFTPlan& pl, const KOp& op, const float2* phi1, const float2* phi2,
+                  float2* const work[3], float* out3, hipStream_t s) {
+  switch (pl.n) {
+#define CASE(N_) case N_: lpt3_impl<N_>(pl, op, phi1, phi2, work, out3, s); return;
     CASE(8) CASE(12) CASE(16) CASE(24) CASE(32) CASE(48) CASE(64) CASE(96) CASE(128)
     CASE(192) CASE(256) CASE(384) CASE(512) CASE(768) CASE(1024) CASE(1536) CASE(2048)
 #undef CASE

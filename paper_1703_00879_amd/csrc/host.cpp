@@ -366,9 +366,21 @@ Layout make_layout(const cola_params& p) {
     L.off_mesh[i] = o;
     o += mesh_bytes;
   }
-  for (int i = 0; i < 6; ++i) {
-    L.off_pfield[i] = o;
-    if (L.kdep) o += pfield_bytes;
+  {
+    const size_t l3 = align_up((size_t)3 * L.N * sizeof(float));
+    const size_t need = 3 * pfield_bytes + 2 * l3;
+    size_t q = 0;
+    if (L.kdep) {
+      if (need <= 3 * mesh_bytes) {
+        q = L.off_mesh[0];
+      } else {
+        q = o;
+        o += need;
+      }
+    }
+    for (int i = 0; i < 3; ++i) L.off_lptw[i] = q + i * pfield_bytes;
+    L.off_lpp3 = q + 3 * pfield_bytes;
+    L.off_dlt3 = L.off_lpp3 + l3;
   }
   L.tile = (L.nm % 16 == 0 && L.nm / 16 >= 2) ? 16 : (L.nm % 8 == 0 && L.nm / 8 >= 2) ? 8 : 4;
   L.nt1 = L.nm / L.tile;

@@ -76,8 +76,11 @@ struct Layout {
   size_t scratch_bytes;
   // offsets (bytes) inside `work`: six mesh slots (padded half-complex / real meshes);
   // the interleaved force mesh [nm][nm][nm][3] spans slots 3-5, and the sorted CIC
-  // records of the deposit reuse slot 5 when they fit there
-  size_t off_mesh[6], off_pfield[6], work_bytes;
+  // records of the deposit reuse slot 5 when they fit there.  Scale-dependent LPT: three
+  // particle-grid half-complex work fields and the interleaved L'' and Delta arrays
+  // (3 N floats each), over slots 0-2 when they fit there (they are written after the
+  // force mesh and read with it by the gather), else in an area of their own.
+  size_t off_mesh[6], off_lptw[3], off_lpp3, off_dlt3, work_bytes;
   // binned deposit: tile edge (cells), tiles per axis, tile count, and the offsets of
   // the per-tile counters and of the particle-index list sorted by home tile
   int tile, nt1;
@@ -247,6 +250,13 @@ void fft_c2r(const FFTPlan& pl, int kind, const KOp& op, float2* data, float* ou
 // f3[((x nm + y) nm + z) 3 + c] (unpadded).
 void fft_c2r_force3(const FFTPlan& pl, const KOp& op, const float2* dk, const float2* src,
                     float2* const work[3], float* f3, hipStream_t s);
+// The three components of IDFT[i k (c1 phi1_k + c2 phi2_k)] / N on the particle grid (a
+// scale-dependent LPT term, App. A), c1 and c2 read per mode from op.coef[|nu|^2]: one X
+// pass forms the field from phi1 and phi2 and writes its two X transforms into work[0]
+// and work[1] (none may alias phi1 or phi2), then the Y and Z passes of fft_c2r_force3
+// write the interleaved rows out3[((x n + y) n + z) 3 + c].  op needs kf, scale and coef.
+void fft_c2r_lpt3(const FFTPlan& pl, const KOp& op, const float2* phi1, const float2* phi2,
+                  float2* const work[3], float* out3, hipStream_t s);
 // Screened source in Fourier space.  dk holds the density contrast after the forward Z
 // and Y passes: one X pass completes delta_k (written back in place for K_POT, where the
 // force needs it; not kept for K_SMOOTH) and applies `kind` (K_POT: Newtonian potential
@@ -326,8 +336,8 @@ struct GatherArgs {
   float* vel;
   const float* psi1;          // scale-independent LPT (else null)
   const float* psi2;
-  const float* lpp[3];        // scale-dependent LPT fields (padded particle grid)
-  const float* dlt[3];
+  const float* lpp3;          // scale-dependent LPT: L''(q) and Delta(q) per particle,
+  const float* dlt3;          // interleaved (3 floats per lattice site, lattice order)
   const double* table;        // growth table (scale-independent coefficients)
   int64_t slice0, slice1;     // element offsets of slices i and i+1
   double dtk, dtd;

@@ -502,8 +502,7 @@ struct GatherDev {
   const float* F3;   // interleaved force mesh, 3 floats per cell, unpadded rows
   float* disp; float* vel;
   const float* psi1; const float* psi2;
-  const float* l0; const float* l1; const float* l2;
-  const float* d0; const float* d1; const float* d2;
+  const float* l3; const float* d3;   // interleaved L'' and Delta (MODE 1)
   const double* table; int64_t slice0, slice1;
   float dtk, dtd;
   float* force_out;
@@ -528,8 +527,7 @@ constexpr int kGatherBrick = 16;
 
 template <int MODE>
 __global__ void __launch_bounds__(256)
-k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int ppitch,
-         int64_t pplane, int bricks) {
+k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int bricks) {
   if (MODE != 2 && g.steps) {
     const StepDev& sd = g.steps[*g.step_ctr];
     g.dtk = sd.dtk;
@@ -590,10 +588,11 @@ k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int 
       d[a] = e1 * s1 + e2 * s2;
     }
   } else {
-    const int ip = (int)p;
-    const int64_t q = (int64_t)(ip / (np * np)) * pplane + (int64_t)((ip / np) % np) * ppitch + ip % np;
-    l[0] = g.l0[q]; l[1] = g.l1[q]; l[2] = g.l2[q];
-    d[0] = g.d0[q]; d[1] = g.d1[q]; d[2] = g.d2[q];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      l[a] = g.l3[3 * p + a];
+      d[a] = g.d3[3 * p + a];
+    }
   }
   const float fv[3] = {f0, f1, f2};
 #pragma unroll
@@ -609,8 +608,7 @@ void launch_gather(const Layout& L, const GatherArgs& a, hipStream_t s) {
   g.F3 = a.F3;
   g.disp = a.disp; g.vel = a.vel;
   g.psi1 = a.psi1; g.psi2 = a.psi2;
-  g.l0 = a.lpp[0]; g.l1 = a.lpp[1]; g.l2 = a.lpp[2];
-  g.d0 = a.dlt[0]; g.d1 = a.dlt[1]; g.d2 = a.dlt[2];
+  g.l3 = a.lpp3; g.d3 = a.dlt3;
   g.table = a.table; g.slice0 = a.slice0; g.slice1 = a.slice1;
   g.dtk = (float)a.dtk; g.dtd = (float)a.dtd;
   g.force_out = a.force_out;
@@ -622,15 +620,15 @@ void launch_gather(const Layout& L, const GatherArgs& a, hipStream_t s) {
   if (a.force_out) {
     ProfScope ps("gather_force", s);
     hipLaunchKernelGGL(k_gather<2>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_p, 2 * L.plane_p, bricks);
+                       bricks);
   } else if (a.psi1) {
     ProfScope ps("gather_kick_drift", s);
     hipLaunchKernelGGL(k_gather<0>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_p, 2 * L.plane_p, bricks);
+                       bricks);
   } else {
     ProfScope ps("gather_kick_drift", s);
     hipLaunchKernelGGL(k_gather<1>, grid, block, 0, s, g, L.N, L.np, L.nm, ratio, L.inv_cell,
-                       2 * L.pitch_p, 2 * L.plane_p, bricks);
+                       bricks);
   }
   COLA_LAUNCH_CHECK();
 }

@@ -39,10 +39,21 @@ def test_query_sizes_and_layout():
     # six mesh slots + tile counters; the sorted CIC records (16 B each) fit in slot 5
     assert 16 * N <= mesh and s["work_bytes"] == 6 * mesh + bins
     assert s["total_bytes"] == sum(v for k, v in s.items() if k != "total_bytes")
-    # scale-dependent f(R) stores phi1_k, phi2_k and six particle-grid LPT fields
+    # scale-dependent f(R) stores phi1_k, phi2_k; its per-step LPT work (three
+    # particle-grid fields and the interleaved L'' and Delta arrays) lies over mesh slots
+    # 0-2 when it fits there, as it does at n_mesh = 2 n_p
     sf = C.cola_query_sizes(p.with_(model=C.FR_HS1))
     pg = up(512 * (512 * 272 + 16) * 8)
-    assert sf["lpt_bytes"] == 2 * pg and sf["work_bytes"] == 6 * mesh + 6 * pg + bins
+    assert 3 * pg + 2 * up(12 * N) <= 3 * mesh
+    assert sf["lpt_bytes"] == 2 * pg and sf["work_bytes"] == 6 * mesh + bins
+    # at n_mesh = n_p it does not fit and gets an area of its own
+    q = C.Params(model=C.FR_HS1, np1d=128, nmesh1d=128, box=128.0, n_steps=10)
+    sq = C.cola_query_sizes(q)
+    mq, pq = up(128 * (128 * 80 + 16) * 8), up(128 * (128 * 80 + 16) * 8)
+    nt = (128 // 16) ** 3
+    bq = -(-(17 * nt + 2 * (-(-nt // 1024)) + 64) * 4 // 256) * 256
+    # (and the 16-byte CIC records, larger than a slot here, get their own area too)
+    assert sq["work_bytes"] == 6 * mq + 3 * pq + 2 * up(12 * 128 ** 3) + bq + up(16 * 128 ** 3)
 
 
 @pytest.mark.parametrize("bad", [dict(np1d=30), dict(np1d=40), dict(nmesh1d=96, np1d=64),

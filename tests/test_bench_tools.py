@@ -46,8 +46,8 @@ def test_algorithmic_bytes(bench):
     assert ab("fft_x_fwd_force_1src") == 24 * H and ab("fft_x_fwd_force") == 32 * H
     assert ab("deposit") == 16 * N + 4 * M
     Hp = p.np1d ** 2 * (p.np1d // 2 + 1)
-    assert ab("fft_x_inv_lpt") == 24 * Hp and ab("lpt_fft_y_inv") == 16 * Hp
-    assert ab("lpt_fft_c2r_z") == 8 * Hp + 4 * N
+    assert ab("lpt_fft_x_inv") == 32 * Hp and ab("lpt_fft_y_inv") == 16 * Hp
+    assert ab("lpt_fft_y_inv_yz") == 24 * Hp and ab("lpt_fft_c2r_z3") == 24 * Hp + 12 * N
     assert ab("no_such_kernel") is None
 
 
@@ -67,6 +67,9 @@ def test_algorithmic_bytes(bench):
     ("void cola::k_fft_col<512, 1, 4, 8>(HIP_vector_type<float, 2u>*, long)", "fft_x_inv_lpt"),
     ("void cola::k_fft_col<512, 1, 0, 16>(HIP_vector_type<float, 2u>*, long)", "lpt_fft_y_inv"),
     ("void cola::k_fft_c2r_row<256>(float2 const*)", "lpt_fft_c2r_z"),
+    ("void cola::k_fft_col_lpt<512>(float2 const*)", "lpt_fft_x_inv"),
+    ("void cola::k_fft_col_inv_yz<512>(float2 const*)", "lpt_fft_y_inv_yz"),
+    ("void cola::k_fft_c2r_row3<256>(float2 const*)", "lpt_fft_c2r_z3"),
 ])
 def test_profile_names(bench, symbol, name):
     assert bench._profile_name(symbol, 1024, 512) == name
@@ -86,7 +89,7 @@ def test_summarize_rocprof_on_synthetic_runs(bench, tmp_path):
     1 GiB copy read 1 GiB, and writes both profile files."""
     d = tmp_path / "prof"
     gather = "void cola::k_gather<0>(cola::GatherDev, long)"
-    c2r3 = "void cola::k_fft_c2r_row3<512>(float2 const*)"
+    c2r3 = "void cola::k_fft_c2r_row3<1024>(float2 const*)"
     trace, fetch, write = [], [], []
     did = 0
     for step in range(3):
