@@ -227,6 +227,13 @@ cola_status cola_power_spectrum(const cola_params* p, cola_state* st, int32_t nb
                                 double* k_out, double* p_out, int64_t* nmodes_out,
                                 hipStream_t stream);
 
+/* Time step i (0 <= i < n_steps) of the leapfrog (Sec. 2), on the host in FP64, no HIP
+ * call: out[0] = a_i, out[1] = a_{i+1} (uniform in a from a_ini to 1), out[2] = the kick
+ * interval tau(a_{i+1/2}) - tau(a_{i-1/2}) (a_{-1/2} = a_0), out[3] = the drift interval
+ * tau(a_{i+1}) - tau(a_i), with d tau = da / (a^3 H/H0) by Gauss-Legendre quadrature.
+ * cola_step uses these, rounded to FP32.  COLA_E_ARG for invalid p or i. */
+cola_status cola_step_times(const cola_params* p, int32_t i, double* out);
+
 /* Wrapped comoving positions x = (q + u) mod L into device float [3][N]. */
 cola_status cola_positions(const cola_params* p, const cola_state* st, float* xyz_out,
                            hipStream_t stream);

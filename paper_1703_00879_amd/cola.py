@@ -24,7 +24,7 @@ READ_X_TOTAL_DENSITY, READ_X_NO_A3, READ_D2_HALF_K = 1, 2, 4
 EXPORTED = ["cola_query_sizes", "cola_validate", "cola_prepare", "cola_make_ic", "cola_pm_force",
             "cola_step", "cola_step_static", "cola_ensemble_create", "cola_ensemble_run",
             "cola_ensemble_destroy", "cola_power_spectrum", "cola_positions", "cola_growth_table",
-            "cola_white_noise", "cola_growth_triangles", "cola_fft_tiles", "cola_autotune",
+            "cola_white_noise", "cola_growth_triangles", "cola_step_times", "cola_fft_tiles", "cola_autotune",
             "cola_profile_enable", "cola_profile_read", "cola_profile_reset",
             "cola_status_string", "cola_last_error"]
 
@@ -145,6 +145,7 @@ def load_library(path=LIB_PATH):
         "cola_positions": [P, St, vp, vp],
         "cola_growth_table": [P, St, i32, vp, i64, vp, vp],
         "cola_white_noise": [P, i32, vp, vp], "cola_growth_triangles": [P, i32, vp, d, vp, vp],
+        "cola_step_times": [P, i32, vp],
         "cola_fft_tiles": [i32, i32, i32, vp], "cola_autotune": [P, St, vp, vp],
         "cola_profile_enable": [i32],
         "cola_profile_read": [vp, vp, vp, i32, vp], "cola_profile_reset": [],
@@ -305,6 +306,13 @@ def cola_growth_triangles(p, tri, a, out, stream=None):
     n = int(tri.shape[0])
     _check(load_library().cola_growth_triangles(ctypes.byref(p._c()), n, _ptr(tri), float(a),
                                                 _ptr(out), _stream(stream)))
+
+
+def cola_step_times(p, i):
+    """(a_i, a_{i+1}, kick interval, drift interval) of step i in FP64 (host only)."""
+    out = (ctypes.c_double * 4)()
+    _check(load_library().cola_step_times(ctypes.byref(p._c()), int(i), out))
+    return tuple(out)
 
 
 def cola_fft_tiles(n, fwd=-1, inv=-1):

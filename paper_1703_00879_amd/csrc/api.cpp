@@ -289,7 +289,10 @@ static void pm_core(const cola_params& p, const Bufs& b, const float* disp, doub
   } else if (flat_out) {
     launch_unpad_mesh(L, R(M[0]), flat_out + L.M, s, 1.f);   // S = delta = rho - 1
   }
-  float2* const work[3] = {M[0], M[1], M[2]};
+  // the X pass writes its two transforms over its own inputs where it can (delta_k in M[1]
+  // and S in M[2]): a 2048-point X column visits one page per x-plane of every field it
+  // touches, and two fields instead of three keep more of those translations cached
+  float2* const work[3] = {M[1], M[2], M[0]};
   fft_c2r_force3(pl, op, dk, src, work, b.force, s);
 }
 
@@ -656,6 +659,15 @@ cola_status cola_power_spectrum(const cola_params* p, cola_state* st, int32_t nb
       p_out[i] = w > 0 ? sp / w : 0.0;
       if (nmodes_out) nmodes_out[i] = (int64_t)c[i];
     }
+  });
+}
+
+cola_status cola_step_times(const cola_params* p, int32_t i, double* out) {
+  return guarded([&] {
+    if (!p || !out) throw Error{COLA_E_ARG, "NULL argument"};
+    validate(*p);
+    if (i < 0 || i >= p->n_steps) throw Error{COLA_E_ARG, "step index out of range"};
+    step_times(*p, i, out);
   });
 }
 

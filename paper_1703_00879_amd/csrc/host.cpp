@@ -244,11 +244,21 @@ PMScalars pm_scalars(const cola_params& p, double a) {
   return s;
 }
 
-StepDev step_dev(const cola_params& p, const Layout& L, int i) {
+void step_times(const cola_params& p, int i, double out[4]) {
   const Cosmo cz{p.omega_m, 1.0 - p.omega_m};
   const double ai = a_of_step(p, i), an = a_of_step(p, i + 1);
   const double a_lo = (i == 0) ? ai : 0.5 * (a_of_step(p, i - 1) + ai);
   const double a_hi = 0.5 * (ai + an);
+  out[0] = ai;
+  out[1] = an;
+  out[2] = tau_between(cz, a_lo, a_hi);
+  out[3] = tau_between(cz, ai, an);
+}
+
+StepDev step_dev(const cola_params& p, const Layout& L, int i) {
+  double tm[4];
+  step_times(p, i, tm);
+  const double ai = tm[0];
   const PMScalars m = pm_scalars(p, ai);
   StepDev d{};
   d.g_n = m.g_n;
@@ -261,8 +271,8 @@ StepDev step_dev(const cola_params& p, const Layout& L, int i) {
   d.cn = m.cn;
   d.c5 = m.c5;
   d.km_r = m.km_r;
-  d.dtk = (float)tau_between(cz, a_lo, a_hi);
-  d.dtd = (float)tau_between(cz, ai, an);
+  d.dtk = (float)tm[2];
+  d.dtd = (float)tm[3];
   d.slice0 = (int64_t)i * L.n_k * 6;
   d.slice1 = (int64_t)(i + 1) * L.n_k * 6;
   return d;

@@ -187,6 +187,8 @@ struct StepDev {
   int64_t slice0, slice1;          // growth-table element offsets of slices i and i + 1
 };
 StepDev step_dev(const cola_params& p, const Layout& L, int i);
+// a_i, a_{i+1} and the kick and drift intervals of step i in FP64 (what step_dev rounds)
+void step_times(const cola_params& p, int i, double out[4]);
 
 // ------------------------------------------------------------------ k-space operators
 enum KKind : int {

@@ -881,16 +881,18 @@ constexpr int kPkBlocks = 1024;
 constexpr int kPkMaxBins = 2048;
 
 // Per block: LDS shell sums of w, w P and w |k| over a grid-stride share of the modes.
+// Each mode's terms are formed in FP32 and summed in FP64 (LDS double atomics), so the
+// order in which a block's threads add them changes only the last bits of a 53-bit sum.
 __global__ void __launch_bounds__(256)
 k_pk_partial(const float2* __restrict__ dk, int n, int pitch, int64_t plane, int nbins, float kf,
              float vol,
-             float* __restrict__ part_p, float* __restrict__ part_k,
+             double* __restrict__ part_p, double* __restrict__ part_k,
              unsigned* __restrict__ part_w) {
-  __shared__ float sp[kPkMaxBins], sk[kPkMaxBins];
+  __shared__ double sp[kPkMaxBins], sk[kPkMaxBins];
   __shared__ unsigned sw[kPkMaxBins];
   for (int b = threadIdx.x; b < nbins; b += blockDim.x) {
-    sp[b] = 0.f;
-    sk[b] = 0.f;
+    sp[b] = 0.0;
+    sk[b] = 0.0;
     sw[b] = 0u;
   }
   __syncthreads();
@@ -913,8 +915,8 @@ k_pk_partial(const float2* __restrict__ dk, int n, int pitch, int64_t plane, int
     const float W = wx * wx * wy * wy * wz * wz;
     const float ar = v.x * invM / W, ai = v.y * invM / W;
     const unsigned w = (iz > 0 && iz < h) ? 2u : 1u;
-    atomicAdd(&sp[b], (float)w * vol * (ar * ar + ai * ai));
-    atomicAdd(&sk[b], (float)w * kf * sqrtf((float)n2));
+    atomicAdd(&sp[b], (double)((float)w * vol * (ar * ar + ai * ai)));
+    atomicAdd(&sk[b], (double)((float)w * kf * sqrtf((float)n2)));
     atomicAdd(&sw[b], w);
   }
   __syncthreads();
@@ -925,38 +927,41 @@ k_pk_partial(const float2* __restrict__ dk, int n, int pitch, int64_t plane, int
   }
 }
 
-// Cross-block reduction per bin with Neumaier-compensated float sums.
-__global__ void k_pk_final(const float* __restrict__ part_p, const float* __restrict__ part_k,
+// Cross-block reduction per bin in FP64, block after block (a fixed order), with
+// Neumaier compensation; each sum leaves as an FP32 pair hi + lo.
+__global__ void k_pk_final(const double* __restrict__ part_p, const double* __restrict__ part_k,
                            const unsigned* __restrict__ part_w, int nblk, int nbins,
                            float4* __restrict__ out, unsigned long long* __restrict__ counts) {
   const int b = blockIdx.x * blockDim.x + threadIdx.x;
   if (b >= nbins) return;
-  float sp = 0.f, cp = 0.f, sk = 0.f, ck = 0.f;
+  double sp = 0.0, cp = 0.0, sk = 0.0, ck = 0.0;
   unsigned long long w = 0;
   for (int i = 0; i < nblk; ++i) {
-    const float xp = part_p[(int64_t)i * nbins + b];
-    float t = sp + xp;
-    cp += (fabsf(sp) >= fabsf(xp)) ? (sp - t) + xp : (xp - t) + sp;
+    const double xp = part_p[(int64_t)i * nbins + b];
+    double t = sp + xp;
+    cp += (fabs(sp) >= fabs(xp)) ? (sp - t) + xp : (xp - t) + sp;
     sp = t;
-    const float xk = part_k[(int64_t)i * nbins + b];
+    const double xk = part_k[(int64_t)i * nbins + b];
     t = sk + xk;
-    ck += (fabsf(sk) >= fabsf(xk)) ? (sk - t) + xk : (xk - t) + sk;
+    ck += (fabs(sk) >= fabs(xk)) ? (sk - t) + xk : (xk - t) + sk;
     sk = t;
     w += part_w[(int64_t)i * nbins + b];
   }
-  out[b] = make_float4(sp, cp, sk, ck);
+  const double P = sp + cp, K = sk + ck;
+  const float ph = (float)P, kh = (float)K;
+  out[b] = make_float4(ph, (float)(P - (double)ph), kh, (float)(K - (double)kh));
   counts[b] = w;
 }
 
 size_t pk_scratch_bytes(const Layout&, int nbins) {
-  return align_up((size_t)kPkBlocks * nbins * 3 * sizeof(float));
+  return align_up((size_t)kPkBlocks * nbins * (2 * sizeof(double) + sizeof(unsigned)));
 }
 
 void launch_pk(const Layout& L, const float2* dk, int nbins, void* scratch, float4* out,
                unsigned long long* counts, hipStream_t s) {
   if (nbins > kPkMaxBins) throw Error{COLA_E_ARG, "nbins exceeds 2048"};
-  float* part_p = static_cast<float*>(scratch);
-  float* part_k = part_p + (size_t)kPkBlocks * nbins;
+  double* part_p = static_cast<double*>(scratch);
+  double* part_k = part_p + (size_t)kPkBlocks * nbins;
   unsigned* part_w = reinterpret_cast<unsigned*>(part_k + (size_t)kPkBlocks * nbins);
   const float kf = (float)(2.0 * M_PI / L.box);
   const float vol = (float)(L.box * L.box * L.box);

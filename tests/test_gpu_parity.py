@@ -129,6 +129,17 @@ PM_CASES = {
                                box=64.0, a=0.8, rms=2.0, clustered=True),
     "kmouflage_m2_radix3": dict(model=C.KMOUFLAGE, km_lambda=5e7, km_m=2, km_k0=0.3, np1d=24,
                                 nmesh1d=48, box=48.0, a=1.0, rms=1.5, clustered=True),
+    # general (non-planar) fields on the mesh sizes the ensemble and serving runs use: the
+    # three- and four-stage plans of 128, 256 and 512 points and their 8- and 16-column
+    # X tiles, with every Fourier component populated
+    "fr_f5_64_128": dict(model=C.FR_HS1, fr0_abs=1e-5, np1d=64, nmesh1d=128, box=128.0, a=0.8,
+                         rms=3.0, clustered=True),
+    "ndgp_128_256": dict(model=C.NDGP, rc_h0=1.0, np1d=128, nmesh1d=256, box=256.0, a=1.0,
+                         rms=3.0, clustered=True),
+    "symmetron_96_192": dict(model=C.SYMMETRON, np1d=96, nmesh1d=192, box=192.0, a=0.9, rms=2.0,
+                             clustered=True),
+    "fr_f6_256_512": dict(model=C.FR_HS1, fr0_abs=1e-6, np1d=256, nmesh1d=512, box=512.0, a=1.0,
+                          rms=3.0, clustered=True),
 }
 
 
@@ -178,6 +189,18 @@ def test_initial_conditions_match_oracle(model):
     record(f"ic_model{model}", u=err)
     assert err < 1e-5
     assert float(st.vel_f.abs().max()) == 0.0
+
+
+@pytest.mark.parametrize("model,n_p", [(C.FR_HS1, 128), (C.NDGP, 128), (C.LCDM, 256)])
+def test_initial_conditions_match_oracle_larger_grids(model, n_p):
+    """2LPT initial conditions on 128^3 and 256^3 particle grids (the 3- and 4-stage plans,
+    8- and 16-column X tiles of the K_HESS, K_POT, K_GRAD and K_LPT passes)."""
+    p = C.Params(model=model, np1d=n_p, nmesh1d=2 * n_p, box=2.0 * n_p, n_steps=10, seed=7)
+    st = _ic_state(p)
+    r = Run(to_oracle(p))
+    err = relrms(st.disp_f.cpu().numpy(), r.u)
+    record(f"ic_model{model}_{n_p}", u=err)
+    assert err < 1e-5
 
 
 @pytest.mark.parametrize("model", [C.FR_HS1, C.NDGP, C.SYMMETRON, C.MBETA, C.KMOUFLAGE])

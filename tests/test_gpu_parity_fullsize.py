@@ -393,3 +393,44 @@ def test_fullsize_initial_conditions_512():
     e = dict(u=math.sqrt(num / den), u_rms=math.sqrt(den / u.size))
     record("fullsize_initial_conditions_512", **e)
     assert e["u"] < 1e-5, e
+
+
+def test_fullsize_power_spectrum_1024():
+    """P(k) on a 1024^3 mesh: a 512^3-particle F5 state after its initial conditions (the
+    scale-dependent workload at half the headline size).  The GPU's own density mesh (rho
+    from cola_pm_force) goes through the oracle's FP64 FFT and shell binning, and
+    cola_power_spectrum (the same deposit, bitwise, then the FP32 FFT and FP64 shell sums)
+    must agree per bin to 0.1 % up to half the mesh Nyquist frequency, with the same mode
+    counts."""
+    from oracle import fftlib
+    from oracle.pk import power_spectrum_mesh
+    p = C.Params(model=C.FR_HS1, fr0_abs=1e-5, np1d=512, nmesh1d=1024, box=1024.0, n_steps=20,
+                 seed=11)
+    st = C.State(p)
+    C.cola_make_ic(p, st)
+    n, nb = p.nmesh1d, p.nmesh1d // 4 + 1
+    k, P, nm = C.cola_power_spectrum(p, st, nbins=nb)
+    M = n ** 3
+    mesh = torch.empty(5, M, dtype=torch.float32, device="cuda")
+    C.cola_pm_force(p, st, 0.05, None, mesh)
+    torch.cuda.synchronize()
+    rho = mesh[0].cpu().numpy()
+    del mesh, st
+    gc.collect()
+    torch.cuda.empty_cache()
+    delta = rho.astype(np.float64).reshape(n, n, n)
+    delta -= 1.0
+    del rho
+    w0 = fftlib.workers()
+    fftlib.set_workers(16)
+    try:
+        ko, Po, nmo = power_spectrum_mesh(delta, p.box, nb)
+    finally:
+        fftlib.set_workers(w0)
+    del delta
+    assert np.array_equal(nm[1:], nmo[1:].astype(np.int64))
+    e_p = float(np.max(np.abs(P[1:] / Po[1:] - 1)))
+    e_k = float(np.max(np.abs(k[1:] / ko[1:] - 1)))
+    record("fullsize_pk_1024", pk=e_p, k=e_k)
+    assert e_p < 1e-3, f"P(k) {e_p:.2e}"
+    assert e_k < 1e-6, f"k {e_k:.2e}"
