@@ -238,6 +238,21 @@ def traffic_for(kernel):
     return None if k is None else k.get("bytes_per_launch")
 
 
+def counted_bytes_per_step():
+    """HBM bytes of one step counted by rocprofv3 (FETCH_SIZE and WRITE_SIZE, copy-calibrated,
+    summed over the step's kernels) from the committed summary, or None if it is missing
+    or was taken on different kernel sources."""
+    path = os.path.join(ROOT, "profiles", TRAFFIC_FILE)
+    try:
+        d = json.load(open(path))
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != source_hash():
+        return None
+    return sum(k["bytes_per_launch"] * k["launches_per_step"] for k in d.get("kernels", {}).values()
+               if k.get("bytes_per_launch") is not None)
+
+
 # rocprofv3 kernel symbols of one step -> the names the library's HIP-event profiler uses
 # ({n}: mesh size; {np}: particle-grid size; {nph} = np/2, the complex row length of the
 # particle grid's real transforms); the first pattern that matches wins
@@ -641,6 +656,12 @@ def main():
                    "box_mpc_h": p.box, "n_steps": p.n_steps, "seed": p.seed,
                    "parallelism": "single GPU"},
         "roofline": roofline_of(p, prof, traffic_for),
+        # HBM fraction of the whole step: rocprofv3-counted bytes of a step (committed
+        # profile of these kernel sources) over the measured step time; the modelled
+        # yardstick figure beside it
+        "hbm_frac_counted": (None if counted_bytes_per_step() is None else
+                             counted_bytes_per_step() / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS),
+        "counted_bytes_per_step": counted_bytes_per_step(),
         "hbm_frac_yardstick": yard / (ms_step / 1e3) / 1e9 / HBM_PEAK_GBS,
         "yardstick_bytes_per_step": yard,
         "ic_ms": ic_ms[-1], "pk_ms": pk_ms, "finite": ok,
