@@ -487,6 +487,17 @@ k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
   const int col = (int)base + c0;
   const int iy = col / op.pitch, iz = col % op.pitch;
   float2 g[NB0][R0];
+  if constexpr (DK) {
+    // delta_k of the thread's elements, loaded with S's (same element map as the first
+    // stage) so that both reads are in flight together; g takes them until the Green's
+    // function replaces them
+#pragma unroll
+    for (int i = 0; i < NB0; ++i) {
+      const int j = (tid + i * T) / B;
+#pragma unroll
+      for (int r = 0; r < R0; ++r) g[i][r] = load_stream(dk + base + (O)(j + r * (N / R0)) * es + c0);
+    }
+  }
   auto load = [&](int, int, int j, int c) -> float2 { return load_stream(src + base + (O)j * es + c); };
   if constexpr (!DK && kHandOff<N>) {
     // one source: g is formed in the forward transform's last stage, in registers
@@ -503,7 +514,7 @@ k_fft_col_fwd_force(const float2* dk, const float2* src, float2* o0, float2* o1,
       for (int r = 0; r < R0; ++r) {
         const int jj = j + r * (N / R0);
         const float2 sv = lds[jj * B + c0];
-        const float2 dv = DK ? load_stream(dk + base + (O)jj * es + c0) : sv;
+        const float2 dv = DK ? g[i][r] : sv;
         g[i][r] = green_force(op, jj, iy, iz, dv, sv);
       }
     }

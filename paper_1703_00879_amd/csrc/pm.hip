@@ -34,15 +34,6 @@ __device__ __forceinline__ void cic_axis(int ixq, float u, int nm, int ratio, fl
   w1 = d;
 }
 
-__device__ __forceinline__ void cic_cell(int64_t p, int np, int nm, int ratio, float inv_cell,
-                                         const float* __restrict__ disp, int64_t N, CicCell& c) {
-  const int ip = (int)p;
-  const int ix = ip / (np * np), iy = (ip / np) % np, iz = ip % np;
-  cic_axis(ix, disp[p], nm, ratio, inv_cell, c.i0[0], c.i1[0], c.w0[0], c.w1[0]);
-  cic_axis(iy, disp[N + p], nm, ratio, inv_cell, c.i0[1], c.i1[1], c.w0[1], c.w1[1]);
-  cic_axis(iz, disp[2 * N + p], nm, ratio, inv_cell, c.i0[2], c.i1[2], c.w0[2], c.w1[2]);
-}
-
 static bool is_pow2(int v) { return v > 0 && (v & (v - 1)) == 0; }
 static int ilog2(int v) {
   int l = 0;
@@ -549,8 +540,32 @@ k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int 
     p = blk * (int64_t)blockDim.x + threadIdx.x;
   }
   if (p >= N) return;
+  // the particle's own values (velocity, LPT terms) do not depend on its cell: their
+  // loads go out first, so that they are in flight while the force corners are fetched
+  float uu[3], vv[3], l[3], d[3], s1[3], s2[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) uu[a] = g.disp[a * N + p];
+  if (MODE != 2) {
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+      vv[a] = g.vel[a * N + p];
+      if (MODE == 0) {
+        s1[a] = g.psi1[a * N + p];
+        s2[a] = g.psi2[a * N + p];
+      } else {
+        l[a] = g.l3[3 * p + a];
+        d[a] = g.d3[3 * p + a];
+      }
+    }
+  }
   CicCell c;
-  cic_cell(p, np, nm, ratio, inv_cell, g.disp, N, c);
+  {
+    const int ip = (int)p;
+    const int ix = ip / (np * np), iy = (ip / np) % np, iz = ip % np;
+    cic_axis(ix, uu[0], nm, ratio, inv_cell, c.i0[0], c.i1[0], c.w0[0], c.w1[0]);
+    cic_axis(iy, uu[1], nm, ratio, inv_cell, c.i0[1], c.i1[1], c.w0[1], c.w1[1]);
+    cic_axis(iz, uu[2], nm, ratio, inv_cell, c.i0[2], c.i1[2], c.w0[2], c.w1[2]);
+  }
   float f0 = 0.f, f1 = 0.f, f2 = 0.f;
 #pragma unroll
   for (int ox = 0; ox < 2; ++ox) {
@@ -575,7 +590,6 @@ k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int 
     g.force_out[2 * N + p] = f2;
     return;
   }
-  float l[3], d[3];
   if (MODE == 0) {
     const double* t0 = g.table + g.slice0;
     const double* t1 = g.table + g.slice1;
@@ -583,23 +597,16 @@ k_gather(GatherDev g, int64_t N, int np, int nm, int ratio, float inv_cell, int 
     const float e1 = (float)(t1[0] - t0[0]), e2 = (float)(t1[3] - t0[3]);
 #pragma unroll
     for (int a = 0; a < 3; ++a) {
-      const float s1 = g.psi1[a * N + p], s2 = g.psi2[a * N + p];
-      l[a] = c1 * s1 + c2 * s2;
-      d[a] = e1 * s1 + e2 * s2;
-    }
-  } else {
-#pragma unroll
-    for (int a = 0; a < 3; ++a) {
-      l[a] = g.l3[3 * p + a];
-      d[a] = g.d3[3 * p + a];
+      l[a] = c1 * s1[a] + c2 * s2[a];
+      d[a] = e1 * s1[a] + e2 * s2[a];
     }
   }
   const float fv[3] = {f0, f1, f2};
 #pragma unroll
   for (int a = 0; a < 3; ++a) {
-    const float v = g.vel[a * N + p] + g.dtk * (fv[a] - l[a]);
+    const float v = vv[a] + g.dtk * (fv[a] - l[a]);
     g.vel[a * N + p] = v;
-    g.disp[a * N + p] = g.disp[a * N + p] + (g.dtd * v + d[a]);
+    g.disp[a * N + p] = uu[a] + (g.dtd * v + d[a]);
   }
 }
 
