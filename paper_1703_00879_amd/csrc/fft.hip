@@ -153,7 +153,7 @@ COLA_PLAN(512, 8, 3, 8, 8, 8)
 COLA_PLAN(768, 24, 4, 8, 8, 4, 3)
 COLA_PLAN(1024, 16, 4, 8, 8, 4, 4)
 COLA_PLAN(1536, 24, 4, 8, 8, 8, 3)
-COLA_PLAN(2048, 16, 4, 8, 8, 8, 4)
+COLA_PLAN(2048, 32, 4, 8, 8, 8, 4)   // 32 per thread: 512 threads per 8-column tile
 #undef COLA_PLAN
 // First and last radix equal: a transform's last stage can hand its outputs to the next
 // transform's first stage in registers (kStoreIR).
@@ -392,12 +392,13 @@ k_fft_col(float2* __restrict__ data, int64_t elemStride, int64_t tilesPerBlock,
 // Tile of the forward-operator-inverse X pass: the X-pass tile (for 1024-point columns 8
 // to a 64 KB tile, two work-groups per CU, 25 % faster than one 16-column tile per CU).
 // Elements per thread of the fused kernels that keep a column (or the Green's function)
-// in registers across two transforms of a tile.  With the plan's 16 elements a 2048-point
-// tile of 8 columns needs 1024 threads, whose 128-register budget per lane spills 150-180
-// bytes per lane to scratch memory (through the L2 to HBM); 32 elements per thread on 512
-// threads get 256 registers and spill 0-64 bytes, and measured 12-30 % faster.  At 1024
-// points the larger E spilled more and ran slower, so there the plan's E stays.  Each
-// butterfly is computed the same way whatever E is.
+// in registers across two transforms of a tile.  With 16 elements a 2048-point tile of 8
+// columns needs 1024 threads, whose 128-register budget per lane spilled 150-180 bytes per
+// lane to scratch memory (through the L2 to HBM); 32 elements per thread on 512 threads
+// get 256 registers and spill 0-64 bytes, and measured 12-30 % faster (the 2048-point plan
+// now takes 32 for every column pass; the plain Y passes gained 2.5 %).  At 1024 points
+// the larger E spilled more and ran slower, so there the plan's E stays.  Each butterfly
+// is computed the same way whatever E is.
 template <int N, int B>
 struct FusedCfg {
   static constexpr int E = (N >= 2048 && N * B / ColCfg<N>::E >= 1024) ? 2 * ColCfg<N>::E
