@@ -118,7 +118,7 @@ struct Bufs {
   float* psi1;
   float* psi2;
   void* bins;
-  float4* entries;
+  void* entries;     // the deposit's 12-byte CIC records
   StepDev* steps;     // per-step scalars of every step
   int* ctr;           // device step counter: the step the step kernels read
 };
@@ -164,7 +164,7 @@ static Bufs carve(const cola_params& p, const cola_state* st, void* work = nullp
   b.lpp3 = L.kdep ? at<float>(work, L.off_lpp3) : nullptr;
   b.dlt3 = L.kdep ? at<float>(work, L.off_dlt3) : nullptr;
   b.bins = at<void>(work, L.off_bins);
-  b.entries = at<float4>(work, L.off_entries);
+  b.entries = at<void>(work, L.off_entries);
   if (L.kdep) {
     b.phi1 = at<float2>(st->lpt, 0);
     b.phi2 = at<float2>(st->lpt, align_up(L.pgrid_elems * sizeof(float2)));

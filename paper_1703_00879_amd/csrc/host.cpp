@@ -397,7 +397,7 @@ Layout make_layout(const cola_params& p) {
   L.ntiles = (int64_t)L.nt1 * L.nt1 * L.nt1;
   L.off_bins = o;
   o += bins_bytes(L.ntiles);
-  const size_t entries_bytes = align_up((size_t)L.N * sizeof(float4));
+  const size_t entries_bytes = align_up((size_t)L.N * 12);   // one 12-byte CIC record per particle
   // k-Mouflage deposits a second time while the Newtonian force mesh (over slots 3-5) is
   // still needed, so its records get their own area
   if (entries_bytes <= mesh_bytes && p.model != COLA_KMOUFLAGE) {

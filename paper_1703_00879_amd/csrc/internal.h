@@ -328,9 +328,9 @@ struct KmArgs {
 void launch_kmouflage_source(const Layout& L, const float* rho, const float* f3, float* out,
                              float* s_out, const KmArgs& k, hipStream_t s);
 // CIC deposit into the padded real mesh.  `bins` is the work area at off_bins, `entries`
-// the packed per-particle CIC records sorted by home tile (float4 each).
+// the packed per-particle CIC records sorted by home tile (12 bytes each).
 void launch_deposit(const Layout& L, const float* disp, float* rho_padded, void* bins,
-                    float4* entries, hipStream_t s);
+                    void* entries, hipStream_t s);
 size_t bins_bytes(int64_t ntiles);
 struct GatherArgs {
   const float* F3;            // interleaved force mesh (F_x, F_y, F_z) per cell

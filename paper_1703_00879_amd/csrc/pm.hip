@@ -134,8 +134,24 @@ __device__ __forceinline__ bool brick_particle(const BinGeo& g, int b, int& ix, 
   return true;
 }
 
+// CIC record of a particle (12 bytes): per axis, the lower corner's cell inside its home
+// tile (bits 28-31) and the offset d in [0, 1) as a 28-bit fraction (bits 0-27).  The
+// record is lossless: f = 1/2 + u/cell is an FP32 sum with 1/2, so f and d = f - floor(f)
+// are multiples of 2^-25 (of 2^-23 once |f| >= 1), and d * 2^28 is an integer below 2^28
+// whose conversion back to FP32 is exact.  Four bytes less per particle than a float4
+// record, written by the scatter and read by the deposit.
+struct CicRec {
+  uint32_t x, y, z;
+};
+__device__ __forceinline__ uint32_t rec_axis(int local, float d) {
+  return ((uint32_t)local << 28) | (uint32_t)(d * 268435456.f);
+}
+__device__ __forceinline__ float rec_d(uint32_t v) {
+  return (float)(v & 0x0FFFFFFFu) * (1.f / 268435456.f);
+}
+
 // MODE 0: count into cnt[tile*8 + cls];  MODE 1: scatter the particle's CIC record
-// (dx, dy, dz, lower corner relative to its home tile) to entries[cur[tile*8 + cls]++].
+// (offsets and lower corner relative to its home tile) to entries[cur[tile*8 + cls]++].
 // A work-group takes kBinBricks consecutive bricks and each thread one particle of each,
 // with all displacement loads issued up front.  The lanes of a wave that share a
 // (tile, class) key are served by one atomic that adds their number; in MODE 1 each lane
@@ -144,7 +160,7 @@ __device__ __forceinline__ bool brick_particle(const BinGeo& g, int b, int& ix, 
 template <int MODE, bool P2>
 __global__ void __launch_bounds__(256)
 k_bin(const float* __restrict__ disp, BinGeo g, uint32_t* __restrict__ cnt,
-      uint32_t* __restrict__ cur, float4* __restrict__ entries) {
+      uint32_t* __restrict__ cur, CicRec* __restrict__ entries) {
   constexpr int S = kBinBricks;
   const int b0 = (int)xcd_block(blockIdx.x, gridDim.x) * S;
   bool valid[S];
@@ -166,11 +182,11 @@ k_bin(const float* __restrict__ disp, BinGeo g, uint32_t* __restrict__ cnt,
   const int lane = (int)__lane_id();
   uint32_t gbase[S], myrank[S];
   int mygroup[S];
-  float4 rec[S];
+  CicRec rec[S];
 #pragma unroll
   for (int s = 0; s < S; ++s) {
     unsigned key = 0xffffffffu;
-    rec[s] = make_float4(0.f, 0.f, 0.f, 0.f);
+    rec[s] = CicRec{0u, 0u, 0u};
     if (valid[s]) {
       float dx, dy, dz;
       const int cx = axis_cell<P2>(ix[s], ux[s], g, dx);
@@ -179,8 +195,7 @@ k_bin(const float* __restrict__ disp, BinGeo g, uint32_t* __restrict__ cnt,
       const int lt = g.lt, m = g.tile - 1;
       const int tile = ((cx >> lt) * g.nt1 + (cy >> lt)) * g.nt1 + (cz >> lt);
       const int cls = ((cx & m) == m ? 1 : 0) | ((cy & m) == m ? 2 : 0) | ((cz & m) == m ? 4 : 0);
-      const unsigned local = (unsigned)(cx & m) | ((unsigned)(cy & m) << 8) | ((unsigned)(cz & m) << 16);
-      rec[s] = make_float4(dx, dy, dz, __uint_as_float(local));
+      rec[s] = CicRec{rec_axis(cx & m, dx), rec_axis(cy & m, dy), rec_axis(cz & m, dz)};
       key = (unsigned)tile * 8u + (unsigned)cls;
     }
     // group the wave's lanes by key with ballots (no memory traffic); group i's key and
@@ -323,7 +338,7 @@ __device__ __forceinline__ float fix_to_float(unsigned long long v) {
 
 template <int T>
 __global__ void __launch_bounds__(kDepositThreads)
-k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__ start,
+k_deposit_tiles(const CicRec* __restrict__ entries, const uint32_t* __restrict__ start,
                 const uint32_t* __restrict__ cnt, BinGeo g, float* __restrict__ rho, int rpitch,
                 int64_t rplane, float mass) {
   // 64-bit fixed-point accumulation in units of 2^-24: integer LDS atomics run several
@@ -382,13 +397,13 @@ k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__
   // batches of KB records per thread: all loads are issued before the LDS accumulation
   constexpr int KB = 4;
   for (uint32_t e0 = threadIdx.x; e0 < total; e0 += KB * blockDim.x) {
-    float4 r[KB];
+    CicRec r[KB];
     int dd[KB];
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
       const uint32_t e = e0 + k * blockDim.x;
       dd[k] = -1;
-      r[k] = make_float4(0.f, 0.f, 0.f, 0.f);
+      r[k] = CicRec{0u, 0u, 0u};
       if (e < total) {
         while (so[sg + 1] <= e) ++sg;
         dd[k] = sdd[sg];
@@ -401,12 +416,11 @@ k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__
       if (d < 0) continue;
       // the lower corner of a particle of tile T - d lies at (home-tile coordinate - T)
       // on every axis where d is set
-      const unsigned loc = __float_as_uint(r[k].w);
-      const int lx0 = (int)(loc & 255u) - ((d & 1) ? T : 0);
-      const int ly0 = (int)((loc >> 8) & 255u) - (((d >> 1) & 1) ? T : 0);
-      const int lz0 = (int)((loc >> 16) & 255u) - (((d >> 2) & 1) ? T : 0);
-      const float wx[2] = {1.f - r[k].x, r[k].x}, wy[2] = {1.f - r[k].y, r[k].y},
-                  wz[2] = {1.f - r[k].z, r[k].z};
+      const int lx0 = (int)(r[k].x >> 28) - ((d & 1) ? T : 0);
+      const int ly0 = (int)(r[k].y >> 28) - (((d >> 1) & 1) ? T : 0);
+      const int lz0 = (int)(r[k].z >> 28) - (((d >> 2) & 1) ? T : 0);
+      const float dx = rec_d(r[k].x), dy = rec_d(r[k].y), dz = rec_d(r[k].z);
+      const float wx[2] = {1.f - dx, dx}, wy[2] = {1.f - dy, dy}, wz[2] = {1.f - dz, dz};
 #pragma unroll
       for (int o = 0; o < 8; ++o) {
         const int lx = lx0 + (o & 1), ly = ly0 + ((o >> 1) & 1), lz = lz0 + ((o >> 2) & 1);
@@ -429,8 +443,9 @@ k_deposit_tiles(const float4* __restrict__ entries, const uint32_t* __restrict__
   }
 }
 
-void launch_deposit(const Layout& L, const float* disp, float* rho, void* bins, float4* entries,
+void launch_deposit(const Layout& L, const float* disp, float* rho, void* bins, void* entries_raw,
                     hipStream_t s) {
+  CicRec* entries = static_cast<CicRec*>(entries_raw);
   BinGeo g;
   g.np = L.np;
   g.nm = L.nm;

@@ -36,8 +36,8 @@ def test_query_sizes_and_layout():
     ntiles = (1024 // 16) ** 3                          # 16^3-cell deposit tiles
     nblk = -(-ntiles // 1024)
     bins = -(-(17 * ntiles + 2 * nblk + 64) * 4 // 256) * 256
-    # six mesh slots + tile counters; the sorted CIC records (16 B each) fit in slot 5
-    assert 16 * N <= mesh and s["work_bytes"] == 6 * mesh + bins
+    # six mesh slots + tile counters; the sorted CIC records (12 B each) fit in slot 5
+    assert 12 * N <= mesh and s["work_bytes"] == 6 * mesh + bins
     assert s["total_bytes"] == sum(v for k, v in s.items() if k != "total_bytes")
     # scale-dependent f(R) stores phi1_k, phi2_k; its per-step LPT work (three
     # particle-grid fields and the interleaved L'' and Delta arrays) lies over mesh slots
@@ -52,8 +52,8 @@ def test_query_sizes_and_layout():
     mq, pq = up(128 * (128 * 80 + 16) * 8), up(128 * (128 * 80 + 16) * 8)
     nt = (128 // 16) ** 3
     bq = -(-(17 * nt + 2 * (-(-nt // 1024)) + 64) * 4 // 256) * 256
-    # (and the 16-byte CIC records, larger than a slot here, get their own area too)
-    assert sq["work_bytes"] == 6 * mq + 3 * pq + 2 * up(12 * 128 ** 3) + bq + up(16 * 128 ** 3)
+    # (and the 12-byte CIC records, larger than a slot here, get their own area too)
+    assert sq["work_bytes"] == 6 * mq + 3 * pq + 2 * up(12 * 128 ** 3) + bq + up(12 * 128 ** 3)
 
 
 @pytest.mark.parametrize("bad", [dict(np1d=30), dict(np1d=40), dict(nmesh1d=96, np1d=64),
