@@ -68,8 +68,8 @@ def algorithmic_bytes(name, p):
     table = {
         "bin_count": 12 * N,                         # read u; tile counts are negligible
         "bin_scan": 0,
-        "bin_scatter": 12 * N + 16 * N,              # read u, write one 16-byte entry each
-        "deposit": 16 * N + 4 * M,                   # read entries, write the density once
+        "bin_scatter": 12 * N + 12 * N,              # read u, write one 12-byte record each
+        "deposit": 12 * N + 4 * M,                   # read records, write the density once
         "fft_r2c_z": 4 * M + 8 * H,                  # read real mesh, write half-complex
         "fft_c2r_z": 8 * H + 4 * M,
         "fft_y_fwd": 16 * H, "fft_x_fwd": 16 * H, "fft_y_inv": 16 * H,

@@ -44,7 +44,7 @@ def test_algorithmic_bytes(bench):
     assert ab("fft_c2r_z3") == 24 * H + 12 * M
     assert ab("fft_x_fwd_smooth") == 16 * H and ab("fft_x_fwd_pot") == 24 * H
     assert ab("fft_x_fwd_force_1src") == 24 * H and ab("fft_x_fwd_force") == 32 * H
-    assert ab("deposit") == 16 * N + 4 * M
+    assert ab("deposit") == 12 * N + 4 * M and ab("bin_scatter") == 24 * N
     Hp = p.np1d ** 2 * (p.np1d // 2 + 1)
     assert ab("lpt_fft_x_inv") == 32 * Hp and ab("lpt_fft_y_inv") == 16 * Hp
     assert ab("lpt_fft_y_inv_yz") == 24 * Hp and ab("lpt_fft_c2r_z3") == 24 * Hp + 12 * N
