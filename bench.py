@@ -610,7 +610,8 @@ def main():
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
-              "(the multi-GPU decomposition is not part of this build)", file=sys.stderr)
+              "(the library runs each state on one GPU; a multi-GPU decomposition is not "
+              "implemented)", file=sys.stderr)
         sys.exit(2)
     if args.steps < 1 or args.warmup < 0:
         print("--steps must be >= 1 and --warmup >= 0", file=sys.stderr)
