@@ -272,8 +272,9 @@ cola_status cola_growth_triangles(const cola_params* p, int32_t n, const double*
  * (cola_ensemble_run) keeps the widths in use when it was captured.
  * cola_fft_tiles: n = a supported transform size (8 ... 2048, 2^a 3^b as the mesh);
  *   fwd / inv = 4, 8 or 16 sets the width of the forward / inverse pass, 0 restores the
- *   default, -1 leaves it; COLA_E_ARG if a width does not fit n (N * width / radix-group
- *   threads above 1024, or LDS above 160 KB).  cur_out (host int32 [2], may be NULL)
+ *   default, -1 leaves it; COLA_E_ARG if a width does not fit n (more than 1024 threads,
+ *   n * width over the plan's elements per thread, or more than 160 KB of LDS), or if n
+ *   is not supported.  cur_out (host int32 [2], may be NULL)
  *   receives the widths now in use (forward, inverse).
  * cola_autotune: times every valid width of both directions for the PM mesh and the
  *   particle grid of p on the state's work buffer (its contents are overwritten; the
