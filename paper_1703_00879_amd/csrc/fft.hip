@@ -673,14 +673,15 @@ __device__ __forceinline__ void row_twiddles(float2* tw, const float2* __restric
 // block's rows while transforming the current ones; kPersist says whether they run as a
 // persistent grid (as many work-groups as fit the device at once) or one work-group per
 // block.  At 1024 the persistent one-row form measured 2-45 % faster, depending on the
-// pass, than four-row tiles one work-group per block; at 512 the multi-row tiles one
-// work-group per block were the faster ones.
+// pass, than four-row tiles one work-group per block, and the persistent grid took
+// 7-20 % off the multi-row passes of 96-384-point rows (the ensemble and serving
+// meshes); at 512 the multi-row tiles one work-group per block were the faster ones.
 template <int NC>
 struct RowCfg {
   static constexpr int E = kRowE<NC>;
   static constexpr int B0 = pow2_floor(4096 / NC);
   static constexpr int B = NC >= 1024 ? 1 : (B0 < 1 ? 1 : (B0 > 64 ? 64 : B0));
-  static constexpr bool kPersist = NC >= 1024;
+  static constexpr bool kPersist = NC != 512;
   static constexpr int T = NC * B / E;
   // odd LDS stride: transposed row loads stay conflict-light; one row needs no padding
   static constexpr int LS = B == 1 ? 1 : B + 1;
@@ -947,13 +948,13 @@ k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
 // Screening row pass tiles.  The pass keeps the next rows, their densities and two
 // transforms' operands in registers (about 150 per lane); with one row of 512 or 1024
 // complex values per work-group (16-24 KB of LDS) enough work-groups share a CU to overlap
-// loads with transforms: persistent, 32 % faster than four-row tiles at 1024 and 40 %
-// faster than eight-row tiles at 512.
+// loads with transforms: 32 % faster than four-row tiles at 1024 and 40 % faster than
+// eight-row tiles at 512.  The pass is persistent at every size.
 template <int NC>
 struct ScreenCfg {
   static constexpr int E = RowCfg<NC>::E;
   static constexpr int B = NC >= 512 ? 1 : RowCfg<NC>::B;
-  static constexpr bool kPersist = NC >= 512;
+  static constexpr bool kPersist = true;
   static constexpr int T = NC * B / E;
   static constexpr int LS = B == 1 ? 1 : B + 1;
 };
