@@ -154,6 +154,25 @@ COLA_PLAN(768, 24, 4, 8, 8, 4, 3)
 COLA_PLAN(1024, 16, 4, 8, 8, 4, 4)
 COLA_PLAN(1536, 24, 4, 8, 8, 8, 3)
 COLA_PLAN(2048, 32, 4, 8, 8, 8, 4)   // 32 per thread: 512 threads per 8-column tile
+// Plans of the row passes: the column plans, except that the lengths with a factor 3 take
+// radices 4, 2 and 3 only, so that 12 elements per thread divide by every radix instead of
+// 24 (a row pass holds its next block's rows in registers besides the butterflies).
+template <int N>
+struct RowPlan : Plan<N> {};
+#define COLA_ROW_PLAN(N_, E_, NST_, ...)                          \
+  template <>                                                     \
+  struct RowPlan<N_> {                                            \
+    static constexpr int E = E_;                                  \
+    static constexpr int nst = NST_;                              \
+    static constexpr int rad[NST_] = {__VA_ARGS__};               \
+  };
+COLA_ROW_PLAN(24, 12, 3, 4, 2, 3)
+COLA_ROW_PLAN(48, 12, 3, 4, 4, 3)
+COLA_ROW_PLAN(96, 12, 4, 4, 4, 2, 3)
+COLA_ROW_PLAN(192, 12, 4, 4, 4, 4, 3)
+COLA_ROW_PLAN(384, 12, 5, 4, 4, 4, 2, 3)
+COLA_ROW_PLAN(768, 12, 5, 4, 4, 4, 4, 3)
+#undef COLA_ROW_PLAN
 #undef COLA_PLAN
 // First and last radix equal: a transform's last stage can hand its outputs to the next
 // transform's first stage in registers (kStoreIR).
@@ -177,14 +196,14 @@ __device__ __forceinline__ float2 stage_twiddle(const float2* __restrict__ tw, i
 // Per-stage twiddle table of the N-point plan (N - 1 entries, stage after stage, the
 // entries of a stage ordered by butterfly k then operand r) from the full table of a
 // transform of length N * S (src[t] = exp(-2 pi i t / (N S))).
-template <int N>
+template <int N, class P = Plan<N>>
 __device__ __forceinline__ void fill_stage_twiddles(float2* tw, const float2* __restrict__ src,
                                                     int S, int tid, int T) {
   for (int e = tid; e < N - 1; e += T) {
     int rest = e, ns = 1, t = 0;
 #pragma unroll
-    for (int st = 0; st < Plan<N>::nst; ++st) {
-      const int R = Plan<N>::rad[st];
+    for (int st = 0; st < P::nst; ++st) {
+      const int R = P::rad[st];
       const int cnt = ns * (R - 1);
       if (rest >= 0 && rest < cnt) t = (rest % (R - 1) + 1) * (rest / (R - 1)) * (N / (ns * R));
       rest -= cnt;
@@ -232,20 +251,20 @@ __device__ __forceinline__ void stockham_stage(float2* lds, int tid, int T, cons
   __syncthreads();
 }
 
-template <int N, int DIR, int E, int B, int LS, int TWS, int S, int NS>
+template <int N, int DIR, int E, int B, int LS, int TWS, int S, int NS, class P>
 struct Stages {
   static __device__ __forceinline__ void run(float2* lds, int tid, int T, const float2* tw) {
-    if constexpr (S < Plan<N>::nst) {
-      constexpr int R = Plan<N>::rad[S];
+    if constexpr (S < P::nst) {
+      constexpr int R = P::rad[S];
       stockham_stage<N, R, NS, DIR, E, B, LS, TWS>(lds, tid, T, tw);
-      Stages<N, DIR, E, B, LS, TWS, S + 1, NS * R>::run(lds, tid, T, tw);
+      Stages<N, DIR, E, B, LS, TWS, S + 1, NS * R, P>::run(lds, tid, T, tw);
     }
   }
 };
 
-template <int N, int DIR, int E, int B, int LS, int TWS>
+template <int N, int DIR, int E, int B, int LS, int TWS, class P = Plan<N>>
 __device__ __forceinline__ void lds_fft(float2* lds, int tid, int T, const float2* tw) {
-  Stages<N, DIR, E, B, LS, TWS, 0, 1>::run(lds, tid, T, tw);
+  Stages<N, DIR, E, B, LS, TWS, 0, 1, P>::run(lds, tid, T, tw);
 }
 
 // Stockham transform of B columns whose first stage reads its operands through
@@ -263,14 +282,15 @@ constexpr int kFirstFromLds = 1, kLastToLds = 2;
 // operands from registers filled by this store.
 constexpr int kStoreIR = 4;
 
-template <int N, int DIR, int E, int B, int LS, int TWS, int S, int NS, int FL = 0>
+template <int N, int DIR, int E, int B, int LS, int TWS, int S, int NS, int FL = 0,
+          class P = Plan<N>>
 struct GStages {
   template <class Load, class Store>
   static __device__ __forceinline__ void run(float2* lds, int tid, int T, const float2* tw,
                                              Load& load, Store& store) {
-    constexpr int nst = Plan<N>::nst;
+    constexpr int nst = P::nst;
     if constexpr (S < nst) {
-      constexpr int R = Plan<N>::rad[S];
+      constexpr int R = P::rad[S];
       constexpr int NB = E / R;
       float2 v[NB][R];
       constexpr bool reads_lds = S > 0 || (FL & kFirstFromLds);
@@ -322,7 +342,7 @@ struct GStages {
       }
       if constexpr (S + 1 < nst) {
         __syncthreads();
-        GStages<N, DIR, E, B, LS, TWS, S + 1, NS * R, FL>::run(lds, tid, T, tw, load, store);
+        GStages<N, DIR, E, B, LS, TWS, S + 1, NS * R, FL, P>::run(lds, tid, T, tw, load, store);
       }
     }
   }
@@ -656,7 +676,7 @@ constexpr int pow2_floor(int x) { return x >= 2 ? 2 * pow2_floor(x / 2) : 1; }
 // Rows of 1024 complex values (2048-point real rows) take 8 elements per thread, half the
 // plan's 16: twice the threads per row tile, which measured 10-35 % faster row passes.
 template <int NC>
-constexpr int kRowE = NC == 1024 ? 8 : Plan<NC>::E;
+constexpr int kRowE = NC == 1024 ? 8 : RowPlan<NC>::E;
 
 // LDS twiddles of a row pass (rows of n = 2 NC reals): tw[k] = exp(-2 pi i k / n) for the
 // split steps, k < NC, then the per-stage table of the NC-point transform at tw + NC.
@@ -664,7 +684,7 @@ template <int NC>
 __device__ __forceinline__ void row_twiddles(float2* tw, const float2* __restrict__ tw_g, int tid,
                                              int T) {
   for (int i = tid; i < NC; i += T) tw[i] = tw_g[i];
-  fill_stage_twiddles<NC>(tw + NC, tw_g, 2, tid, T);
+  fill_stage_twiddles<NC, RowPlan<NC>>(tw + NC, tw_g, 2, tid, T);
 }
 
 // Row-pass tiles: rows of 1024 complex values go one to a work-group with an unpadded
@@ -803,7 +823,7 @@ k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nr
     }
     if (blk + gridDim.x < nblk) issue(blk + gridDim.x);
     __syncthreads();
-    lds_fft<NC, -1, E, B, LS, 0>(lds, tid, T, tw + NC);
+    lds_fft<NC, -1, E, B, LS, 0, RowPlan<NC>>(lds, tid, T, tw + NC);
     split_fwd_store<NC, E, B, LS, T>(lds, tw, tid, [&](int c, int k, float2 v) {
       if (r0 + c >= (O)nrows) return;
       const O r = r0 + c;
@@ -848,7 +868,7 @@ k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nr
     sp.store(tid, T, tw, lds, LS);
     if (blk + gridDim.x < nblk) sp.load(tid, T, rows_at(blk + gridDim.x));
     __syncthreads();
-    lds_fft<NC, +1, E, B, LS, 0>(lds, tid, T, tw + NC);
+    lds_fft<NC, +1, E, B, LS, 0, RowPlan<NC>>(lds, tid, T, tw + NC);
     for (int e = tid; e < NC * B; e += T) {
       const int c = e / NC, m = e % NC;
       if (r0 + c >= (O)nrows) continue;
@@ -929,7 +949,7 @@ k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
         rowp[0] = v.x;
         rowp[3] = v.y;
       };
-      GStages<NC, +1, E, B, LS, 0, 0, 1, kFirstFromLds | kLastToLds>::run(tile, lt, TC, tw + NC, load, store);
+      GStages<NC, +1, E, B, LS, 0, 0, 1, kFirstFromLds | kLastToLds, RowPlan<NC>>::run(tile, lt, TC, tw + NC, load, store);
     }
     __syncthreads();
     const O rows_here = (O)nrows - r0 < (O)B ? (O)nrows - r0 : (O)B;
@@ -984,8 +1004,9 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
   // j = b / B): the output of operand r of its butterfly i in the last inverse stage of
   // radix RL.  Its density pair (x_2m, x_2m+1) is loaded with the row, so that the
   // latency hides behind the inverse transform.
-  constexpr int RL = Plan<NC>::rad[Plan<NC>::nst - 1], NBL = E / RL;
-  constexpr bool kHandOff = RL == Plan<NC>::rad[0];
+  using RP = RowPlan<NC>;
+  constexpr int RL = RP::rad[RP::nst - 1], NBL = E / RL;
+  constexpr bool kHandOff = RL == RP::rad[0];
   // Persistent: the work-group takes row blocks blockIdx.x, + gridDim.x, ...; the field
   // and density rows of the next block are loaded into registers while this block is
   // transformed and stored.
@@ -1052,16 +1073,16 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
       {
         auto load = [&](int, int, int j, int c) -> float2 { return lds[j * LS + c]; };
         auto store = [&](int m, int c, float2 f, int i, int r) { tv[i][r] = source(f, rv[i][r], m, c); };
-        GStages<NC, +1, E, B, LS, 0, 0, 1, kFirstFromLds | kStoreIR>::run(lds, tid, T, tw + NC, load, store);
+        GStages<NC, +1, E, B, LS, 0, 0, 1, kFirstFromLds | kStoreIR, RP>::run(lds, tid, T, tw + NC, load, store);
       }
       __syncthreads();   // every thread has read its last operands out of the tile
       {
         auto load = [&](int i, int r, int, int) -> float2 { return tv[i][r]; };
         auto store = [&](int j, int c, float2 v) { lds[j * LS + c] = v; };
-        GStages<NC, -1, E, B, LS, 0, 0, 1, kLastToLds>::run(lds, tid, T, tw + NC, load, store);
+        GStages<NC, -1, E, B, LS, 0, 0, 1, kLastToLds, RP>::run(lds, tid, T, tw + NC, load, store);
       }
     } else {
-      lds_fft<NC, +1, E, B, LS, 0>(lds, tid, T, tw + NC);
+      lds_fft<NC, +1, E, B, LS, 0, RowPlan<NC>>(lds, tid, T, tw + NC);
 #pragma unroll
       for (int i = 0; i < NBL; ++i) {
         const int b = tid + i * T, c = b % B, j = b / B;
@@ -1072,7 +1093,7 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
         }
       }
       __syncthreads();
-      lds_fft<NC, -1, E, B, LS, 0>(lds, tid, T, tw + NC);
+      lds_fft<NC, -1, E, B, LS, 0, RowPlan<NC>>(lds, tid, T, tw + NC);
     }
     __syncthreads();
     split_fwd_store<NC, E, B, LS, T>(lds, tw, tid, [&](int c, int k, float2 v) {
