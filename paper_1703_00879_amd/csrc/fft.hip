@@ -678,6 +678,36 @@ constexpr int pow2_floor(int x) { return x >= 2 ? 2 * pow2_floor(x / 2) : 1; }
 template <int NC>
 constexpr int kRowE = NC == 1024 ? 8 : RowPlan<NC>::E;
 
+// Row block blk of a row pass: rows r0 = blk B .. r0 + B - 1 of a mesh of nrows rows, kN
+// to a plane, `pitch` elements apart within a plane and `plane` elements apart between
+// planes.  The row count is whole planes (nrows = kN x planes), so when B divides kN a
+// block is complete and lies within one plane: a row's offset is one multiply-add from
+// the block's, with no division and no bounds test per element.
+template <int kN, int B, class O>
+struct RowBlock {
+  O r0, base;
+  int64_t nrows, plane;
+  int pitch;
+  __device__ __forceinline__ RowBlock(int64_t blk, int64_t nrows_, int pitch_, int64_t plane_)
+      : r0((O)blk * B), nrows(nrows_), plane(plane_), pitch(pitch_) {
+    base = (r0 / kN) * (O)plane + (r0 % kN) * (O)pitch;
+  }
+  __device__ __forceinline__ bool valid(int c) const {
+    if constexpr (kN % B == 0)
+      return true;
+    else
+      return r0 + c < (O)nrows;
+  }
+  __device__ __forceinline__ O off(int c) const {
+    if constexpr (kN % B == 0) {
+      return base + (O)(c * pitch);
+    } else {
+      const O r = r0 + c;
+      return (r / kN) * (O)plane + (r % kN) * (O)pitch;
+    }
+  }
+};
+
 // LDS twiddles of a row pass (rows of n = 2 NC reals): tw[k] = exp(-2 pi i k / n) for the
 // split steps, k < NC, then the per-stage table of the NC-point transform at tw + NC.
 template <int NC>
@@ -797,24 +827,22 @@ k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nr
   // (in place, in may alias out: a block's rows are read and written only by its owner).
   const int64_t nblk = (nrows + B - 1) / B;
   float2 v[E];
+  using RB = RowBlock<kN, B, O>;
   auto issue = [&](int64_t blk) {
-    const O r0 = (O)blk * B;
+    const RB rb(blk, nrows, pitch, plane);
 #pragma unroll
     for (int i = 0; i < E; ++i) {
       const int e = tid + i * T;
       const int c = e / NC, m = e % NC;
       v[i] = make_float2(0.f, 0.f);
-      if (r0 + c < (O)nrows) {
-        const O r = r0 + c;
-        v[i] = reinterpret_cast<const float2*>(in + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[m];
-      }
+      if (rb.valid(c)) v[i] = reinterpret_cast<const float2*>(in + 2 * rb.off(c))[m];
     }
   };
   int64_t blk = blockIdx.x;
   if (blk < nblk) issue(blk);
   row_twiddles<NC>(tw, tw_g, tid, T);   // after the row loads issue
   for (; blk < nblk; blk += gridDim.x) {
-    const O r0 = (O)blk * B;
+    const RB rb(blk, nrows, pitch, plane);
     __syncthreads();   // twiddles staged; the previous block has left the tile
 #pragma unroll
     for (int i = 0; i < E; ++i) {
@@ -825,9 +853,7 @@ k_fft_r2c_row(const float* __restrict__ in, float2* __restrict__ out, int64_t nr
     __syncthreads();
     lds_fft<NC, -1, E, B, LS, 0, RowPlan<NC>>(lds, tid, T, tw + NC);
     split_fwd_store<NC, E, B, LS, T>(lds, tw, tid, [&](int c, int k, float2 v) {
-      if (r0 + c >= (O)nrows) return;
-      const O r = r0 + c;
-      out[(r / kN) * (O)plane + (r % kN) * (O)pitch + k] = v;
+      if (rb.valid(c)) out[rb.off(c) + k] = v;
     });
   }
 }
@@ -850,20 +876,17 @@ k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nr
   // the next block are loaded into registers while this block is transformed and stored
   // (in place, in may alias out: a block's rows are read and written only by its owner).
   const int64_t nblk = (nrows + B - 1) / B;
+  using RB = RowBlock<kN, B, O>;
   auto rows_at = [&](int64_t blk) {
-    const O r0 = (O)blk * B;
-    return [=](int c) -> const float2* {
-      if (r0 + c >= (O)nrows) return nullptr;
-      const O r = r0 + c;
-      return in + (r / kN) * (O)plane + (r % kN) * (O)pitch;
-    };
+    const RB rb(blk, nrows, pitch, plane);
+    return [=](int c) -> const float2* { return rb.valid(c) ? in + rb.off(c) : nullptr; };
   };
   InvSplit<NC, E / 2> sp;   // all row loads are issued before any is used
   int64_t blk = blockIdx.x;
   if (blk < nblk) sp.load(tid, T, rows_at(blk));
   row_twiddles<NC>(tw, tw_g, tid, T);   // after the row loads issue
   for (; blk < nblk; blk += gridDim.x) {
-    const O r0 = (O)blk * B;
+    const RB rb(blk, nrows, pitch, plane);
     __syncthreads();   // twiddles staged; the previous block has left the tile
     sp.store(tid, T, tw, lds, LS);
     if (blk + gridDim.x < nblk) sp.load(tid, T, rows_at(blk + gridDim.x));
@@ -871,9 +894,7 @@ k_fft_c2r_row(const float2* __restrict__ in, float* __restrict__ out, int64_t nr
     lds_fft<NC, +1, E, B, LS, 0, RowPlan<NC>>(lds, tid, T, tw + NC);
     for (int e = tid; e < NC * B; e += T) {
       const int c = e / NC, m = e % NC;
-      if (r0 + c >= (O)nrows) continue;
-      const O r = r0 + c;
-      reinterpret_cast<float2*>(out + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[m] = lds[m * LS + c];
+      if (rb.valid(c)) reinterpret_cast<float2*>(out + 2 * rb.off(c))[m] = lds[m * LS + c];
     }
   }
 }
@@ -918,13 +939,10 @@ k_fft_c2r_row3(const float2* __restrict__ in0, const float2* __restrict__ in1,
   // Persistent: the work-group takes row blocks blockIdx.x, + gridDim.x, ...; the rows of
   // the next block are loaded into registers while this block is transformed and stored.
   const int64_t nblk = (nrows + B - 1) / B;
+  using RB = RowBlock<kN, B, O>;
   auto rows_at = [&](int64_t blk) {
-    const O r0 = (O)blk * B;
-    return [=](int c) -> const float2* {
-      if (r0 + c >= (O)nrows) return nullptr;
-      const O r = r0 + c;
-      return in + (r / kN) * (O)plane + (r % kN) * (O)pitch;
-    };
+    const RB rb(blk, nrows, pitch, plane);
+    return [=](int c) -> const float2* { return rb.valid(c) ? in + rb.off(c) : nullptr; };
   };
   InvSplit<NC, E / 2> sp;   // each row value is read from HBM once
   int64_t blk = blockIdx.x;
@@ -979,8 +997,12 @@ struct ScreenCfg {
   static constexpr int LS = B == 1 ? 1 : B + 1;
 };
 
+// With 12 elements per thread (the radix-3 lengths and 12) the compiler takes about 280
+// registers, one wave per SIMD; held to two waves it spills 30-90 bytes per lane and runs
+// 20-25 % faster.
 template <int NC, int MODEL>
 __global__ void __launch_bounds__(ScreenCfg<NC>::T)
+__attribute__((amdgpu_waves_per_eu(ScreenCfg<NC>::E == 12 ? 2 : 1)))
 k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float* __restrict__ s_out,
                  int64_t nrows, int /*n*/, int pitch, int64_t plane, const float2* __restrict__ tw_g,
                  ScreenArgs sa) {
@@ -1013,29 +1035,24 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
   const int64_t nblk = (nrows + B - 1) / B;
   InvSplit<NC, E / 2> sp;
   float2 rv[NBL][RL], rn[NBL][RL];
+  using RB = RowBlock<kN, B, O>;
   auto issue = [&](int64_t blk) {
-    const O r0 = (O)blk * B;
-    sp.load(tid, T, [=](int c) -> const float2* {
-      if (r0 + c >= (O)nrows) return nullptr;
-      const O r = r0 + c;
-      return data + (r / kN) * (O)plane + (r % kN) * (O)pitch;
-    });
+    const RB rb(blk, nrows, pitch, plane);
+    sp.load(tid, T, [=](int c) -> const float2* { return rb.valid(c) ? data + rb.off(c) : nullptr; });
 #pragma unroll
     for (int i = 0; i < NBL; ++i) {
       const int b = tid + i * T, c = b % B, j = b / B;
-      const O r = r0 + c;
-      const float2* rr =
-          reinterpret_cast<const float2*>(rho + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch));
+      const float2* rr = reinterpret_cast<const float2*>(rho + 2 * rb.off(c));
 #pragma unroll
       for (int q = 0; q < RL; ++q)
-        rn[i][q] = r < (O)nrows ? rr[j + q * (NC / RL)] : make_float2(1.f, 1.f);
+        rn[i][q] = rb.valid(c) ? rr[j + q * (NC / RL)] : make_float2(1.f, 1.f);
     }
   };
   int64_t blk = blockIdx.x;
   if (blk < nblk) issue(blk);
   row_twiddles<NC>(tw, tw_g, tid, T);   // after the row loads issue
   for (; blk < nblk; blk += gridDim.x) {
-    const O r0 = (O)blk * B;
+    const RB rb(blk, nrows, pitch, plane);
     __syncthreads();   // twiddles staged; the previous block has left the tile
     sp.store(tid, T, tw, lds, LS);
 #pragma unroll
@@ -1060,11 +1077,8 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
         e1 = 2.f * fast_rcp(1.f + fast_sqrt(1.f + x1));
       }
       const float2 dl = make_float2(rho2.x - 1.f, rho2.y - 1.f);
-      if (s_out && r0 + c < (O)nrows) {
-        const O r = r0 + c;
-        reinterpret_cast<float2*>(s_out + 2 * ((r / kN) * (O)plane + (r % kN) * (O)pitch))[m] =
-            make_float2(dl.x * e0, dl.y * e1);
-      }
+      if (s_out && rb.valid(c))
+        reinterpret_cast<float2*>(s_out + 2 * rb.off(c))[m] = make_float2(dl.x * e0, dl.y * e1);
       return make_float2(dl.x * (cn + c5 * e0), dl.y * (cn + c5 * e1));
     };
     if constexpr (kHandOff) {
@@ -1097,9 +1111,7 @@ k_fft_screen_row(float2* __restrict__ data, const float* __restrict__ rho, float
     }
     __syncthreads();
     split_fwd_store<NC, E, B, LS, T>(lds, tw, tid, [&](int c, int k, float2 v) {
-      if (r0 + c >= (O)nrows) return;
-      const O r = r0 + c;
-      data[(r / kN) * (O)plane + (r % kN) * (O)pitch + k] = v;
+      if (rb.valid(c)) data[rb.off(c) + k] = v;
     });
   }
 }
