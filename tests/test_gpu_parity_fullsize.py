@@ -12,7 +12,7 @@ and every particle exactly.
 - One COLA step: every particle's displacement and velocity is compared.
 
 The same planar check runs on radix-3 meshes of 192^3, 384^3 and 768^3 cells (the sizes
-of the serving mix).  The white noise and the scale-dependent growth table are checked on
+of the serving mix) and of 1536^3 cells (the largest radix-3 plan).  The white noise and the scale-dependent growth table are checked on
 samples the oracle computes one by one.
 
 Tolerances are those of test_gpu_parity:
@@ -125,8 +125,9 @@ def test_fullsize_planar_pm_force(ax):
 
 # Radix-3 meshes at the sizes of the serving mix (n_p = 384, 192, 96 on 768^3, 384^3,
 # 192^3 meshes, L = 2 n_p Mpc/h): f(R) with its potential screening and two sources,
-# screened nDGP with one combined source, LCDM.
-RADIX3 = [(C.FR_HS1, 384, 0), (C.NDGP, 192, 1), (C.LCDM, 96, 2)]
+# screened nDGP with one combined source, LCDM; and f(R) on the largest radix-3 mesh,
+# 1536^3 (about 170 GB of device memory with the test's mesh outputs).
+RADIX3 = [(C.FR_HS1, 384, 0), (C.NDGP, 192, 1), (C.LCDM, 96, 2), (C.FR_HS1, 768, 2)]
 
 
 @pytest.mark.parametrize("model,n_p,ax", RADIX3)
