@@ -38,7 +38,7 @@ typedef int32_t cola_status;
 #define COLA_E_SIZE (-2)         /* buffer too small / size overflow */
 #define COLA_E_STATE (-3)        /* call out of order (e.g. step before make_ic) */
 #define COLA_E_HIP (-4)          /* a HIP runtime call failed */
-#define COLA_E_UNSUPPORTED (-5)  /* valid request this build does not implement */
+#define COLA_E_UNSUPPORTED (-5)  /* valid request the library does not implement */
 
 /* Gravity models (Sec. 5, App. C): LCDM, Hu-Sawicki f(R) with n = 1, normal-branch DGP,
  * the symmetron, and the general {m(a), beta(a)} model given by tables, both of the
