@@ -569,6 +569,100 @@ def roofline_of(p, prof, traffic=None):
             "algorithmic_bytes_per_launch": by}
 
 
+# Hardware-counter passes of counters_command (each within one pass's counter limits).
+COUNTER_PASSES = [
+    "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR SQ_WAIT_INST_LDS "
+    "SQ_LDS_BANK_CONFLICT SQ_BUSY_CYCLES",
+    "TCP_UTCL1_TRANSLATION_MISS_sum TCP_UTCL1_TRANSLATION_HIT_sum TCP_UTCL1_REQUEST_sum "
+    "TCP_UTCL1_STALL_MULTI_MISS_sum",
+    "SQ_WAVE_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_LDS SQ_INST_LEVEL_VMEM SQ_ACTIVE_INST_ANY "
+    "SQ_WAIT_ANY SQ_INSTS_SALU SQ_ACTIVE_INST_VMEM",
+    "TCC_HIT_sum TCC_MISS_sum TCC_EA0_RDREQ_sum TCC_EA0_WRREQ_sum",
+]
+COUNTERS_FILE = "counters_fr5_1024_2048.md"
+
+
+def counters_command(steps):
+    """The rocprofv3 counter passes whose per-kernel ratios summarize_counters writes (D =
+    output directory, REPO = repository root), one run of the headline workload each."""
+    b = f"python3 $REPO/bench.py --steps {steps} --warmup 0 --headline-only --no-profile"
+    cmds = ["cd /tmp && export TMPDIR=/tmp"]
+    for i, c in enumerate(COUNTER_PASSES, 1):
+        cmds.append(f"rocprofv3 --pmc {c} --output-format csv -d $D/p{i} -o p{i} -- {b}")
+    cmds.append(f"python3 $REPO/bench.py --summarize-counters $D --steps {steps}")
+    return "; ".join(cmds)
+
+
+def summarize_counters(d, out_dir, steps):
+    """Per-kernel ratios of the counter passes of counters_command(steps) under directory d,
+    over the dispatches of timed steps 2..K (as in summarize_rocprof), written to out_dir
+    as a markdown table: what the kernels spend their wave-cycles on, the LDS bank
+    conflicts per LDS instruction, the address-translation (UTCL1) miss rate and the L2 hit
+    rate."""
+    import csv
+    from collections import defaultdict
+    from paper_1703_00879_amd import cola as C
+    p = workload_params(C)
+    n, np_ = p.nmesh1d, p.np1d
+    acc = defaultdict(lambda: defaultdict(float))
+    launches = defaultdict(set)
+    nsteps = None
+    for i in range(1, len(COUNTER_PASSES) + 1):
+        with open(os.path.join(d, f"p{i}", f"p{i}_counter_collection.csv")) as fh:
+            recs = list(csv.DictReader(fh))
+        ids = sorted({int(r["Dispatch_Id"]) for r in recs if "k_gather" in r["Kernel_Name"]})[-steps:]
+        lo, hi, nsteps = ids[0], ids[-1], len(ids) - 1
+        for r in recs:
+            if lo < int(r["Dispatch_Id"]) <= hi:
+                name = _profile_name(r["Kernel_Name"], n, np_)
+                acc[name][r["Counter_Name"]] += float(r["Counter_Value"])
+                if i == 1:
+                    launches[name].add(int(r["Dispatch_Id"]))
+
+    def ratio(a, x, y, scale=1.0):
+        return f"{scale * a[x] / a[y]:.2f}" if a.get(y) else "-"
+
+    lines = [f"# Hardware counters of the PM step kernels: {WORKLOAD} (rocprofv3)", "",
+             f"Source hash {source_hash()}; timed steps 2..{steps} of a {steps}-step run "
+             f"({nsteps} steps), summed over each kernel's dispatches.", "",
+             "Command (from the repository root on the GPU host, D = output directory, "
+             "REPO = repository root):", "",
+             "```", counters_command(steps).replace("; ", "\n"), "```", "",
+             "Columns: wave instructions (VALU, LDS, and VMEM reads + writes: SQ_INSTS_VALU, "
+             "SQ_INSTS_LDS, SQ_INSTS_VMEM_RD + _WR) per KiB of the kernel's algorithmic bytes; "
+             "% of wave-cycles with a VALU or LDS instruction in flight and waiting on anything "
+             "(SQ_ACTIVE_INST_VALU, SQ_ACTIVE_INST_LDS, SQ_WAIT_ANY over SQ_WAVE_CYCLES); LDS "
+             "bank-conflict cycles per LDS instruction; UTCL1 address-translation misses per "
+             "translation (MISS / (MISS + HIT)); L2 hits per L2 request (TCC_HIT / (TCC_HIT + "
+             "TCC_MISS)).", "",
+             "| kernel | launches/step | VALU/KiB | LDS/KiB | VMEM/KiB | VALU % | LDS % | wait % "
+             "| bank conflicts/LDS | UTCL1 miss % | L2 hit % |",
+             "|---|---|---|---|---|---|---|---|---|---|---|"]
+    for name, a in sorted(acc.items(), key=lambda kv: -kv[1].get("SQ_WAVE_CYCLES", 0)):
+        if not a.get("SQ_WAVES"):
+            continue
+        a = dict(a)
+        nl = len(launches[name])
+        ab = algorithmic_bytes(name, p)
+        a["KiB"] = ab * nl / 1024 if ab else 0
+        a["VMEM"] = a.get("SQ_INSTS_VMEM_RD", 0) + a.get("SQ_INSTS_VMEM_WR", 0)
+        a["UTCL1"] = a.get("TCP_UTCL1_TRANSLATION_MISS_sum", 0) + a.get("TCP_UTCL1_TRANSLATION_HIT_sum", 0)
+        a["TCC"] = a.get("TCC_HIT_sum", 0) + a.get("TCC_MISS_sum", 0)
+        lines.append(
+            f"| {name} | {nl / nsteps:g} | {ratio(a, 'SQ_INSTS_VALU', 'KiB')} "
+            f"| {ratio(a, 'SQ_INSTS_LDS', 'KiB')} | {ratio(a, 'VMEM', 'KiB')} "
+            f"| {ratio(a, 'SQ_ACTIVE_INST_VALU', 'SQ_WAVE_CYCLES', 100)} "
+            f"| {ratio(a, 'SQ_ACTIVE_INST_LDS', 'SQ_WAVE_CYCLES', 100)} "
+            f"| {ratio(a, 'SQ_WAIT_ANY', 'SQ_WAVE_CYCLES', 100)} "
+            f"| {ratio(a, 'SQ_LDS_BANK_CONFLICT', 'SQ_INSTS_LDS')} "
+            f"| {ratio(a, 'TCP_UTCL1_TRANSLATION_MISS_sum', 'UTCL1', 100)} "
+            f"| {ratio(a, 'TCC_HIT_sum', 'TCC', 100)} |")
+    os.makedirs(out_dir, exist_ok=True)
+    with open(os.path.join(out_dir, COUNTERS_FILE), "w") as fh:
+        fh.write("\n".join(lines) + "\n")
+    return lines
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -589,6 +683,8 @@ def main():
                     help="do not record per-kernel HIP events in the timed region")
     ap.add_argument("--summarize-rocprof", metavar="DIR",
                     help="condense rocprofv3 output under DIR into profiles/ and exit")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="condense the hardware-counter passes under DIR into profiles/ and exit")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy (three times), the "
                          "reference for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE readings")
@@ -597,6 +693,10 @@ def main():
         t = summarize_rocprof(args.summarize_rocprof, os.path.join(ROOT, "profiles"), args.steps,
                               args.warmup)
         print(json.dumps({k: v["bytes_per_launch"] for k, v in t["kernels"].items()}))
+        return
+    if args.summarize_counters:
+        print("\n".join(summarize_counters(args.summarize_counters, os.path.join(ROOT, "profiles"),
+                                           args.steps)))
         return
     if args.calibrate_copy:
         import torch

@@ -125,3 +125,35 @@ def test_summarize_rocprof_on_synthetic_runs(bench, tmp_path):
     assert saved["source_hash"] == bench.source_hash()
     md = open(out / bench.PROFILE_FILE).read()
     assert "| fft_c2r_z3 | 1 | 5.000 |" in md and "rocprofv3 --kernel-trace" in md
+
+
+def test_summarize_counters_on_synthetic_runs(bench, tmp_path):
+    """Three timed steps of the counter passes: the summary covers the two steps after the
+    first gather and gives per-kernel ratios of the summed counters."""
+    d = tmp_path / "cnt"
+    gather = "void cola::k_gather<0>(cola::GatherDev, long)"
+    values = {"SQ_WAVES": 10.0, "SQ_INSTS_VALU": 300.0, "SQ_INSTS_LDS": 0.0,
+              "SQ_INSTS_VMEM_RD": 20.0, "SQ_INSTS_VMEM_WR": 2.0, "SQ_WAIT_INST_LDS": 0.0,
+              "SQ_LDS_BANK_CONFLICT": 0.0, "SQ_BUSY_CYCLES": 100.0,
+              "TCP_UTCL1_TRANSLATION_MISS_sum": 1.0, "TCP_UTCL1_TRANSLATION_HIT_sum": 3.0,
+              "TCP_UTCL1_REQUEST_sum": 4.0, "TCP_UTCL1_STALL_MULTI_MISS_sum": 0.0,
+              "SQ_WAVE_CYCLES": 1000.0, "SQ_ACTIVE_INST_VALU": 50.0, "SQ_ACTIVE_INST_LDS": 0.0,
+              "SQ_INST_LEVEL_VMEM": 0.0, "SQ_ACTIVE_INST_ANY": 60.0, "SQ_WAIT_ANY": 250.0,
+              "SQ_INSTS_SALU": 5.0, "SQ_ACTIVE_INST_VMEM": 0.0,
+              "TCC_HIT_sum": 9.0, "TCC_MISS_sum": 1.0, "TCC_EA0_RDREQ_sum": 1.0,
+              "TCC_EA0_WRREQ_sum": 1.0}
+    for i, names in enumerate(bench.COUNTER_PASSES, 1):
+        rows = [[step + 1, gather, c, values[c]] for step in range(3) for c in names.split()]
+        _write(str(d / f"p{i}" / f"p{i}_counter_collection.csv"),
+               ["Dispatch_Id", "Kernel_Name", "Counter_Name", "Counter_Value"], rows)
+    out = tmp_path / "profiles"
+    lines = bench.summarize_counters(str(d), str(out), steps=3)
+    row = [ln for ln in lines if ln.startswith("| gather_kick_drift |")]
+    assert len(row) == 1
+    cells = [c.strip() for c in row[0].strip("|").split("|")]
+    # launches/step, then VALU % 5, LDS % 0, wait % 25, UTCL1 miss 25 %, L2 hit 90 %
+    assert cells[1] == "1"
+    assert cells[5:8] == ["5.00", "0.00", "25.00"]
+    assert cells[9:11] == ["25.00", "90.00"]
+    md = open(out / bench.COUNTERS_FILE).read()
+    assert bench.source_hash() in md and "rocprofv3 --pmc" in md
